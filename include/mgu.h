@@ -1,0 +1,291 @@
+/*
+ * mgu.h - C ABI of libmgu: the per-frame dynamic mesh-Gaussian update on one
+ * AMD MI355X (gfx950).
+ *
+ * Paper: "Real-Time Physics Simulation with Dynamic Mesh-Gaussian
+ * Reconstructions" (arXiv 2606.00444).  A fixed-topology physics mesh drives
+ * a Gaussian render representation (Sec. 3.2); acceleration structures are
+ * built once from the template faces and reused (Sec. 3.4, Initialization);
+ * each frame only rewrites the vertex buffer, normals being recomputed on
+ * demand inside collision queries (Sec. 3.4, per-frame steps 1-3); varying
+ * topology instead destroys and rebuilds the collision structures every frame
+ * (Sec. 4.1).
+ *
+ * Conventions for every entry point:
+ *  - All array pointers are DEVICE pointers unless marked "host".  The caller
+ *    allocates everything (inputs, outputs, BVH buffers, workspaces); the
+ *    library never allocates, frees or synchronises, so every call may be
+ *    captured into a HIP graph.
+ *  - Layout is structure-of-arrays: "[k][n]" means k planes of n contiguous
+ *    values (vertices [3][n_verts] float32 x/y/z planes; faces [3][n_faces]
+ *    int32 vertex ids).  Counts are int32 and must be >= 0 and < 2^30.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Work is enqueued asynchronously on it; outputs are valid once the stream
+ *    reaches that point.
+ *  - Arguments are checked on the host before any HIP call; a bad argument
+ *    returns a status and enqueues nothing.  Index ranges inside arrays are
+ *    NOT checked by the compute calls (mg_validate_indices does that on
+ *    request); out-of-range ids are undefined behaviour.  A failed kernel
+ *    launch returns MG_ERR_HIP.  No C++ exception crosses this boundary.
+ *  - n == 0 is a valid no-op for every call.
+ */
+#ifndef MGU_H
+#define MGU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mg_status;
+
+#define MG_OK                       0
+#define MG_ERR_INVALID_ARGUMENT     1  /* null pointer, negative or too large count, bad flag */
+#define MG_ERR_WORKSPACE_TOO_SMALL  2  /* a caller buffer is smaller than the size query says */
+#define MG_ERR_INDEX_OUT_OF_RANGE   3  /* reported by mg_validate_indices */
+#define MG_ERR_NONFINITE_INPUT      4  /* reported by mg_validate_finite */
+#define MG_ERR_TOPOLOGY_MISMATCH    5  /* BVH used with a different primitive count or kind */
+#define MG_ERR_HIP                  6  /* a HIP runtime call failed (launch, copy) */
+#define MG_ERR_UNSUPPORTED_DEVICE   7  /* current device is not gfx950 */
+
+#define MG_PRIM_TRIANGLES 0  /* primitives are faces [3][n] into a vertex array */
+#define MG_PRIM_POINTS    1  /* primitives are the points [3][n] themselves */
+
+/* Human-readable name of a status code (static storage). */
+const char *mg_status_string(mg_status s);
+
+/* Library version as major * 10000 + minor * 100 + patch. */
+int32_t mg_version(void);
+
+/* Returns MG_OK if the current HIP device is a gfx950 (MI355X class) GPU. */
+mg_status mg_check_device(void);
+
+/* ------------------------------------------------------------------------
+ * Frame selection and vertex-buffer update (Sec. 3.3 MaGS paragraph:
+ * k = floor(t * f_recon); Sec. 3.4 per-frame steps 1-2).
+ * ---------------------------------------------------------------------- */
+
+/* Host-only integer arithmetic: t = step / f_sim seconds, f_recon =
+ * f_recon_num / f_recon_den frames per second, *k_out (host) =
+ * min(floor(step * f_recon_num / (f_sim * f_recon_den)), n_frames - 1).
+ * Invalid: step < 0, f_recon_num < 0, f_recon_den <= 0, f_sim <= 0,
+ * n_frames <= 0, k_out == NULL. */
+mg_status mg_frame_index(int64_t step, int64_t f_recon_num, int64_t f_recon_den, int64_t f_sim,
+                         int32_t n_frames, int32_t *k_out);
+
+/* live[3][n_verts] <- frames[k][3][n_verts] (a bitwise O(N_v) copy on the
+ * device).  frames is a [n_frames][3][n_verts] store; 0 <= k < n_frames.
+ * live must not overlap frame k. */
+mg_status mg_vertex_buffer_update(const float *frames, int32_t n_frames, int32_t n_verts, int32_t k,
+                                  float *live, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Face-bound Gaussian re-pose (render side of the dual representation,
+ * Sec. 3.2).  The paper states no binding formula; the library computes, per
+ * Gaussian g bound to face f = gface[g] with vertices (v0, v1, v2) in stored
+ * order:
+ *   triangle frame  e1 = v1 - v0, e2 = v2 - v0, n = e1 x e2, t = e1/|e1|,
+ *                   nh = n/|n|, b = nh x t, R_f = [t b nh] (columns);
+ *                   |e1| == 0 or |n| == 0 gives R_f = I, nh = 0;
+ *   mean            mu = (1 - b1 - b2) v0 + b1 v1 + b2 v2 + offset * nh;
+ *   rotation        R_g = R_f R(q_l), q_l = (w,x,y,z) normalised; quat =
+ *                   Shepperd's extraction of R_g, sign fixed so w > 0 (w == 0:
+ *                   first non-zero of x, y, z positive);
+ *   covariance      Sigma = R_g diag(exp(2 log_scale)) R_g^T packed as
+ *                   (xx, xy, xz, yy, yz, zz).
+ * ---------------------------------------------------------------------- */
+
+/* Inputs: verts [3][n_verts], faces [3][n_faces], gface [n_gauss] (face of
+ * each Gaussian, any order; sorted by face is fastest), bary [2][n_gauss]
+ * (b1, b2), q_local [4][n_gauss], log_scale [3][n_gauss], offset [n_gauss]
+ * or NULL (zero).  Outputs: mean [3][n_gauss] (required), quat [4][n_gauss],
+ * cov [6][n_gauss], rot [9][n_gauss] (row-major R_g), each NULL to skip.
+ * flags must be 0. */
+mg_status mg_mesh_gaussian_update(const float *verts, int32_t n_verts, const int32_t *faces,
+                                  int32_t n_faces, const int32_t *gface, const float *bary,
+                                  const float *q_local, const float *log_scale, const float *offset,
+                                  int32_t n_gauss, uint32_t flags, float *mean, float *quat,
+                                  float *cov, float *rot, void *stream);
+
+/* Backward of mg_mesh_gaussian_update w.r.t. the vertices: g_verts [3][n_verts]
+ * is ACCUMULATED into (+=) from g_mean [3][G] (required), g_rot [9][G]
+ * (row-major dL/dR_g) and g_cov [6][G] (dL/d packed Sigma), either NULL for
+ * zero.  The quaternion output is not differentiated.  Uses float atomics:
+ * results are reproducible to rounding, not bitwise. */
+mg_status mg_mesh_gaussian_update_backward(const float *verts, int32_t n_verts, const int32_t *faces,
+                                           int32_t n_faces, const int32_t *gface, const float *bary,
+                                           const float *q_local, const float *log_scale,
+                                           const float *offset, int32_t n_gauss, const float *g_mean,
+                                           const float *g_rot, const float *g_cov, float *g_verts,
+                                           void *stream);
+
+/* ------------------------------------------------------------------------
+ * Linear BVH (Karras 2012) over triangles or points.  Built once from the
+ * template faces and then only refit per frame (Sec. 3.4); rebuilt every frame
+ * on the varying-topology comparison path (Sec. 4.1).
+ *
+ * Construction, all on the device: per-axis bounds of s = (v0 + v1) + v2
+ * (points: s = p); 30-bit Morton codes defined in IEEE binary32 (scale =
+ * 1024/(hi - lo) or 0, q = min(1023, trunc((s - lo) * scale)), x bits most
+ * significant); stable LSD radix sort of (code, primitive id); Karras binary
+ * radix tree with the leaf index as tie-break; leaf permutation; refit.
+ *
+ * A BVH lives in ONE caller-allocated device buffer of
+ * mg_lbvh_layout_query()->total_bytes, 256-byte aligned; section offsets (in
+ * bytes from its start) are returned so callers may read it:
+ *   header      mg_lbvh_header (below)
+ *   codes       uint32 [n]       sorted Morton codes
+ *   prim        int32  [n]       leaf -> original primitive id
+ *   leaf_faces  int32  [3][n]    vertex ids of each leaf's face (triangles only)
+ *   leaf_parent int32  [n]       (parent << 1) | slot, -1 when n == 1
+ *   node_parent int32  [n-1]     (parent << 1) | slot, -1 for the root (node 0)
+ *   nodes       float4 [n-1][4]  per internal node, slot 0 = left child,
+ *                                slot 1 = right child, each two float4:
+ *                                (lo.x, lo.y, lo.z, ref) (hi.x, hi.y, hi.z, aux)
+ *                                ref (int bits): >= 0 internal node, < 0 leaf ~ref;
+ *                                aux (int bits): original primitive id of a leaf
+ *                                child, 0 for an internal child
+ *   counters    uint32 [n-1]     refit arrival counters (zero between calls)
+ * ---------------------------------------------------------------------- */
+
+typedef struct mg_lbvh_header {
+    int32_t n_prims;
+    int32_t prim_kind;
+    int32_t status;        /* device-side error word (0 = fine) */
+    int32_t reserved0;
+    float root_lo[3];      /* root box (the only box not stored in a node record) */
+    float pad0;
+    float root_hi[3];
+    float pad1;
+    float quant_lo[3];     /* Morton quantisation of the last build: lo, scale */
+    float quant_scale[3];
+    uint32_t bounds_enc[6];/* build scratch: order-preserving encodings of lo/hi */
+    uint32_t tile_counter[4];
+    int32_t reserved[12];
+} mg_lbvh_header;
+
+typedef struct mg_lbvh_layout {
+    int64_t total_bytes;
+    int64_t off_header;
+    int64_t off_codes;
+    int64_t off_prim;
+    int64_t off_leaf_faces;
+    int64_t off_leaf_parent;
+    int64_t off_node_parent;
+    int64_t off_nodes;
+    int64_t off_counters;
+} mg_lbvh_layout;
+
+/* Host-only: section offsets and total size of a BVH over n_prims primitives
+ * of the given kind.  out is a host pointer. */
+mg_status mg_lbvh_layout_query(int32_t n_prims, int32_t prim_kind, mg_lbvh_layout *out);
+
+/* Host-only: bytes of device workspace mg_lbvh_build needs (ws_bytes host). */
+mg_status mg_lbvh_workspace_size(int32_t n_prims, int32_t prim_kind, size_t *ws_bytes);
+
+/* Build a BVH.  verts [3][n_verts] (points: the primitives themselves, then
+ * n_prims == n_verts and faces == NULL); faces [3][n_prims] for triangles.
+ * bvh: device buffer of at least layout.total_bytes; ws: device workspace of
+ * at least mg_lbvh_workspace_size bytes (contents need not be initialised,
+ * may be reused after the call completes on the stream). */
+mg_status mg_lbvh_build(const float *verts, int32_t n_verts, const int32_t *faces, int32_t n_prims,
+                        int32_t prim_kind, void *bvh, size_t bvh_bytes, void *ws, size_t ws_bytes,
+                        void *stream);
+
+/* Refit in place: recompute every box of a built BVH for new vertex positions
+ * (same n_prims and prim_kind as the build; topology unchanged). */
+mg_status mg_lbvh_refit(const float *verts, int32_t n_verts, void *bvh, size_t bvh_bytes,
+                        int32_t n_prims, int32_t prim_kind, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Closest point on a triangle mesh (NearestSurface with barycentric
+ * interpolation, Sec. 3.3 Eq. 1-2, read as the single nearest face) with the
+ * face normal computed on demand (Sec. 3.4 step 3).  Exact ties of the float32
+ * squared distance go to the lowest original face id.  Per query q:
+ *   face[q]   original face id, -1 if no face has d^2 <= max_dist2
+ *   point     [3][nq] closest point (the query itself when face == -1)
+ *   bary      [2][nq] (w1, w2): point = (1-w1-w2) v0 + w1 v1 + w2 v2 (0 when none)
+ *   dist2     [nq] squared distance (+inf when none)
+ *   normal    [3][nq] unit normal of the face, zero if degenerate or none
+ * point, bary, dist2, normal may each be NULL to skip.  max_dist2 >= 0
+ * (+inf allowed).  bvh must be a MG_PRIM_TRIANGLES BVH built/refit on verts.
+ * ---------------------------------------------------------------------- */
+mg_status mg_closest_point_query(const void *bvh, size_t bvh_bytes, int32_t n_prims,
+                                 const float *verts, int32_t n_verts, const float *queries,
+                                 int32_t n_queries, float max_dist2, int32_t *face, float *point,
+                                 float *bary, float *dist2, float *normal, void *stream);
+
+/* Same contract as mg_closest_point_query but tests every face for every query
+ * (no BVH; for self-checks on small meshes).  faces [3][n_faces]. */
+mg_status mg_closest_point_bruteforce(const float *verts, int32_t n_verts, const int32_t *faces,
+                                      int32_t n_faces, const float *queries, int32_t n_queries,
+                                      float max_dist2, int32_t *face, float *point, float *bary,
+                                      float *dist2, float *normal, void *stream);
+
+/* Nearest point of a MG_PRIM_POINTS BVH built over points [3][n_prims]:
+ * index[q] (lowest index on exact ties, -1 if none within max_dist2) and
+ * dist2[q] (+inf if none); dist2 may be NULL. */
+mg_status mg_nearest_point_query(const void *bvh, size_t bvh_bytes, int32_t n_prims,
+                                 const float *points, const float *queries, int32_t n_queries,
+                                 float max_dist2, int32_t *index, float *dist2, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Losses for differentiable template projection.  Chamfer distance is used
+ * by the paper as a metric (Sec. 4.2) without a formula; the library's is
+ * CD(A,B) = mean_a min_b |a-b|^2 + mean_b min_a |a-b|^2.
+ * ---------------------------------------------------------------------- */
+
+/* Workspace bytes (host out) for mg_mean / mg_chamfer over up to n values. */
+mg_status mg_reduce_workspace_size(int64_t n, size_t *ws_bytes);
+
+/* out[0] (device, float64) = mean of x[n] (0 when n == 0), deterministic:
+ * fixed-order per-block float64 partial sums, then one block sums them. */
+mg_status mg_mean(const float *x, int64_t n, double *out, void *ws, size_t ws_bytes, void *stream);
+
+/* Both nearest-neighbour directions and the two means:
+ * nn_ab[i] / d_ab[i]: nearest b of a_i and its squared distance (via bvh_b,
+ * a MG_PRIM_POINTS BVH over b); nn_ba / d_ba likewise via bvh_a over a;
+ * out[0] = mean d_ab, out[1] = mean d_ba (device float64). */
+mg_status mg_chamfer(const float *a, int32_t na, const void *bvh_a, size_t bvh_a_bytes,
+                     const float *b, int32_t nb, const void *bvh_b, size_t bvh_b_bytes,
+                     int32_t *nn_ab, float *d_ab, int32_t *nn_ba, float *d_ba, double *out,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/* g_verts [3][n_verts] += scale * sum_q -2 w_k (y_q - c_q) on the three
+ * vertices of each query's face (queries with face == -1 contribute nothing).
+ * face/point/bary as returned by mg_closest_point_query on the same mesh. */
+mg_status mg_point_mesh_backward(const float *verts, int32_t n_verts, const int32_t *faces,
+                                 int32_t n_faces, const float *queries, int32_t n_queries,
+                                 const int32_t *face, const float *point, const float *bary,
+                                 float scale, float *g_verts, void *stream);
+
+/* g_a [3][na] += 2 scale_ab (a_i - b_nn_ab(i)) + 2 scale_ba sum_{j: nn_ba(j)=i} (a_i - b_j). */
+mg_status mg_chamfer_backward(const float *a, int32_t na, const float *b, int32_t nb,
+                              const int32_t *nn_ab, const int32_t *nn_ba, float scale_ab,
+                              float scale_ba, float *g_a, void *stream);
+
+/* Adam (Kingma & Ba 2015) in torch.optim.Adam's order, in place on param/m/v
+ * [n] float32; step counts from 1. */
+mg_status mg_adam_step(float *param, const float *grad, float *m, float *v, int64_t n, int32_t step,
+                       float lr, float beta1, float beta2, float eps, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Validation helpers (asynchronous; the result lands in a device int32).
+ * ---------------------------------------------------------------------- */
+
+/* *status_out (device int32) is set to MG_ERR_INDEX_OUT_OF_RANGE if any of
+ * idx[n] lies outside [0, bound), else left unchanged (caller zeroes it). */
+mg_status mg_validate_indices(const int32_t *idx, int64_t n, int32_t bound, int32_t *status_out,
+                              void *stream);
+
+/* *status_out (device int32) is set to MG_ERR_NONFINITE_INPUT if any of x[n]
+ * is NaN or infinite, else left unchanged. */
+mg_status mg_validate_finite(const float *x, int64_t n, int32_t *status_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MGU_H */

@@ -206,6 +206,21 @@ def _closest_point_mesh_c(verts, faces, queries, max_dist2):
     return {"face": face, "point": point, "bary": bary, "dist2": d2, "normal": normal}
 
 
+def closest_on_faces(verts, faces, queries, face_ids):
+    """Closest-point records of each query on one given face each (float64).
+
+    Used to evaluate the oracle at another implementation's argmins once those
+    are shown to be ties of the oracle's own minimum.
+    """
+    V = np.asarray(verts, dtype=np.float64).T
+    fid = np.asarray(face_ids, dtype=np.int64)
+    F = np.asarray(faces).astype(np.int64).T[fid]
+    p = np.asarray(queries, dtype=np.float64).T
+    pt, w = closest_on_triangle(p, V[F[:, 0]], V[F[:, 1]], V[F[:, 2]])
+    return {"face": fid, "point": pt.T.copy(), "bary": w[:, 1:].T.copy(), "dist2": _dot(p - pt, p - pt),
+            "normal": _tri_normals(V[F[:, 0]], V[F[:, 1]], V[F[:, 2]]).T.copy()}
+
+
 def distances_to_faces(verts, faces, queries, face_ids):
     """Squared distance from each query to one given face each (for tie checks)."""
     V = np.asarray(verts, dtype=np.float64).T

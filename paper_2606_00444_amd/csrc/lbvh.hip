@@ -1,0 +1,556 @@
+// Linear BVH over triangles or points: build and refit (gfx950).
+//
+// The paper builds its collision structures once from the template faces and
+// reuses them for every frame (Sec. 3.4, Initialization; O(N_v) per frame);
+// the varying-topology baseline destroys and rebuilds them every frame
+// (Sec. 4.1).  The BVH kind is not named by the paper; this is a linear BVH
+// (Karras 2012) built entirely on the device:
+//
+//   init     clear build scratch (histograms, look-back words, counters)
+//   bounds   per-axis min/max of s = (v0 + v1) + v2, block reduce + one
+//            atomic per block on order-preserving uint encodings
+//   morton   30-bit codes defined in IEEE binary32 (no contraction), fused
+//            with the four 8-bit digit histograms of the radix sort
+//   sort     4 passes of a stable LSD radix sort of (code, id): one kernel per
+//            pass, tiles ranked with wave64 ballots (match masks over the 8
+//            digit bits), global digit offsets by decoupled look-back
+//   tree     Karras radix tree per internal node + leaf permutation of faces
+//   refit    bottom-up boxes with one arrival counter per internal node
+//
+// Node records are child-centric (two child boxes per internal node, 64 B) so
+// a traversal step reads one record.
+#include "mgu_internal.hpp"
+
+namespace mgu {
+namespace {
+
+constexpr int kSortThreads = 256;          // 4 waves
+constexpr int kSortItems = 16;             // keys per lane
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr uint32_t kFlagAgg = 1u << 30;    // look-back word: tile aggregate
+constexpr uint32_t kFlagPrefix = 2u << 30; //                 inclusive prefix
+constexpr uint32_t kValueMask = (1u << 30) - 1;
+constexpr int kSpinLimit = 1 << 24;        // bounded waits: error word instead of a hang
+
+constexpr int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+inline mg_lbvh_layout make_layout(int64_t n, int kind) {
+    mg_lbvh_layout L{};
+    const int64_t m = n > 0 ? n - 1 : 0;
+    int64_t o = 0;
+    L.off_header = o;      o += align256(sizeof(mg_lbvh_header));
+    L.off_codes = o;       o += align256(4 * n);
+    L.off_prim = o;        o += align256(4 * n);
+    L.off_leaf_faces = o;  o += align256(kind == MG_PRIM_TRIANGLES ? 12 * n : 0);
+    L.off_leaf_parent = o; o += align256(4 * n);
+    L.off_node_parent = o; o += align256(4 * m);
+    L.off_nodes = o;       o += align256(64 * m);
+    L.off_counters = o;    o += align256(4 * m);
+    L.total_bytes = o;
+    return L;
+}
+
+struct WsLayout {
+    int64_t keys_a, vals_a, keys_b, vals_b, hist, lookback, total;
+    int64_t tiles;
+};
+
+inline WsLayout make_ws(int64_t n) {
+    WsLayout W{};
+    W.tiles = (n + kSortTile - 1) / kSortTile;
+    int64_t o = 0;
+    W.keys_a = o;   o += align256(4 * n);
+    W.vals_a = o;   o += align256(4 * n);
+    W.keys_b = o;   o += align256(4 * n);
+    W.vals_b = o;   o += align256(4 * n);
+    W.hist = o;     o += align256(4 * 4 * 256);
+    W.lookback = o; o += align256(4 * 4 * 256 * W.tiles);
+    W.total = o;
+    return W;
+}
+
+template <typename T>
+inline T *at(void *base, int64_t off) {
+    return reinterpret_cast<T *>(static_cast<char *>(base) + off);
+}
+
+// ------------------------------------------------------------------ kernels
+
+__global__ void build_init_kernel(mg_lbvh_header *hdr, uint32_t *hist, uint32_t *lookback,
+                                  int64_t n_lookback, int n, int kind) {
+    const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    if (hist != nullptr)          // no sort scratch when there are no primitives
+        for (int64_t i = tid; i < 4 * 256; i += stride) hist[i] = 0;
+    if (lookback != nullptr)
+        for (int64_t i = tid; i < n_lookback; i += stride) lookback[i] = 0;
+    if (tid == 0) {
+        hdr->n_prims = n;
+        hdr->prim_kind = kind;
+        hdr->status = 0;
+        for (int k = 0; k < 3; ++k) {
+            hdr->bounds_enc[k] = 0xffffffffu;   // running min
+            hdr->bounds_enc[3 + k] = 0u;        // running max
+        }
+        for (int k = 0; k < 4; ++k) hdr->tile_counter[k] = 0;
+    }
+}
+
+// s = (v0 + v1) + v2 for face i (three times its centroid), or the point itself.
+// Every operation is a separately rounded binary32 add.
+__device__ __forceinline__ f3 centroid_sum(const float *__restrict__ v, int64_t nv,
+                                           const int32_t *__restrict__ faces, int64_t n, int64_t i) {
+    if (faces == nullptr) return load3(v, nv, i);
+    const f3 a = load3(v, nv, faces[i]);
+    const f3 b = load3(v, nv, faces[n + i]);
+    const f3 c = load3(v, nv, faces[2 * n + i]);
+    return (a + b) + c;
+}
+
+__device__ __forceinline__ float wave_min(float x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x = fminf(x, __shfl_xor(x, o));
+    return x;
+}
+__device__ __forceinline__ float wave_max(float x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x = fmaxf(x, __shfl_xor(x, o));
+    return x;
+}
+
+__global__ __launch_bounds__(256) void bounds_kernel(const float *__restrict__ v, int64_t nv,
+                                                     const int32_t *__restrict__ faces, int64_t n,
+                                                     mg_lbvh_header *hdr) {
+    __shared__ float s_red[6][4];
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const f3 s = centroid_sum(v, nv, faces, n, i);
+        mn[0] = fminf(mn[0], s.x); mn[1] = fminf(mn[1], s.y); mn[2] = fminf(mn[2], s.z);
+        mx[0] = fmaxf(mx[0], s.x); mx[1] = fmaxf(mx[1], s.y); mx[2] = fmaxf(mx[2], s.z);
+    }
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        mn[k] = wave_min(mn[k]);
+        mx[k] = wave_max(mx[k]);
+    }
+    if (lane == 0)
+        for (int k = 0; k < 3; ++k) { s_red[k][wave] = mn[k]; s_red[3 + k][wave] = mx[k]; }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int k = threadIdx.x;
+        float r = s_red[k][0];
+        for (int w = 1; w < 4; ++w) r = k < 3 ? fminf(r, s_red[k][w]) : fmaxf(r, s_red[k][w]);
+        if (k < 3) atomicMin(&hdr->bounds_enc[k], f2ord(r));
+        else atomicMax(&hdr->bounds_enc[k], f2ord(r));
+    }
+}
+
+// Put bit i of a 10-bit value at bit 3 i (magic-number spreading).
+__device__ __forceinline__ uint32_t spread10(uint32_t x) {
+    x &= 0x3ffu;
+    x = (x | (x << 16)) & 0x030000ffu;
+    x = (x | (x << 8)) & 0x0300f00fu;
+    x = (x | (x << 4)) & 0x030c30c3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+// Quantisation defined in binary32: q = min(1023, trunc((s - lo) * scale)).
+__device__ __forceinline__ uint32_t quant10(float s, float lo, float scale) {
+#pragma clang fp contract(off)
+    const float x = (s - lo) * scale;
+    const uint32_t q = static_cast<uint32_t>(x);
+    return q < 1023u ? q : 1023u;
+}
+
+__global__ __launch_bounds__(256) void morton_kernel(const float *__restrict__ v, int64_t nv,
+                                                     const int32_t *__restrict__ faces, int64_t n,
+                                                     mg_lbvh_header *hdr, uint32_t *__restrict__ keys,
+                                                     uint32_t *__restrict__ hist) {
+#pragma clang fp contract(off)
+    __shared__ uint32_t s_hist[4][256];
+    for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) (&s_hist[0][0])[i] = 0;
+    float lo[3], scale[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = ord2f(hdr->bounds_enc[k]);
+        const float hi = ord2f(hdr->bounds_enc[3 + k]);
+        // 1024 / (hi - lo) correctly rounded to binary32: the binary64 quotient of
+        // two binary32 values rounds to the same binary32 as a direct division.
+        const float ext = hi - lo[k];
+        scale[k] = hi > lo[k] ? static_cast<float>(1024.0 / static_cast<double>(ext)) : 0.0f;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int k = 0; k < 3; ++k) { hdr->quant_lo[k] = lo[k]; hdr->quant_scale[k] = scale[k]; }
+    }
+    __syncthreads();
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const f3 s = centroid_sum(v, nv, faces, n, i);
+        const uint32_t code = (spread10(quant10(s.x, lo[0], scale[0])) << 2) |
+                              (spread10(quant10(s.y, lo[1], scale[1])) << 1) |
+                              spread10(quant10(s.z, lo[2], scale[2]));
+        keys[i] = code;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) atomicAdd(&s_hist[p][(code >> (8 * p)) & 0xffu], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) {
+        const uint32_t c = (&s_hist[0][0])[i];
+        if (c) atomicAdd(hist + i, c);
+    }
+}
+
+// Exclusive scan of one value per thread over a 256-thread block.
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t *s_tmp /*[4]*/,
+                                                       uint32_t &total) {
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    uint32_t inc = x;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == kWave - 1) s_tmp[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t t = s_tmp[w];
+        if (w < wave) before += t;
+        total += t;
+    }
+    __syncthreads();
+    return before + inc - x;
+}
+
+// One stable LSD pass over digit (key >> shift) & 255.  vals_in == nullptr
+// means the values are the input positions (first pass).
+__global__ __launch_bounds__(kSortThreads) void radix_pass_kernel(
+    const uint32_t *__restrict__ keys_in, const int32_t *__restrict__ vals_in,
+    uint32_t *__restrict__ keys_out, int32_t *__restrict__ vals_out, int64_t n, int shift,
+    const uint32_t *__restrict__ hist, uint32_t *lookback, uint32_t *tile_counter, int32_t *status) {
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_wave_cnt[4][256];
+    __shared__ uint32_t s_digit_start[256];
+    __shared__ uint32_t s_global[256];
+    __shared__ uint32_t s_tmp[4];
+    __shared__ uint32_t s_keys[kSortTile];
+    __shared__ int32_t s_vals[kSortTile];
+
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
+    for (int i = tid; i < 4 * 256; i += kSortThreads) (&s_wave_cnt[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t base = tile * kSortTile;
+
+    uint32_t key[kSortItems];
+    int32_t val[kSortItems];
+    uint32_t rank[kSortItems];
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+        const int64_t idx = base + (static_cast<int64_t>(wave) * kSortItems + j) * kWave + lane;
+        const bool valid = idx < n;
+        key[j] = valid ? keys_in[idx] : 0u;
+        val[j] = valid ? (vals_in ? vals_in[idx] : static_cast<int32_t>(idx)) : 0;
+        const uint32_t d = (key[j] >> shift) & 0xffu;
+        // lanes of this wave holding the same digit (match mask from 8 ballots)
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        const uint64_t below = m & lt;
+        const uint32_t prev = valid ? s_wave_cnt[wave][d] : 0u;
+        rank[j] = prev + static_cast<uint32_t>(__popcll(below));
+        if (valid && below == 0) s_wave_cnt[wave][d] = prev + static_cast<uint32_t>(__popcll(m));
+    }
+    __syncthreads();
+
+    // per digit: counts of each wave -> exclusive offsets across waves
+    const int d = tid;
+    const uint32_t c0 = s_wave_cnt[0][d], c1 = s_wave_cnt[1][d], c2 = s_wave_cnt[2][d], c3 = s_wave_cnt[3][d];
+    const uint32_t tile_cnt = c0 + c1 + c2 + c3;
+    // publish this tile's aggregate as early as possible
+    uint32_t *my_word = lookback + tile * 256 + d;
+    __hip_atomic_store(my_word, (tile == 0 ? kFlagPrefix : kFlagAgg) | tile_cnt, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();   // every wave has read its counts before they are overwritten
+    s_wave_cnt[0][d] = 0;
+    s_wave_cnt[1][d] = c0;
+    s_wave_cnt[2][d] = c0 + c1;
+    s_wave_cnt[3][d] = c0 + c1 + c2;
+    uint32_t tile_total;
+    const uint32_t dstart = block_excl_scan256(tile_cnt, s_tmp, tile_total);
+    s_digit_start[d] = dstart;
+    uint32_t hist_total;
+    const uint32_t dbase = block_excl_scan256(hist[d], s_tmp, hist_total);
+
+    // decoupled look-back: sum the counts of digit d over all earlier tiles
+    uint32_t excl = 0;
+    if (tile > 0) {
+        int64_t t = tile - 1;
+        int spins = 0;
+        while (true) {
+            const uint32_t w = __hip_atomic_load(lookback + t * 256 + d, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            if ((w & ~kValueMask) == 0) {
+                if (++spins > kSpinLimit) {   // never expected: report instead of hanging
+                    atomicOr(status, 1);
+                    break;
+                }
+                continue;
+            }
+            excl += w & kValueMask;
+            if (w & kFlagPrefix) break;
+            --t;
+        }
+        __hip_atomic_store(my_word, kFlagPrefix | (excl + tile_cnt), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    s_global[d] = dbase + excl - dstart;
+    __syncthreads();
+
+    // scatter into the tile in digit order (stable), then write out coalesced
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+        const int64_t idx = base + (static_cast<int64_t>(wave) * kSortItems + j) * kWave + lane;
+        if (idx < n) {
+            const uint32_t dj = (key[j] >> shift) & 0xffu;
+            const uint32_t pos = s_digit_start[dj] + s_wave_cnt[wave][dj] + rank[j];
+            s_keys[pos] = key[j];
+            s_vals[pos] = val[j];
+        }
+    }
+    __syncthreads();
+    const int64_t count = (n - base) < kSortTile ? (n - base) : kSortTile;
+    for (int i = tid; i < count; i += kSortThreads) {
+        const uint32_t k = s_keys[i];
+        const uint32_t out = s_global[(k >> shift) & 0xffu] + i;
+        if (out < static_cast<uint64_t>(n)) {
+            keys_out[out] = k;
+            vals_out[out] = s_vals[i];
+        } else {
+            atomicOr(status, 2);   // inconsistent histogram: never expected
+        }
+    }
+}
+
+// delta(i, j) of Karras 2012 over keys (code, index); -1 outside [0, n).
+__device__ __forceinline__ int kdelta(const uint32_t *__restrict__ codes, int64_t n, int64_t i, int64_t j) {
+    if (j < 0 || j >= n) return -1;
+    const uint32_t a = codes[i], b = codes[j];
+    if (a != b) return __clz(static_cast<int>(a ^ b));
+    return 32 + __clz(static_cast<int>(static_cast<uint32_t>(i) ^ static_cast<uint32_t>(j)));
+}
+
+// Internal node i (i < n - 1) and leaf i (i < n): Karras's range and split
+// search; children's parent tags; leaf face permutation; counter reset.
+__global__ __launch_bounds__(256) void hierarchy_kernel(const uint32_t *__restrict__ codes,
+                                                        const int32_t *__restrict__ prim, int64_t n,
+                                                        const int32_t *__restrict__ faces,
+                                                        int32_t *__restrict__ leaf_faces,
+                                                        int32_t *__restrict__ leaf_parent,
+                                                        int32_t *__restrict__ node_parent,
+                                                        uint32_t *__restrict__ counters) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (faces) {
+        const int32_t p = prim[i];
+        leaf_faces[i] = faces[p];
+        leaf_faces[n + i] = faces[n + p];
+        leaf_faces[2 * n + i] = faces[2 * n + p];
+    }
+    if (n == 1) {
+        leaf_parent[0] = -1;
+        return;
+    }
+    if (i >= n - 1) return;
+    const int d = (kdelta(codes, n, i, i + 1) - kdelta(codes, n, i, i - 1)) > 0 ? 1 : -1;
+    const int dmin = kdelta(codes, n, i, i - d);
+    int64_t lmax = 2;
+    while (kdelta(codes, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    int64_t l = 0;
+    for (int64_t t = lmax >> 1; t >= 1; t >>= 1)
+        if (kdelta(codes, n, i, i + (l + t) * d) > dmin) l += t;
+    const int64_t j = i + l * d;
+    const int dnode = kdelta(codes, n, i, j);
+    int64_t s = 0;
+    for (int64_t div = 2;; div <<= 1) {
+        const int64_t t = (l + div - 1) / div;
+        if (kdelta(codes, n, i, i + (s + t) * d) > dnode) s += t;
+        if (t <= 1) break;
+    }
+    const int64_t gamma = i + s * d + (d < 0 ? -1 : 0);
+    const int64_t lo = i < j ? i : j, hi = i < j ? j : i;
+    const int32_t tag_l = static_cast<int32_t>(i << 1), tag_r = static_cast<int32_t>((i << 1) | 1);
+    if (lo == gamma) leaf_parent[gamma] = tag_l; else node_parent[gamma] = tag_l;
+    if (hi == gamma + 1) leaf_parent[gamma + 1] = tag_r; else node_parent[gamma + 1] = tag_r;
+    if (i == 0) node_parent[0] = -1;
+    counters[i] = 0;
+}
+
+struct RefitArgs {
+    const float *verts; int64_t nv;
+    const int32_t *leaf_faces; const int32_t *prim;
+    const int32_t *leaf_parent; const int32_t *node_parent;
+    float4 *nodes; uint32_t *counters; mg_lbvh_header *hdr;
+    int64_t n;
+};
+
+// Bottom-up refit: each leaf writes its box into its parent's record and bumps
+// the parent's arrival counter; the second arrival (acquire/release at agent
+// scope, so boxes written on another XCD are visible) merges the sibling box
+// and climbs.  Counters are reset by the second arrival, so they are zero
+// again when the kernel ends.
+__global__ __launch_bounds__(256) void refit_kernel(RefitArgs a) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    f3 lo, hi;
+    const int32_t p0 = a.prim[i];
+    if (a.leaf_faces) {
+        const f3 x = load3(a.verts, a.nv, a.leaf_faces[i]);
+        const f3 y = load3(a.verts, a.nv, a.leaf_faces[a.n + i]);
+        const f3 z = load3(a.verts, a.nv, a.leaf_faces[2 * a.n + i]);
+        lo = fmin3(fmin3(x, y), z);
+        hi = fmax3(fmax3(x, y), z);
+    } else {
+        lo = hi = load3(a.verts, a.nv, p0);
+    }
+    int32_t tag = a.leaf_parent[i];
+    int32_t ref = ~static_cast<int32_t>(i), aux = p0;
+    // A valid tree is at most 62 levels deep; the cap and the range check only
+    // turn a corrupted buffer into an error word instead of a fault or a hang.
+    for (int level = 0;; ++level) {
+        if (level > 64 || (tag >= 0 && (tag >> 1) >= a.n - 1)) {
+            atomicOr(&a.hdr->status, 4);
+            return;
+        }
+        if (tag < 0) {
+            a.hdr->root_lo[0] = lo.x; a.hdr->root_lo[1] = lo.y; a.hdr->root_lo[2] = lo.z;
+            a.hdr->root_hi[0] = hi.x; a.hdr->root_hi[1] = hi.y; a.hdr->root_hi[2] = hi.z;
+            return;
+        }
+        const int32_t p = tag >> 1, slot = tag & 1;
+        float4 *rec = a.nodes + 4 * static_cast<int64_t>(p);
+        rec[2 * slot] = make_float4(lo.x, lo.y, lo.z, __int_as_float(ref));
+        rec[2 * slot + 1] = make_float4(hi.x, hi.y, hi.z, __int_as_float(aux));
+        const uint32_t old = __hip_atomic_fetch_add(a.counters + p, 1u, __ATOMIC_ACQ_REL,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        if (old == 0) return;
+        __hip_atomic_store(a.counters + p, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const float4 s0 = rec[2 * (1 - slot)], s1 = rec[2 * (1 - slot) + 1];
+        lo = fmin3(lo, f3{s0.x, s0.y, s0.z});
+        hi = fmax3(hi, f3{s1.x, s1.y, s1.z});
+        ref = p;
+        aux = 0;
+        tag = a.node_parent[p];
+    }
+}
+
+mg_status check_kind(int32_t kind) {
+    return (kind == MG_PRIM_TRIANGLES || kind == MG_PRIM_POINTS) ? MG_OK : MG_ERR_INVALID_ARGUMENT;
+}
+
+mg_status launch_refit(const float *verts, int64_t nv, void *bvh, int64_t n, int kind, hipStream_t s) {
+    const mg_lbvh_layout L = make_layout(n, kind);
+    RefitArgs a;
+    a.verts = verts; a.nv = nv;
+    a.leaf_faces = kind == MG_PRIM_TRIANGLES ? at<int32_t>(bvh, L.off_leaf_faces) : nullptr;
+    a.prim = at<int32_t>(bvh, L.off_prim);
+    a.leaf_parent = at<int32_t>(bvh, L.off_leaf_parent);
+    a.node_parent = at<int32_t>(bvh, L.off_node_parent);
+    a.nodes = at<float4>(bvh, L.off_nodes);
+    a.counters = at<uint32_t>(bvh, L.off_counters);
+    a.hdr = at<mg_lbvh_header>(bvh, L.off_header);
+    a.n = n;
+    hipLaunchKernelGGL(refit_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, a);
+    return launch_status();
+}
+
+}  // namespace
+}  // namespace mgu
+
+using namespace mgu;
+
+extern "C" mg_status mg_lbvh_layout_query(int32_t n_prims, int32_t prim_kind, mg_lbvh_layout *out) {
+    if (!out || bad_count(n_prims) || check_kind(prim_kind) != MG_OK) return MG_ERR_INVALID_ARGUMENT;
+    *out = make_layout(n_prims, prim_kind);
+    return MG_OK;
+}
+
+extern "C" mg_status mg_lbvh_workspace_size(int32_t n_prims, int32_t prim_kind, size_t *ws_bytes) {
+    if (!ws_bytes || bad_count(n_prims) || check_kind(prim_kind) != MG_OK) return MG_ERR_INVALID_ARGUMENT;
+    *ws_bytes = static_cast<size_t>(make_ws(n_prims).total);
+    return MG_OK;
+}
+
+extern "C" mg_status mg_lbvh_build(const float *verts, int32_t n_verts, const int32_t *faces,
+                                   int32_t n_prims, int32_t prim_kind, void *bvh, size_t bvh_bytes,
+                                   void *ws, size_t ws_bytes, void *stream) {
+    if (bad_count(n_verts) || bad_count(n_prims) || check_kind(prim_kind) != MG_OK)
+        return MG_ERR_INVALID_ARGUMENT;
+    if (prim_kind == MG_PRIM_TRIANGLES && n_prims > 0 && (!faces || n_verts == 0))
+        return MG_ERR_INVALID_ARGUMENT;
+    if (prim_kind == MG_PRIM_POINTS && (faces || n_verts != n_prims)) return MG_ERR_INVALID_ARGUMENT;
+    if (!bvh) return MG_ERR_INVALID_ARGUMENT;
+    const mg_lbvh_layout L = make_layout(n_prims, prim_kind);
+    if (bvh_bytes < static_cast<size_t>(L.total_bytes)) return MG_ERR_WORKSPACE_TOO_SMALL;
+    const WsLayout W = make_ws(n_prims);
+    if (n_prims > 0 && (!ws || ws_bytes < static_cast<size_t>(W.total))) return MG_ERR_WORKSPACE_TOO_SMALL;
+    if (n_prims > 0 && !verts) return MG_ERR_INVALID_ARGUMENT;
+    hipStream_t s = as_stream(stream);
+    const int64_t n = n_prims;
+    mg_lbvh_header *hdr = at<mg_lbvh_header>(bvh, L.off_header);
+    uint32_t *hist = n ? at<uint32_t>(ws, W.hist) : nullptr;
+    uint32_t *lookback = n ? at<uint32_t>(ws, W.lookback) : nullptr;
+    const int64_t n_lookback = 4 * 256 * W.tiles;
+    hipLaunchKernelGGL(build_init_kernel, dim3(n_lookback > 65536 ? 256 : 16), dim3(256), 0, s, hdr,
+                       hist, lookback, n_lookback, n_prims, prim_kind);
+    if (launch_status() != MG_OK) return MG_ERR_HIP;
+    if (n == 0) return MG_OK;
+    const int32_t *fz = prim_kind == MG_PRIM_TRIANGLES ? faces : nullptr;
+    const int grid = static_cast<int>(std::min<int64_t>(blocks_for(n, 256), 1024));
+    hipLaunchKernelGGL(bounds_kernel, dim3(grid), dim3(256), 0, s, verts, (int64_t)n_verts, fz, n, hdr);
+    uint32_t *ka = at<uint32_t>(ws, W.keys_a), *kb = at<uint32_t>(ws, W.keys_b);
+    int32_t *va = at<int32_t>(ws, W.vals_a), *vb = at<int32_t>(ws, W.vals_b);
+    hipLaunchKernelGGL(morton_kernel, dim3(grid), dim3(256), 0, s, verts, (int64_t)n_verts, fz, n, hdr, ka,
+                       hist);
+    uint32_t *codes = at<uint32_t>(bvh, L.off_codes);
+    int32_t *prim = at<int32_t>(bvh, L.off_prim);
+    // pass p reads (src) and writes (dst): A->B, B->A, A->B, B->final
+    const uint32_t *ksrc[4] = {ka, kb, ka, kb};
+    const int32_t *vsrc[4] = {nullptr, vb, va, vb};
+    uint32_t *kdst[4] = {kb, ka, kb, codes};
+    int32_t *vdst[4] = {vb, va, vb, prim};
+    for (int p = 0; p < 4; ++p) {
+        hipLaunchKernelGGL(radix_pass_kernel, dim3(static_cast<unsigned>(W.tiles)), dim3(kSortThreads), 0, s,
+                           ksrc[p], vsrc[p], kdst[p], vdst[p], n, 8 * p, hist + 256 * p,
+                           lookback + static_cast<int64_t>(p) * 256 * W.tiles, &hdr->tile_counter[p],
+                           &hdr->status);
+    }
+    hipLaunchKernelGGL(hierarchy_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, codes, prim, n, fz,
+                       fz ? at<int32_t>(bvh, L.off_leaf_faces) : nullptr, at<int32_t>(bvh, L.off_leaf_parent),
+                       at<int32_t>(bvh, L.off_node_parent), at<uint32_t>(bvh, L.off_counters));
+    if (launch_status() != MG_OK) return MG_ERR_HIP;
+    return launch_refit(verts, n_verts, bvh, n, prim_kind, s);
+}
+
+extern "C" mg_status mg_lbvh_refit(const float *verts, int32_t n_verts, void *bvh, size_t bvh_bytes,
+                                   int32_t n_prims, int32_t prim_kind, void *stream) {
+    if (bad_count(n_verts) || bad_count(n_prims) || check_kind(prim_kind) != MG_OK || !bvh)
+        return MG_ERR_INVALID_ARGUMENT;
+    const mg_lbvh_layout L = make_layout(n_prims, prim_kind);
+    if (bvh_bytes < static_cast<size_t>(L.total_bytes)) return MG_ERR_WORKSPACE_TOO_SMALL;
+    if (prim_kind == MG_PRIM_POINTS && n_verts != n_prims) return MG_ERR_TOPOLOGY_MISMATCH;
+    if (n_prims == 0) return MG_OK;
+    if (!verts || n_verts == 0) return MG_ERR_INVALID_ARGUMENT;
+    return launch_refit(verts, n_verts, bvh, n_prims, prim_kind, as_stream(stream));
+}

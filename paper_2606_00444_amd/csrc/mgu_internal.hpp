@@ -1,0 +1,153 @@
+// Internal helpers shared by the libmgu HIP translation units (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "mgu.h"
+
+namespace mgu {
+
+constexpr int kWave = 64;
+constexpr int kMaxCount = 1 << 30;
+
+// ---------------------------------------------------------------- host side
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline bool bad_count(int64_t n) { return n < 0 || n >= kMaxCount; }
+
+inline int blocks_for(int64_t n, int threads) {
+    return static_cast<int>((n + threads - 1) / threads);
+}
+
+// Maps the status of the last launch (or any HIP call) to mg_status.
+inline mg_status launch_status() {
+    return hipGetLastError() == hipSuccess ? MG_OK : MG_ERR_HIP;
+}
+
+// ---------------------------------------------------------------- device side
+struct f3 {
+    float x, y, z;
+};
+
+__device__ __forceinline__ f3 mk(float x, float y, float z) { return f3{x, y, z}; }
+__device__ __forceinline__ f3 operator+(f3 a, f3 b) { return f3{a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ f3 operator-(f3 a, f3 b) { return f3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ f3 operator*(float s, f3 a) { return f3{s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ f3 cross(f3 a, f3 b) {
+    return f3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ f3 fmin3(f3 a, f3 b) { return f3{fminf(a.x, b.x), fminf(a.y, b.y), fminf(a.z, b.z)}; }
+__device__ __forceinline__ f3 fmax3(f3 a, f3 b) { return f3{fmaxf(a.x, b.x), fmaxf(a.y, b.y), fmaxf(a.z, b.z)}; }
+
+// SoA [3][n] load of element i.
+__device__ __forceinline__ f3 load3(const float *__restrict__ p, int64_t n, int64_t i) {
+    return f3{p[i], p[n + i], p[2 * n + i]};
+}
+__device__ __forceinline__ void store3(float *__restrict__ p, int64_t n, int64_t i, f3 v) {
+    p[i] = v.x;
+    p[n + i] = v.y;
+    p[2 * n + i] = v.z;
+}
+
+// Closest point on triangle abc to p by Voronoi regions (Ericson 2005,
+// Sec. 5.1.5).  Returns squared distance; w1, w2 are the barycentric weights of
+// b and c (weight of a = 1 - w1 - w2).  A triangle whose interior denominator
+// is not positive (zero area in float32) falls back to the nearest of its edge
+// segments, ties in the order ab, ac, bc.
+__device__ __forceinline__ float seg_closest(f3 p, f3 a, f3 b, float &t) {
+    f3 ab = b - a;
+    float den = dot(ab, ab);
+    t = den > 0.0f ? dot(p - a, ab) / den : 0.0f;
+    t = fminf(fmaxf(t, 0.0f), 1.0f);
+    f3 d = p - (a + t * ab);
+    return dot(d, d);
+}
+
+__device__ __forceinline__ float tri_closest(f3 p, f3 a, f3 b, f3 c, float &w1, float &w2) {
+    f3 ab = b - a, ac = c - a, ap = p - a;
+    float d1 = dot(ab, ap), d2 = dot(ac, ap);
+    if (d1 <= 0.0f && d2 <= 0.0f) {
+        w1 = 0.0f; w2 = 0.0f;
+    } else {
+        f3 bp = p - b;
+        float d3 = dot(ab, bp), d4 = dot(ac, bp);
+        float vc = d1 * d4 - d3 * d2;
+        if (d3 >= 0.0f && d4 <= d3) {
+            w1 = 1.0f; w2 = 0.0f;
+        } else if (vc <= 0.0f && d1 >= 0.0f && d3 <= 0.0f) {
+            float den = d1 - d3;
+            w1 = den != 0.0f ? d1 / den : 0.0f; w2 = 0.0f;
+        } else {
+            f3 cp = p - c;
+            float d5 = dot(ab, cp), d6 = dot(ac, cp);
+            float vb = d5 * d2 - d1 * d6;
+            float va = d3 * d6 - d5 * d4;
+            if (d6 >= 0.0f && d5 <= d6) {
+                w1 = 0.0f; w2 = 1.0f;
+            } else if (vb <= 0.0f && d2 >= 0.0f && d6 <= 0.0f) {
+                float den = d2 - d6;
+                w1 = 0.0f; w2 = den != 0.0f ? d2 / den : 0.0f;
+            } else if (va <= 0.0f && (d4 - d3) >= 0.0f && (d5 - d6) >= 0.0f) {
+                float den = (d4 - d3) + (d5 - d6);
+                float t = den != 0.0f ? (d4 - d3) / den : 0.0f;
+                w1 = 1.0f - t; w2 = t;
+            } else {
+                float den = va + vb + vc;
+                if (den > 0.0f) {
+                    w1 = vb / den; w2 = vc / den;
+                } else {
+                    float t, best = seg_closest(p, a, b, t);
+                    w1 = t; w2 = 0.0f;
+                    float d = seg_closest(p, a, c, t);
+                    if (d < best) { best = d; w1 = 0.0f; w2 = t; }
+                    d = seg_closest(p, b, c, t);
+                    if (d < best) { w1 = 1.0f - t; w2 = t; }
+                }
+            }
+        }
+    }
+    float w0 = 1.0f - w1 - w2;
+    f3 q = f3{w0 * a.x + w1 * b.x + w2 * c.x, w0 * a.y + w1 * b.y + w2 * c.y,
+              w0 * a.z + w1 * b.z + w2 * c.z};
+    f3 d = p - q;
+    return dot(d, d);
+}
+
+// Unit normal of triangle abc from its stored winding; zero when |ab| == 0 or
+// |ab x ac| == 0 (degenerate).
+__device__ __forceinline__ f3 tri_normal(f3 a, f3 b, f3 c) {
+    f3 e1 = b - a;
+    f3 n = cross(e1, c - a);
+    float l1 = dot(e1, e1), ln = dot(n, n);
+    if (l1 == 0.0f || ln == 0.0f) return f3{0.0f, 0.0f, 0.0f};
+    float r = 1.0f / sqrtf(ln);
+    return r * n;
+}
+
+// Squared distance from p to an axis-aligned box.
+__device__ __forceinline__ float box_dist2(f3 p, f3 lo, f3 hi) {
+    float dx = fmaxf(fmaxf(lo.x - p.x, p.x - hi.x), 0.0f);
+    float dy = fmaxf(fmaxf(lo.y - p.y, p.y - hi.y), 0.0f);
+    float dz = fmaxf(fmaxf(lo.z - p.z, p.z - hi.z), 0.0f);
+    return dx * dx + dy * dy + dz * dz;
+}
+
+// Order-preserving float <-> uint32 encoding (for atomic min/max of floats).
+__device__ __forceinline__ uint32_t f2ord(float f) {
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float ord2f(uint32_t u) {
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const int lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+}  // namespace mgu

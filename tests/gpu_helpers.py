@@ -1,0 +1,96 @@
+"""Shared helpers for the GPU parity tests: device transfer, BVH decoding, tolerances.
+
+The tolerance rule (float32 device vs float64 oracle), with L the diagonal-scale
+of the frame's mesh (largest bounding-box extent):
+  positions, means, distances  |d| <= 1e-5 * max(|ref|, 0.1 L)
+  covariance entries           |d| <= 1e-5 * ||Sigma_ref||_F
+  quaternions                  min(|q - q_ref|, |q + q_ref|) <= 1e-5
+  boxes, codes, permutations, topology: bitwise
+  face ids: bitwise except ties (the oracle distance to the device's face is
+  within the position tolerance of the oracle's minimum).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+REL = 1e-5
+
+
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_00444_amd as mg
+    mg.check_device()          # raises if libmgu.so is missing or the device is not gfx950
+    return torch.device("cuda:0")
+
+
+def dev(a, device):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def scale_of(verts):
+    v = np.asarray(verts, dtype=np.float64)
+    return float(np.ptp(v, axis=1).max())
+
+
+def assert_positions(got, ref, L, what="positions"):
+    got = np.asarray(got, dtype=np.float64)
+    tol = REL * np.maximum(np.abs(ref), 0.1 * L)
+    bad = np.abs(got - ref) > tol
+    assert not bad.any(), f"{what}: {bad.sum()} entries off, worst {np.max(np.abs(got - ref) / tol):.3g}x tol"
+
+
+def assert_quats(got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    d = np.minimum(np.linalg.norm(got - ref, axis=0), np.linalg.norm(got + ref, axis=0))
+    assert d.max() <= REL, f"quaternions off by {d.max():.3g}"
+
+
+def assert_cov(got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    # Frobenius norm of the symmetric matrix from its packed entries
+    fro = np.sqrt(ref[0] ** 2 + ref[3] ** 2 + ref[5] ** 2 + 2 * (ref[1] ** 2 + ref[2] ** 2 + ref[4] ** 2))
+    bad = np.abs(got - ref) > REL * fro[None]
+    assert not bad.any(), f"covariance: {bad.sum()} entries off"
+
+
+def decode_bvh(bvh):
+    """Host copy of a device LBVH: codes, prim, topology and per-node boxes (Karras numbering)."""
+    n = bvh.n
+    m = max(n - 1, 0)
+    out = {
+        "codes": host(bvh.section("codes", torch.int32, n)).view(np.uint32),
+        "prim": host(bvh.section("prim", torch.int32, n)),
+        "leaf_parent": host(bvh.section("leaf_parent", torch.int32, n)),
+        "node_parent": host(bvh.section("node_parent", torch.int32, m)),
+    }
+    if bvh.kind == 0:
+        out["leaf_faces"] = host(bvh.section("leaf_faces", torch.int32, 3 * n)).reshape(3, n)
+    hdr = host(bvh.buf[:256].view(torch.float32))
+    hdr_i = host(bvh.buf[:256].view(torch.int32))
+    out["n_prims"], out["status"] = int(hdr_i[0]), int(hdr_i[2])
+    root = np.concatenate([hdr[4:7], hdr[8:11]]).astype(np.float64)
+    out["root_box"] = root
+    nodes = host(bvh.section("nodes", torch.float32, 16 * m)).reshape(m, 2, 2, 4)   # [node][slot][lo|hi][xyzw]
+    ints = nodes.view(np.int32)
+    out["child"] = np.stack([ints[:, 0, 0, 3], ints[:, 1, 0, 3]]) if m else np.zeros((2, 0), np.int32)
+    out["aux"] = np.stack([ints[:, 0, 1, 3], ints[:, 1, 1, 3]]) if m else np.zeros((2, 0), np.int32)
+    slot_box = np.concatenate([nodes[:, :, 0, :3], nodes[:, :, 1, :3]], axis=2).astype(np.float64)  # [m][2][6]
+    ib = np.zeros((m, 6))
+    lb = np.zeros((n, 6))
+    if m:
+        ib[0] = root
+        np_ = out["node_parent"]
+        c = np.arange(1, m)
+        ib[c] = slot_box[np_[c] >> 1, np_[c] & 1]
+        lp = out["leaf_parent"]
+        lb[:] = slot_box[lp >> 1, lp & 1]
+    elif n == 1:
+        lb[0] = root
+    out["internal_box"], out["leaf_box"] = ib, lb
+    return out

@@ -1,0 +1,162 @@
+"""GPU LBVH build and refit against the oracle: codes, permutation, topology and boxes bitwise."""
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import need_gpu, dev, decode_bvh
+from synth import make_config
+from oracle import lbvh as ol
+from oracle import morton as om
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def device():
+    return need_gpu()
+
+
+def _check_build(bvh, verts, faces):
+    got = decode_bvh(bvh)
+    ref = ol.build(verts, faces)
+    n = ref["perm"].size
+    assert got["status"] == 0
+    assert got["n_prims"] == n
+    np.testing.assert_array_equal(got["codes"], ref["sorted_codes"])
+    np.testing.assert_array_equal(got["prim"], ref["perm"])
+    if n > 1:
+        np.testing.assert_array_equal(got["child"], ref["tree"]["child"])
+        np.testing.assert_array_equal(got["node_parent"], _tags(ref["tree"], n)[0])
+        np.testing.assert_array_equal(got["leaf_parent"], _tags(ref["tree"], n)[1])
+        # aux of a leaf child is its original primitive id
+        leaf = got["child"] < 0
+        np.testing.assert_array_equal(got["aux"][leaf], ref["perm"][~got["child"][leaf]])
+    if faces is not None:
+        np.testing.assert_array_equal(got["leaf_faces"], np.asarray(faces)[:, ref["perm"]])
+    np.testing.assert_array_equal(got["leaf_box"], ref["leaf_box"])
+    np.testing.assert_array_equal(got["internal_box"], ref["internal_box"])
+    np.testing.assert_array_equal(got["root_box"], ref["root_box"])
+    return got, ref
+
+
+def _tags(tree, n):
+    """Parent tags (parent << 1 | slot) of internal nodes and leaves from the oracle tree."""
+    m = n - 1
+    node_tag = np.full(m, -1, np.int64)
+    leaf_tag = np.full(n, -1, np.int64)
+    for slot in (0, 1):
+        c = tree["child"][slot]
+        p = np.arange(m)
+        internal = c >= 0
+        node_tag[c[internal]] = (p[internal] << 1) | slot
+        leaf_tag[~c[~internal]] = (p[~internal] << 1) | slot
+    return node_tag.astype(np.int32), leaf_tag.astype(np.int32)
+
+
+@pytest.mark.parametrize("cfg,small", [(1, False), (2, False), (2, True), (5, True)])
+def test_build_template(device, cfg, small):
+    import paper_2606_00444_amd as mg
+    sc = make_config(cfg, small=small)
+    bvh = mg.lbvh_build(dev(sc.verts0, device), dev(sc.faces, device))
+    _check_build(bvh, sc.verts0, sc.faces)
+
+
+def test_build_varying_target(device):
+    import paper_2606_00444_amd as mg
+    sc = make_config(2)
+    for t in (0, 117):
+        tv, tf = sc.target(t)
+        bvh = mg.lbvh_build(dev(tv, device), dev(tf, device))
+        _check_build(bvh, tv, tf)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4095, 4096, 4097, 12289])
+def test_build_ragged_sizes_points(device, n):
+    import paper_2606_00444_amd as mg
+    rng = np.random.default_rng(n)
+    P = rng.normal(size=(3, n)).astype(np.float32)
+    bvh = mg.lbvh_build(dev(P, device), None)
+    _check_build(bvh, P, None)
+
+
+def test_build_degenerate_keys(device):
+    import paper_2606_00444_amd as mg
+    rng = np.random.default_rng(41)
+    # all centroids coincide: every code is 0, the tree is fixed by the index tie-break
+    V = np.ones((3, 30), np.float32)
+    F = rng.integers(0, 30, size=(3, 5000)).astype(np.int32)
+    bvh = mg.lbvh_build(dev(V, device), dev(F, device))
+    got, ref = _check_build(bvh, V, F)
+    assert (got["codes"] == 0).all()
+    # planar grid: one zero-extent axis, many duplicate codes
+    g = np.stack(np.meshgrid(np.arange(60), np.arange(60), indexing="ij"), 0).reshape(2, -1).astype(np.float32)
+    V = np.concatenate([g, np.zeros((1, g.shape[1]), np.float32)])
+    F = np.stack([np.arange(0, 3540), np.arange(1, 3541), np.arange(60, 3600)]).astype(np.int32)
+    bvh = mg.lbvh_build(dev(V, device), dev(F, device))
+    _check_build(bvh, V, F)
+
+
+def test_refit_matches_oracle_and_fresh_root(device):
+    import paper_2606_00444_amd as mg
+    sc = make_config(2)
+    bvh = mg.lbvh_build(dev(sc.verts0, device), dev(sc.faces, device))
+    ref = ol.build(sc.verts0, sc.faces)
+    for t in (3, 150):
+        V = sc.frames([t])[0]
+        Vd = dev(V, device)
+        mg.lbvh_refit(bvh, Vd)
+        got = decode_bvh(bvh)
+        lb = ol.leaf_boxes(V, sc.faces, ref["perm"])
+        ib = ol.refit(ref["tree"], lb)
+        np.testing.assert_array_equal(got["leaf_box"], lb)
+        np.testing.assert_array_equal(got["internal_box"], ib)
+        np.testing.assert_array_equal(got["root_box"], ib[0])
+        # same root as a fresh build of the same frame (different tree, same bounds)
+        fresh = mg.lbvh_build(Vd, dev(sc.faces, device))
+        np.testing.assert_array_equal(decode_bvh(fresh)["root_box"], got["root_box"])
+        # topology untouched by refit
+        np.testing.assert_array_equal(got["child"], ref["tree"]["child"])
+
+
+def test_refit_repeated_is_bitwise_stable(device):
+    import paper_2606_00444_amd as mg
+    sc = make_config(5, small=True)
+    bvh = mg.lbvh_build(dev(sc.verts0, device), dev(sc.faces, device))
+    V = dev(sc.frames([9])[0], device)
+    mg.lbvh_refit(bvh, V)
+    first = bvh.buf.clone()
+    for _ in range(50):
+        mg.lbvh_refit(bvh, V)
+    assert torch.equal(first, bvh.buf)
+
+
+def test_refit_points(device):
+    import paper_2606_00444_amd as mg
+    rng = np.random.default_rng(42)
+    P = rng.random((3, 20000)).astype(np.float32)
+    bvh = mg.lbvh_build(dev(P, device), None)
+    P2 = (P + 0.01 * rng.normal(size=P.shape)).astype(np.float32)
+    mg.lbvh_refit(bvh, dev(P2, device))
+    got = decode_bvh(bvh)
+    ref = ol.build(P, None)
+    lb = ol.leaf_boxes(P2, None, ref["perm"])
+    np.testing.assert_array_equal(got["leaf_box"], lb)
+    np.testing.assert_array_equal(got["internal_box"], ol.refit(ref["tree"], lb))
+
+
+def test_empty_build(device):
+    import paper_2606_00444_amd as mg
+    bvh = mg.lbvh_build(torch.empty(3, 0, device=device), torch.empty(3, 0, dtype=torch.int32, device=device))
+    torch.cuda.synchronize()
+    assert bvh.n == 0
+
+
+def test_build_large_template_and_rebuild_target(device):
+    import paper_2606_00444_amd as mg
+    sc = make_config(5)
+    bvh = mg.lbvh_build(dev(sc.verts0, device), dev(sc.faces, device))
+    _check_build(bvh, sc.verts0, sc.faces)
+    tv, tf = sc.target(11)            # 1,000,000 faces / 750,002 vertices
+    tb = mg.lbvh_build(dev(tv, device), dev(tf, device))
+    _check_build(tb, tv, tf)

@@ -1,0 +1,159 @@
+"""GPU Chamfer, point-to-mesh and binding gradients, and Adam against the float64 oracle."""
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import need_gpu, dev, host, scale_of
+from synth import make_config
+from oracle import losses as olo
+from oracle import closest as oc
+from oracle import adam as oa
+from oracle import gaussians as og
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def device():
+    return need_gpu()
+
+
+def _normwise(a, b):
+    return np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b)
+
+
+def test_mean_deterministic(device):
+    import paper_2606_00444_amd as mg
+    x = torch.rand(1_234_567, device=device)
+    a = mg.mean(x).item()
+    b = mg.mean(x).item()
+    assert a == b
+    assert a == pytest.approx(host(x).astype(np.float64).mean(), rel=1e-12)
+    assert mg.mean(torch.empty(0, device=device)).item() == 0.0
+
+
+def test_chamfer_parity(device):
+    import paper_2606_00444_amd as mg
+    sc = make_config(4, small=True)
+    Y = sc.extra["targets"]
+    mu = og.repose(sc.verts0, sc.faces, sc.binding)["mean"].astype(np.float32)
+    A, B = dev(mu, device), dev(Y, device)
+    ba, bb = mg.lbvh_build(A, None), mg.lbvh_build(B, None)
+    out = mg.chamfer(A, ba, B, bb)
+    cd, nn_ab, nn_ba, d_ab, d_ba = olo.chamfer(mu, Y)
+    means = host(out["means"])
+    assert means.sum() == pytest.approx(cd, rel=1e-5)
+    assert means[0] == pytest.approx(d_ab.mean(), rel=1e-5)
+    assert (host(out["nn_ab"]) == nn_ab).mean() > 0.999
+    assert (host(out["nn_ba"]) == nn_ba).mean() > 0.999
+
+
+def _gpu_template_grad(mg, device, sc, Y):
+    V = dev(sc.verts0, device)
+    F = dev(sc.faces, device)
+    b = {k: dev(v, device) for k, v in sc.binding.items()}
+    Yd = dev(Y, device)
+    bvh = mg.lbvh_build(V, F)
+    rec = mg.closest_point_query(bvh, V, Yd)
+    P = mg.mean(rec["dist2"]).item()
+    g = mg.mesh_gaussian_update(V, F, b["face"], b["bary"], b["q_local"], b["log_scale"], quat=False, cov=False)
+    mu = g["mean"]
+    bm, by = mg.lbvh_build(mu, None), mg.lbvh_build(Yd, None)
+    ch = mg.chamfer(mu, bm, Yd, by)
+    gV = mg.point_mesh_backward(V, F, Yd, rec, 1.0 / Y.shape[1])
+    gmu = mg.chamfer_backward(mu, Yd, ch["nn_ab"], ch["nn_ba"], 1.0 / mu.shape[1], 1.0 / Y.shape[1])
+    mg.mesh_gaussian_update_backward(V, F, b["face"], b["bary"], b["q_local"], b["log_scale"], None, gmu,
+                                     g_verts=gV)
+    argmins = (host(rec["face"]).astype(np.int64), host(ch["nn_ab"]).astype(np.int64),
+               host(ch["nn_ba"]).astype(np.int64))
+    return P + host(ch["means"]).sum(), host(gV), argmins
+
+
+def _oracle_grad_at(sc, Y, argmins):
+    """Oracle loss and analytic gradient, evaluated at the device's argmins after checking
+    that each of them ties the oracle's own minimum (gradients of a min are only defined
+    up to the choice among tied minimisers)."""
+    V, F, B = sc.verts0, sc.faces, sc.binding
+    face, nn_ab, nn_ba = argmins
+    L_ref, aux = olo.template_loss(V, F, B, Y)
+    Lsc = scale_of(V)
+    rec = oc.closest_on_faces(V, F, Y, face)
+    tol = 1e-5 * np.maximum(np.sqrt(aux["rec"]["dist2"]), 0.1 * Lsc)
+    assert (np.sqrt(rec["dist2"]) <= np.sqrt(aux["rec"]["dist2"]) + tol).all()
+    mu = aux["mu"]
+    d_ab = ((mu - Y[:, nn_ab]) ** 2).sum(0)
+    d_ba = ((mu[:, nn_ba] - Y) ** 2).sum(0)
+    _, _, _, r_ab, r_ba = olo.chamfer(mu, Y)
+    assert (np.sqrt(d_ab) <= np.sqrt(r_ab) + 1e-5 * np.maximum(np.sqrt(r_ab), 0.1 * Lsc)).all()
+    assert (np.sqrt(d_ba) <= np.sqrt(r_ba) + 1e-5 * np.maximum(np.sqrt(r_ba), 0.1 * Lsc)).all()
+    g = olo.point_to_mesh_grad(V, F, Y, rec)
+    g = g + olo.binding_vjp(V, F, B, olo.chamfer_grad_a(mu, Y, nn_ab, nn_ba))
+    return L_ref, g
+
+
+def test_template_gradient_fd_subset(device):
+    import paper_2606_00444_amd as mg
+    sc = make_config(4, small=True)
+    Y = sc.extra["targets"]
+    L_dev, g_dev, am = _gpu_template_grad(mg, device, sc, Y)
+    L_ref, g_ref = _oracle_grad_at(sc, Y, am)
+    assert L_dev == pytest.approx(L_ref, rel=1e-5)
+    assert _normwise(g_dev, g_ref) <= 1e-5
+    # where every argmin agrees, the oracle's own gradient is the same
+    L0, g0, aux = olo.template_loss_grad(sc.verts0, sc.faces, sc.binding, Y)
+    if all(np.array_equal(x, y) for x, y in zip(am, (aux["rec"]["face"], aux["nn_ab"], aux["nn_ba"]))):
+        assert _normwise(g_dev, g0) <= 1e-5
+
+
+def test_template_gradient_full_size_subsampled_targets(device):
+    import paper_2606_00444_amd as mg
+    sc = make_config(4)
+    Y = sc.extra["targets"][:, :4000]
+    L_dev, g_dev, am = _gpu_template_grad(mg, device, sc, Y)
+    L_ref, g_ref = _oracle_grad_at(sc, Y, am)
+    assert L_dev == pytest.approx(L_ref, rel=1e-5)
+    assert _normwise(g_dev, g_ref) <= 1e-5
+
+
+def test_binding_backward_all_outputs(device):
+    import paper_2606_00444_amd as mg
+    sc = make_config(2, small=True)
+    rng = np.random.default_rng(90)
+    G = sc.n_gauss
+    gm = rng.normal(size=(3, G)).astype(np.float32)
+    gr = rng.normal(size=(9, G)).astype(np.float32)
+    gc = rng.normal(size=(6, G)).astype(np.float32)
+    off = rng.normal(0, 0.01, G).astype(np.float32)
+    V = sc.frames([4])[0]
+    b = {k: dev(v, device) for k, v in sc.binding.items()}
+    g = mg.mesh_gaussian_update_backward(dev(V, device), dev(sc.faces, device), b["face"], b["bary"],
+                                         b["q_local"], b["log_scale"], dev(off, device), dev(gm, device),
+                                         dev(gr, device), dev(gc, device))
+    ref = olo.binding_vjp(V, sc.faces, sc.binding, gm, gr.reshape(3, 3, G).transpose(2, 0, 1), gc, offset=off)
+    assert _normwise(host(g), ref) <= 1e-5
+
+
+def test_adam_parity(device):
+    import paper_2606_00444_amd as mg
+    rng = np.random.default_rng(91)
+    th = rng.normal(size=60000).astype(np.float32)
+    p, m, v = dev(th, device), torch.zeros(60000, device=device), torch.zeros(60000, device=device)
+    tr, mr, vr = th.astype(np.float64), np.zeros(60000), np.zeros(60000)
+    for step in range(1, 6):
+        g = rng.normal(size=60000).astype(np.float32)
+        mg.adam_step(p, dev(g, device), m, v, step, 1e-3)
+        tr, mr, vr = oa.adam_step(tr, g, mr, vr, step, 1e-3)
+    assert np.abs(host(p) - tr).max() <= 1e-5 * max(1.0, np.abs(tr).max())
+
+
+def test_validation_helpers(device):
+    import paper_2606_00444_amd as mg
+    st = torch.zeros(1, dtype=torch.int32, device=device)
+    mg.validate_indices(torch.tensor([0, 5, 9], dtype=torch.int32, device=device), 10, st)
+    assert st.item() == 0
+    mg.validate_indices(torch.tensor([0, 5, 10], dtype=torch.int32, device=device), 10, st)
+    assert st.item() == 3
+    st.zero_()
+    mg.validate_finite(torch.tensor([0.0, float("nan")], device=device), st)
+    assert st.item() == 4

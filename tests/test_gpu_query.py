@@ -1,0 +1,176 @@
+"""GPU closest-point queries (collision, template projection) against the float64 brute-force oracle."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import need_gpu, dev, host, scale_of, assert_positions
+from synth import make_config
+from oracle import closest as oc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def device():
+    return need_gpu()
+
+
+def check_closest(got, verts, faces, queries, max_dist2=math.inf):
+    """Face equal except ties; point, bary, distance and normal within the tolerance rule.
+
+    The device's face must tie the oracle's minimum (its oracle distance is within
+    the position tolerance of the minimum).  Two faces can tie while their closest
+    points lie far apart (a query equidistant from two parts of the surface), so
+    point, barycentrics, distance and normal are compared with the oracle's
+    closest point on the device's face.
+    """
+    ref = oc.closest_point_mesh(verts, faces, queries, max_dist2=max_dist2)
+    L = scale_of(verts)
+    face = host(got["face"]).astype(np.int64)
+    hit = ref["face"] >= 0
+    if math.isinf(max_dist2):
+        assert (face >= 0).all()
+    assert (face[hit] >= 0).all()
+    at = oc.closest_on_faces(verts, faces, queries[:, hit], face[hit])
+    d_ref = np.sqrt(ref["dist2"][hit])
+    tol = 1e-5 * np.maximum(d_ref, 0.1 * L)
+    assert (np.sqrt(at["dist2"]) <= d_ref + tol).all(), "closest face not within tie tolerance"
+    assert_positions(np.sqrt(host(got["dist2"]).astype(np.float64)[hit]), np.sqrt(at["dist2"]), L, "distance")
+    assert_positions(host(got["point"])[:, hit], at["point"], L, "closest point")
+    if got.get("bary") is not None:
+        # the barycentrics reproduce the closest point on the device's face
+        w = host(got["bary"]).astype(np.float64)[:, hit]
+        tri = np.asarray(faces)[:, face[hit]]
+        V = np.asarray(verts, dtype=np.float64)
+        p = (1 - w[0] - w[1]) * V[:, tri[0]] + w[0] * V[:, tri[1]] + w[1] * V[:, tri[2]]
+        assert_positions(p, at["point"], L, "bary point")
+    if got.get("normal") is not None:
+        n_dev = host(got["normal"]).astype(np.float64)[:, hit]
+        assert np.abs(n_dev - at["normal"]).max() <= 1e-5
+    miss = ~hit
+    if miss.any():
+        assert (face[miss] == -1).all()
+        assert np.isinf(host(got["dist2"])[miss]).all()
+        np.testing.assert_array_equal(host(got["point"])[:, miss], queries[:, miss])
+    return ref
+
+
+def test_c1_all_queries(device):
+    import paper_2606_00444_amd as mg
+    sc = make_config(1)
+    V = sc.frames([22])[0]
+    bvh = mg.lbvh_build(dev(sc.verts0, device), dev(sc.faces, device))
+    Vd = dev(V, device)
+    mg.lbvh_refit(bvh, Vd)
+    got = mg.closest_point_query(bvh, Vd, dev(sc.queries, device), normal=True)
+    check_closest(got, V, sc.faces, sc.queries)
+
+
+def test_c2_collision_and_template_projection_sampled(device):
+    import paper_2606_00444_amd as mg
+    sc = make_config(2)
+    V = sc.frames([71])[0]
+    F = dev(sc.faces, device)
+    bvh = mg.lbvh_build(dev(sc.verts0, device), F)
+    Vd = dev(V, device)
+    mg.lbvh_refit(bvh, Vd)
+    got = mg.closest_point_query(bvh, Vd, dev(sc.queries, device), normal=True)
+    idx = np.random.default_rng(50).choice(sc.queries.shape[1], 1500, replace=False)
+    sub = {k: (v[..., idx] if v is not None else None) for k, v in got.items()}
+    check_closest(sub, V, sc.faces, sc.queries[:, idx])
+    # template projection (Eq. 2): every template vertex onto the rebuilt varying target
+    tv, tf = sc.target(71)
+    tb = mg.lbvh_build(dev(tv, device), dev(tf, device))
+    proj = mg.closest_point_query(tb, dev(tv, device), dev(sc.verts0, device))
+    idx = np.random.default_rng(51).choice(sc.n_verts, 1500, replace=False)
+    sub = {k: (v[..., idx] if v is not None else None) for k, v in proj.items()}
+    check_closest(sub, tv, tf, sc.verts0[:, idx])
+
+
+def test_traversal_equals_bruteforce_kernel(device):
+    import paper_2606_00444_amd as mg
+    sc = make_config(2, small=True)
+    tv, tf = sc.target(5)
+    q = dev(sc.queries, device)
+    bvh = mg.lbvh_build(dev(tv, device), dev(tf, device))
+    a = mg.closest_point_query(bvh, dev(tv, device), q)
+    b = mg.closest_point_bruteforce(dev(tv, device), dev(tf, device), q)
+    fa, fb = host(a["face"]), host(b["face"])
+    same = fa == fb
+    assert same.mean() > 0.999
+    np.testing.assert_array_equal(host(a["dist2"])[same], host(b["dist2"])[same])
+    np.testing.assert_array_equal(host(a["point"])[:, same], host(b["point"])[:, same])
+
+
+def test_queries_on_vertices_and_far_away(device):
+    import paper_2606_00444_amd as mg
+    sc = make_config(1, small=True)
+    V = sc.verts0
+    bvh = mg.lbvh_build(dev(V, device), dev(sc.faces, device))
+    # queries exactly on vertices: distance 0 and the vertex itself
+    got = mg.closest_point_query(bvh, dev(V, device), dev(V, device))
+    assert (host(got["dist2"]) == 0).all()
+    np.testing.assert_array_equal(host(got["point"]), V)
+    check_closest(got, V, sc.faces, V)
+    far = (np.random.default_rng(52).normal(size=(3, 300)) * 100).astype(np.float32)
+    got = mg.closest_point_query(bvh, dev(V, device), dev(far, device))
+    check_closest(got, V, sc.faces, far)
+
+
+def test_max_dist2_and_empty(device):
+    import paper_2606_00444_amd as mg
+    sc = make_config(1, small=True)
+    V = sc.verts0
+    bvh = mg.lbvh_build(dev(V, device), dev(sc.faces, device))
+    q = dev(sc.queries, device)
+    got = mg.closest_point_query(bvh, dev(V, device), q, max_dist2=0.01, normal=True)
+    check_closest(got, V, sc.faces, sc.queries, max_dist2=0.01)
+    e = mg.closest_point_query(bvh, dev(V, device), torch.empty(3, 0, device=device))
+    assert e["face"].numel() == 0
+
+
+@pytest.mark.parametrize("nf", [1, 2, 3])
+def test_tiny_meshes(device, nf):
+    import paper_2606_00444_amd as mg
+    rng = np.random.default_rng(60 + nf)
+    V = rng.normal(size=(3, 3 * nf)).astype(np.float32)
+    F = np.arange(3 * nf, dtype=np.int32).reshape(nf, 3).T.copy()
+    q = rng.normal(size=(3, 500)).astype(np.float32) * 2
+    bvh = mg.lbvh_build(dev(V, device), dev(F, device))
+    got = mg.closest_point_query(bvh, dev(V, device), dev(q, device), normal=True)
+    check_closest(got, V, F, q)
+
+
+def test_nearest_point_query(device):
+    import paper_2606_00444_amd as mg
+    rng = np.random.default_rng(70)
+    P = rng.random((3, 30000)).astype(np.float32)
+    Q = rng.random((3, 5000)).astype(np.float32)
+    bvh = mg.lbvh_build(dev(P, device), None)
+    idx, d2 = mg.nearest_point_query(bvh, dev(P, device), dev(Q, device))
+    ri, rd = oc.nearest_points(Q, P)
+    idx = host(idx)
+    d_dev = ((P[:, idx].astype(np.float64) - Q) ** 2).sum(0)
+    assert (np.sqrt(d_dev) <= np.sqrt(rd) + 1e-5 * np.maximum(np.sqrt(rd), 0.1)).all()
+    assert (idx == ri).mean() > 0.999
+    assert_positions(np.sqrt(host(d2)), np.sqrt(rd), 1.0, "nn distance")
+
+
+def test_c5_large_sampled(device):
+    import paper_2606_00444_amd as mg
+    sc = make_config(5)
+    F = dev(sc.faces, device)
+    bvh = mg.lbvh_build(dev(sc.verts0, device), F)
+    V = sc.frames([37])[0]
+    Vd = dev(V, device)
+    mg.lbvh_refit(bvh, Vd)
+    got = mg.closest_point_query(bvh, Vd, dev(sc.queries, device))
+    idx = np.random.default_rng(80).choice(sc.queries.shape[1], 48, replace=False)
+    sub = {k: (v[..., idx] if v is not None else None) for k, v in got.items()}
+    check_closest(sub, V, sc.faces, sc.queries[:, idx])
+    # every query got a face and a finite distance
+    assert (host(got["face"]) >= 0).all()
+    assert np.isfinite(host(got["dist2"])).all()
