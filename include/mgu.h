@@ -141,13 +141,18 @@ mg_status mg_mesh_gaussian_update_backward(const float *verts, int32_t n_verts, 
  *   leaf_faces  int32  [3][n]    vertex ids of each leaf's face (triangles only)
  *   leaf_parent int32  [n]       (parent << 1) | slot, -1 when n == 1
  *   node_parent int32  [n-1]     (parent << 1) | slot, -1 for the root (node 0)
- *   nodes       float4 [n-1][4]  per internal node, slot 0 = left child,
- *                                slot 1 = right child, each two float4:
- *                                (lo.x, lo.y, lo.z, ref) (hi.x, hi.y, hi.z, aux)
+ *   nodes       float4 [n-1][6]  per internal node, slot 0 = left child (float4
+ *                                0..2), slot 1 = right child (float4 3..5):
+ *                                internal child: (lo.xyz, ref) (hi.xyz, 0) (unused)
+ *                                leaf triangle:  (v0.xyz, ref) (v1.xyz, id) (v2.xyz, 0)
+ *                                leaf point:     (p.xyz, ref)  (p.xyz, id)  (unused)
  *                                ref (int bits): >= 0 internal node, < 0 leaf ~ref;
- *                                aux (int bits): original primitive id of a leaf
- *                                child, 0 for an internal child
- *   counters    uint32 [n-1]     refit arrival counters (zero between calls)
+ *                                id: original primitive id.  A leaf's box is the
+ *                                min/max of its vertices; refit rewrites all of it.
+ *   node_aux    int32  [n-1]     refit schedule: index among the "top" nodes (whose
+ *                                leaf range crosses a refit chunk boundary), or -1
+ *   top_nodes   int32  [n]       the top nodes (header.n_top of them)
+ *   top_scratch uint32 [7][n]    second-phase refit scratch when n_top is large
  * ---------------------------------------------------------------------- */
 
 typedef struct mg_lbvh_header {
@@ -163,7 +168,9 @@ typedef struct mg_lbvh_header {
     float quant_scale[3];
     uint32_t bounds_enc[6];/* build scratch: order-preserving encodings of lo/hi */
     uint32_t tile_counter[4];
-    int32_t reserved[12];
+    int32_t chunk_log2;    /* refit chunk: 2^chunk_log2 consecutive leaves per workgroup */
+    int32_t n_top;         /* number of top nodes */
+    int32_t reserved[10];
 } mg_lbvh_header;
 
 typedef struct mg_lbvh_layout {
@@ -175,7 +182,9 @@ typedef struct mg_lbvh_layout {
     int64_t off_leaf_parent;
     int64_t off_node_parent;
     int64_t off_nodes;
-    int64_t off_counters;
+    int64_t off_node_aux;
+    int64_t off_top_nodes;
+    int64_t off_top_scratch;
 } mg_lbvh_layout;
 
 /* Host-only: section offsets and total size of a BVH over n_prims primitives
@@ -199,6 +208,36 @@ mg_status mg_lbvh_build(const float *verts, int32_t n_verts, const int32_t *face
 mg_status mg_lbvh_refit(const float *verts, int32_t n_verts, void *bvh, size_t bvh_bytes,
                         int32_t n_prims, int32_t prim_kind, void *stream);
 
+/* Traversal choice for the query calls (NULL options = MG_QUERY_AUTO).
+ *   MG_QUERY_LANE   one query per lane, depth-first, nearer child first
+ *   MG_QUERY_BATCH  one wave per `batch` queries (1, 2, 4, 8, 16 or 32) sharing
+ *                   an LDS work stack, up to 64 node expansions per step; suits
+ *                   few queries or queries with many near-equidistant faces
+ *   MG_QUERY_AUTO   BATCH with batch 4 and seed on
+ * batch == 0 means 4.  NULL options also turn the seed on; with options given,
+ * seed is as set.  seed != 0 (BATCH only): each query first descends
+ * greedily (nearer child first) to one leaf to start from a tight bound before
+ * the wide expansion.  order (device int32 [n_queries] permutation, or NULL):
+ * queries are processed in the order order[0], order[1], ... - e.g. the prim
+ * section of a MG_PRIM_POINTS BVH built over the queries, i.e. Morton order -
+ * and every result is still written at the query's own index.  counters
+ * (device uint64 [4], or NULL): += node expansions, leaf bound tests, exact
+ * leaf tests, queries.  Results do not depend on these choices except among
+ * exact ties, which all pick the lowest original id. */
+#define MG_QUERY_AUTO  0
+#define MG_QUERY_LANE  1
+#define MG_QUERY_BATCH 2
+
+typedef struct mg_query_options {
+    int32_t kernel;
+    int32_t batch;
+    int32_t seed;
+    int32_t reserved0;
+    const int32_t *order;
+    uint64_t *counters;
+    int64_t reserved[2];
+} mg_query_options;
+
 /* ------------------------------------------------------------------------
  * Closest point on a triangle mesh (NearestSurface with barycentric
  * interpolation, Sec. 3.3 Eq. 1-2, read as the single nearest face) with the
@@ -210,12 +249,15 @@ mg_status mg_lbvh_refit(const float *verts, int32_t n_verts, void *bvh, size_t b
  *   dist2     [nq] squared distance (+inf when none)
  *   normal    [3][nq] unit normal of the face, zero if degenerate or none
  * point, bary, dist2, normal may each be NULL to skip.  max_dist2 >= 0
- * (+inf allowed).  bvh must be a MG_PRIM_TRIANGLES BVH built/refit on verts.
+ * (+inf allowed).  bvh must be a MG_PRIM_TRIANGLES BVH built/refit on verts
+ * (leaf triangles are read from the BVH, the winner's from verts).  opts: host
+ * pointer or NULL.
  * ---------------------------------------------------------------------- */
 mg_status mg_closest_point_query(const void *bvh, size_t bvh_bytes, int32_t n_prims,
                                  const float *verts, int32_t n_verts, const float *queries,
                                  int32_t n_queries, float max_dist2, int32_t *face, float *point,
-                                 float *bary, float *dist2, float *normal, void *stream);
+                                 float *bary, float *dist2, float *normal,
+                                 const mg_query_options *opts, void *stream);
 
 /* Same contract as mg_closest_point_query but tests every face for every query
  * (no BVH; for self-checks on small meshes).  faces [3][n_faces]. */
@@ -226,10 +268,11 @@ mg_status mg_closest_point_bruteforce(const float *verts, int32_t n_verts, const
 
 /* Nearest point of a MG_PRIM_POINTS BVH built over points [3][n_prims]:
  * index[q] (lowest index on exact ties, -1 if none within max_dist2) and
- * dist2[q] (+inf if none); dist2 may be NULL. */
+ * dist2[q] (+inf if none); dist2 may be NULL.  opts as for mg_closest_point_query. */
 mg_status mg_nearest_point_query(const void *bvh, size_t bvh_bytes, int32_t n_prims,
                                  const float *points, const float *queries, int32_t n_queries,
-                                 float max_dist2, int32_t *index, float *dist2, void *stream);
+                                 float max_dist2, int32_t *index, float *dist2,
+                                 const mg_query_options *opts, void *stream);
 
 /* ------------------------------------------------------------------------
  * Losses for differentiable template projection.  Chamfer distance is used
@@ -247,11 +290,12 @@ mg_status mg_mean(const float *x, int64_t n, double *out, void *ws, size_t ws_by
 /* Both nearest-neighbour directions and the two means:
  * nn_ab[i] / d_ab[i]: nearest b of a_i and its squared distance (via bvh_b,
  * a MG_PRIM_POINTS BVH over b); nn_ba / d_ba likewise via bvh_a over a;
- * out[0] = mean d_ab, out[1] = mean d_ba (device float64). */
+ * out[0] = mean d_ab, out[1] = mean d_ba (device float64).  opts as for
+ * mg_nearest_point_query (applies to both directions). */
 mg_status mg_chamfer(const float *a, int32_t na, const void *bvh_a, size_t bvh_a_bytes,
                      const float *b, int32_t nb, const void *bvh_b, size_t bvh_b_bytes,
                      int32_t *nn_ab, float *d_ab, int32_t *nn_ba, float *d_ba, double *out,
-                     void *ws, size_t ws_bytes, void *stream);
+                     void *ws, size_t ws_bytes, const mg_query_options *opts, void *stream);
 
 /* g_verts [3][n_verts] += scale * sum_q -2 w_k (y_q - c_q) on the three
  * vertices of each query's face (queries with face == -1 contribute nothing).

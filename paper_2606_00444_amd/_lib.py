@@ -20,6 +20,9 @@ STATUS = {
 }
 MG_PRIM_TRIANGLES = 0
 MG_PRIM_POINTS = 1
+MG_QUERY_AUTO = 0
+MG_QUERY_LANE = 1
+MG_QUERY_BATCH = 2
 
 
 class MguError(RuntimeError):
@@ -30,7 +33,13 @@ class MguError(RuntimeError):
 
 class LbvhLayout(ctypes.Structure):
     _fields_ = [(n, I64) for n in ("total_bytes", "off_header", "off_codes", "off_prim", "off_leaf_faces",
-                                   "off_leaf_parent", "off_node_parent", "off_nodes", "off_counters")]
+                                   "off_leaf_parent", "off_node_parent", "off_nodes", "off_node_aux",
+                                   "off_top_nodes", "off_top_scratch")]
+
+
+class QueryOptions(ctypes.Structure):
+    _fields_ = [("kernel", I32), ("batch", I32), ("seed", I32), ("reserved0", I32), ("order", P),
+                ("counters", P), ("reserved", I64 * 2)]
 
 
 # name -> (restype, argtypes); every symbol declared in include/mgu.h
@@ -46,12 +55,12 @@ PROTOTYPES = {
     "mg_lbvh_workspace_size": (I32, [I32, I32, P]),
     "mg_lbvh_build": (I32, [P, I32, P, I32, I32, P, SZ, P, SZ, P]),
     "mg_lbvh_refit": (I32, [P, I32, P, SZ, I32, I32, P]),
-    "mg_closest_point_query": (I32, [P, SZ, I32, P, I32, P, I32, F32, P, P, P, P, P, P]),
+    "mg_closest_point_query": (I32, [P, SZ, I32, P, I32, P, I32, F32, P, P, P, P, P, P, P]),
     "mg_closest_point_bruteforce": (I32, [P, I32, P, I32, P, I32, F32, P, P, P, P, P, P]),
-    "mg_nearest_point_query": (I32, [P, SZ, I32, P, P, I32, F32, P, P, P]),
+    "mg_nearest_point_query": (I32, [P, SZ, I32, P, P, I32, F32, P, P, P, P]),
     "mg_reduce_workspace_size": (I32, [I64, P]),
     "mg_mean": (I32, [P, I64, P, P, SZ, P]),
-    "mg_chamfer": (I32, [P, I32, P, SZ, P, I32, P, SZ, P, P, P, P, P, P, SZ, P]),
+    "mg_chamfer": (I32, [P, I32, P, SZ, P, I32, P, SZ, P, P, P, P, P, P, SZ, P, P]),
     "mg_point_mesh_backward": (I32, [P, I32, P, I32, P, I32, P, P, P, F32, P, P]),
     "mg_chamfer_backward": (I32, [P, I32, P, I32, P, P, F32, F32, P, P]),
     "mg_adam_step": (I32, [P, P, P, P, I64, I32, F32, F32, F32, F32, P]),

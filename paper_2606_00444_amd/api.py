@@ -12,11 +12,11 @@ import math
 import torch
 
 from . import _lib
-from ._lib import MG_PRIM_POINTS, MG_PRIM_TRIANGLES, LbvhLayout
+from ._lib import MG_PRIM_POINTS, MG_PRIM_TRIANGLES, MG_QUERY_AUTO, MG_QUERY_BATCH, MG_QUERY_LANE, LbvhLayout, QueryOptions
 
 __all__ = [
     "frame_index", "vertex_buffer_update", "mesh_gaussian_update", "mesh_gaussian_update_backward",
-    "LBVH", "lbvh_bytes", "lbvh_workspace_bytes", "lbvh_build", "lbvh_refit", "closest_point_query", "closest_point_bruteforce",
+    "LBVH", "query_order", "lbvh_bytes", "lbvh_workspace_bytes", "lbvh_build", "lbvh_refit", "closest_point_query", "closest_point_bruteforce",
     "nearest_point_query", "mean", "chamfer", "point_mesh_backward", "chamfer_backward", "adam_step",
     "validate_indices", "validate_finite", "version", "check_device",
 ]
@@ -181,6 +181,32 @@ def lbvh_refit(bvh, verts):
     return bvh
 
 
+def _opts(kernel, batch, seed=False, order=None, counters=None):
+    """ctypes options for the traversal ("auto" | "lane" | "batch"); None when automatic."""
+    if kernel in (None, "auto") and not batch and not seed and order is None and counters is None:
+        return None
+    k = {"auto": MG_QUERY_AUTO, None: MG_QUERY_AUTO, "lane": MG_QUERY_LANE, "batch": MG_QUERY_BATCH}[kernel]
+    o = QueryOptions()
+    o.kernel = k
+    o.batch = int(batch or 0)
+    o.seed = int(bool(seed))
+    if order is not None:
+        if order.dtype != torch.int32:
+            raise TypeError("order must be int32")
+        o.order = _ptr(order)
+    if counters is not None:
+        if counters.dtype != torch.int64 or counters.numel() < 4:
+            raise TypeError("counters must be int64 [4]")
+        o.counters = _ptr(counters)
+    return ctypes.byref(o)
+
+
+def query_order(queries):
+    """Morton order of query points [3][Q] (int32 permutation), from a point LBVH build."""
+    bvh = lbvh_build(_f32(queries, 3, "queries"), None)
+    return bvh.section("prim", torch.int32, bvh.n).clone()
+
+
 def _query_out(nq, device, point, bary, dist2, normal):
     return {
         "face": torch.empty(nq, dtype=torch.int32, device=device),
@@ -192,15 +218,19 @@ def _query_out(nq, device, point, bary, dist2, normal):
 
 
 def closest_point_query(bvh, verts, queries, max_dist2=math.inf, *, point=True, bary=True, dist2=True,
-                        normal=False, out=None):
-    """Closest point on the mesh of a triangle LBVH for every query [3][Q]."""
+                        normal=False, out=None, kernel=None, batch=0, seed=False, order=None,
+                        counters=None):
+    """Closest point on the mesh of a triangle LBVH for every query [3][Q].
+
+    kernel: None/"auto", "lane" or "batch" (batch = queries per wave) - see mg_query_options.
+    """
     if bvh.kind != MG_PRIM_TRIANGLES:
         raise ValueError("closest_point_query needs a triangle BVH")
     nq = _f32(queries, 3, "queries").shape[1]
     o = out or _query_out(nq, queries.device, point, bary, dist2, normal)
     _call("mg_closest_point_query", _ptr(bvh.buf), bvh.nbytes, bvh.n, _ptr(verts), verts.shape[1],
           _ptr(queries), nq, float(max_dist2), _ptr(o["face"]), _ptr(o["point"]), _ptr(o["bary"]),
-          _ptr(o["dist2"]), _ptr(o["normal"]), _stream())
+          _ptr(o["dist2"]), _ptr(o["normal"]), _opts(kernel, batch, seed, order, counters), _stream())
     return o
 
 
@@ -214,7 +244,8 @@ def closest_point_bruteforce(verts, faces, queries, max_dist2=math.inf, *, norma
     return o
 
 
-def nearest_point_query(bvh, points, queries, max_dist2=math.inf):
+def nearest_point_query(bvh, points, queries, max_dist2=math.inf, *, kernel=None, batch=0, seed=False,
+                        order=None, counters=None):
     """(index [Q] int32, dist2 [Q]) of the nearest point of a point LBVH."""
     if bvh.kind != MG_PRIM_POINTS:
         raise ValueError("nearest_point_query needs a point BVH")
@@ -222,7 +253,7 @@ def nearest_point_query(bvh, points, queries, max_dist2=math.inf):
     idx = torch.empty(nq, dtype=torch.int32, device=queries.device)
     d2 = torch.empty(nq, device=queries.device)
     _call("mg_nearest_point_query", _ptr(bvh.buf), bvh.nbytes, bvh.n, _ptr(points), _ptr(queries), nq,
-          float(max_dist2), _ptr(idx), _ptr(d2), _stream())
+          float(max_dist2), _ptr(idx), _ptr(d2), _opts(kernel, batch, seed, order, counters), _stream())
     return idx, d2
 
 
@@ -246,7 +277,7 @@ def mean(x, out=None):
     return out
 
 
-def chamfer(a, bvh_a, b, bvh_b):
+def chamfer(a, bvh_a, b, bvh_b, *, kernel=None, batch=0, seed=False):
     """Two-sided Chamfer pieces: dict nn_ab, d_ab, nn_ba, d_ba and means [2] (float64)."""
     na, nb = a.shape[1], b.shape[1]
     dev = a.device
@@ -256,7 +287,7 @@ def chamfer(a, bvh_a, b, bvh_b):
     ws = _rws(dev)
     _call("mg_chamfer", _ptr(_f32(a, 3)), na, _ptr(bvh_a.buf), bvh_a.nbytes, _ptr(_f32(b, 3)), nb, _ptr(bvh_b.buf),
           bvh_b.nbytes, _ptr(o["nn_ab"]), _ptr(o["d_ab"]), _ptr(o["nn_ba"]), _ptr(o["d_ba"]), _ptr(o["means"]),
-          _ptr(ws), ws.numel(), _stream())
+          _ptr(ws), ws.numel(), _opts(kernel, batch, seed), _stream())
     return o
 
 

@@ -1,0 +1,119 @@
+"""Autotuner for the closest-point / nearest-point traversal.
+
+For a given BVH and query set it times every candidate traversal (one query per
+lane, or one wave per batch of 1-16 queries with or without the greedy seed
+descent; in the given query order or a supplied one such as Morton order), each
+as a HIP graph of back-to-back launches bracketed by HIP events
+on the launch stream, and keeps the fastest.  Choices are cached per device,
+primitive kind, primitive count, query count and ordering in a JSON file
+(MGU_AUTOTUNE_CACHE, default ~/.cache/mgu_autotune.json), so a workload is
+tuned once.  Results never depend on the choice except among exact ties.
+"""
+
+import json
+import os
+
+import torch
+
+from . import api
+
+CANDIDATES = [("lane", 0, False)] + [("batch", b, s) for b in (1, 2, 4, 8, 16) for s in (False, True)]
+
+
+def _cache_path():
+    return os.environ.get("MGU_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "mgu_autotune.json"))
+
+
+def _load_cache():
+    try:
+        with open(_cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store_cache(cache):
+    path = _cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + f".tmp{os.getpid()}"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+
+
+def _graph_time(fn, reps):
+    """Average milliseconds of fn over a HIP graph of `reps` launches."""
+    fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(reps):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    g.replay()
+    z.record(s)
+    torch.cuda.synchronize()
+    return a.elapsed_time(z) / reps
+
+
+def _key(kind, bvh, queries, ordered, extra=""):
+    dev = torch.cuda.get_device_properties(queries.device)
+    arch = getattr(dev, "gcnArchName", dev.name)
+    return f"{arch}|{kind}|n={bvh.n}|q={queries.shape[1]}|ordered={int(ordered)}{extra}"
+
+
+def _tune(key, run, orders, candidates, reps, use_cache):
+    cache = _load_cache() if use_cache else {}
+    if key in cache:
+        return cache[key]
+    timings = {}
+    for oname, order in orders.items():
+        for kernel, batch, seed in candidates or CANDIDATES:
+            timings[f"{kernel}/{batch}/{int(seed)}/{oname}"] = _graph_time(
+                lambda: run(kernel=kernel, batch=batch, seed=seed, order=order), reps)
+    best = min(timings, key=timings.get)
+    k, b, s, o = best.split("/")
+    res = {"kernel": k, "batch": int(b), "seed": bool(int(s)), "order": o, "ms": timings[best], "timings": timings}
+    if use_cache:
+        cache = _load_cache()
+        cache[key] = res
+        _store_cache(cache)
+    return res
+
+
+def tune_closest(bvh, verts, queries, *, order=None, normal=False, reps=5, use_cache=True, candidates=None):
+    """Best traversal options for mg_closest_point_query on this BVH and query set.
+
+    order: an optional processing order to consider besides the given one (e.g.
+    query_order(queries)); the result's "order" is "given" or "order".  Returns
+    {"kernel", "batch", "seed", "order", "ms", "timings"}; options(res, order)
+    gives the keyword arguments for closest_point_query.
+    """
+    orders = {"given": None} if order is None else {"given": None, "order": order}
+    key = _key("closest", bvh, queries, order is not None, f"|normal={int(normal)}")
+    out = api.closest_point_query(bvh, verts, queries, normal=normal)
+    run = lambda **kw: api.closest_point_query(bvh, verts, queries, normal=normal, out=out, **kw)
+    return _tune(key, run, orders, candidates, reps, use_cache)
+
+
+def tune_nearest(bvh, points, queries, *, order=None, reps=5, use_cache=True, candidates=None):
+    """Best traversal options for mg_nearest_point_query (same contract as tune_closest)."""
+    orders = {"given": None} if order is None else {"given": None, "order": order}
+    key = _key("nearest", bvh, queries, order is not None)
+    run = lambda **kw: api.nearest_point_query(bvh, points, queries, **kw)
+    return _tune(key, run, orders, candidates, reps, use_cache)
+
+
+def options(res, order=None):
+    """Keyword arguments of a tuning result for the query calls (order: the candidate order tensor)."""
+    kw = {"kernel": res["kernel"], "batch": res["batch"], "seed": res["seed"]}
+    if res.get("order") == "order":
+        kw["order"] = order
+    return kw

@@ -14,11 +14,18 @@
 //   sort     4 passes of a stable LSD radix sort of (code, id): one kernel per
 //            pass, tiles ranked with wave64 ballots (match masks over the 8
 //            digit bits), global digit offsets by decoupled look-back
-//   tree     Karras radix tree per internal node + leaf permutation of faces
-//   refit    bottom-up boxes with one arrival counter per internal node
+//   tree     Karras radix tree per internal node + leaf permutation of faces;
+//            marks the "top" nodes whose leaf range crosses a refit chunk
+//   refit    two phases.  Internal nodes of a Karras tree cover contiguous leaf
+//            ranges, so every node whose range lies inside one chunk of
+//            2^chunk_log2 leaves is refit by the workgroup owning that chunk,
+//            with arrival counters in LDS (workgroup scope, no cross-XCD
+//            traffic).  The few top nodes are then finished by one workgroup,
+//            again with LDS counters and LDS atomic min/max accumulators.
 //
-// Node records are child-centric (two child boxes per internal node, 64 B) so
-// a traversal step reads one record.
+// Node records are child-centric (96 B: both children's boxes, or a leaf
+// child's triangle itself) so a traversal step reads one record and a leaf
+// test needs no further gathers.
 #include "mgu_internal.hpp"
 
 namespace mgu {
@@ -44,10 +51,20 @@ inline mg_lbvh_layout make_layout(int64_t n, int kind) {
     L.off_leaf_faces = o;  o += align256(kind == MG_PRIM_TRIANGLES ? 12 * n : 0);
     L.off_leaf_parent = o; o += align256(4 * n);
     L.off_node_parent = o; o += align256(4 * m);
-    L.off_nodes = o;       o += align256(64 * m);
-    L.off_counters = o;    o += align256(4 * m);
+    L.off_nodes = o;       o += align256(96 * m);
+    L.off_node_aux = o;    o += align256(4 * m);
+    L.off_top_nodes = o;   o += align256(4 * n);
+    L.off_top_scratch = o; o += align256(28 * n);
     L.total_bytes = o;
     return L;
+}
+
+// Refit chunk: the smallest power of two >= 256 leaves that gives at most
+// about 256 chunks (one workgroup each), capped at 4096 leaves.
+inline int chunk_log2_for(int64_t n) {
+    int c = 8;
+    while ((int64_t(1) << c) * 256 < n && c < 12) ++c;
+    return c;
 }
 
 struct WsLayout {
@@ -77,7 +94,7 @@ inline T *at(void *base, int64_t off) {
 // ------------------------------------------------------------------ kernels
 
 __global__ void build_init_kernel(mg_lbvh_header *hdr, uint32_t *hist, uint32_t *lookback,
-                                  int64_t n_lookback, int n, int kind) {
+                                  int64_t n_lookback, int n, int kind, int chunk_log2) {
     const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     if (hist != nullptr)          // no sort scratch when there are no primitives
@@ -93,6 +110,8 @@ __global__ void build_init_kernel(mg_lbvh_header *hdr, uint32_t *hist, uint32_t 
             hdr->bounds_enc[3 + k] = 0u;        // running max
         }
         for (int k = 0; k < 4; ++k) hdr->tile_counter[k] = 0;
+        hdr->chunk_log2 = chunk_log2;
+        hdr->n_top = 0;
     }
 }
 
@@ -359,7 +378,10 @@ __global__ __launch_bounds__(256) void hierarchy_kernel(const uint32_t *__restri
                                                         int32_t *__restrict__ leaf_faces,
                                                         int32_t *__restrict__ leaf_parent,
                                                         int32_t *__restrict__ node_parent,
-                                                        uint32_t *__restrict__ counters) {
+                                                        int32_t *__restrict__ node_aux,
+                                                        int32_t *__restrict__ top_nodes,
+                                                        float *__restrict__ nodes,
+                                                        mg_lbvh_header *hdr, int chunk_log2) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (faces) {
@@ -394,65 +416,182 @@ __global__ __launch_bounds__(256) void hierarchy_kernel(const uint32_t *__restri
     if (lo == gamma) leaf_parent[gamma] = tag_l; else node_parent[gamma] = tag_l;
     if (hi == gamma + 1) leaf_parent[gamma + 1] = tag_r; else node_parent[gamma + 1] = tag_r;
     if (i == 0) node_parent[0] = -1;
-    counters[i] = 0;
+    // child references live in the records' first .w word of each slot; the refit
+    // rewrites the same values, so they are valid before any box exists
+    nodes[24 * i + 3] = __int_as_float(static_cast<int32_t>(lo == gamma ? ~gamma : gamma));
+    nodes[24 * i + 15] = __int_as_float(static_cast<int32_t>(hi == gamma + 1 ? ~(gamma + 1) : gamma + 1));
+    // top node: its leaf range crosses a chunk boundary (slot order is irrelevant)
+    if ((lo >> chunk_log2) != (hi >> chunk_log2)) {
+        const int32_t t = static_cast<int32_t>(atomicAdd(reinterpret_cast<uint32_t *>(&hdr->n_top), 1u));
+        top_nodes[t] = static_cast<int32_t>(i);
+        node_aux[i] = t;
+    } else {
+        node_aux[i] = -1;
+    }
 }
 
 struct RefitArgs {
     const float *verts; int64_t nv;
-    const int32_t *leaf_faces; const int32_t *prim;
+    const int32_t *leaf_faces;    // [3][n] or nullptr for points
+    const int32_t *prim;
     const int32_t *leaf_parent; const int32_t *node_parent;
-    float4 *nodes; uint32_t *counters; mg_lbvh_header *hdr;
+    float4 *nodes;                // [n-1][6]
+    const int32_t *node_aux; const int32_t *top_nodes;
+    uint32_t *top_scratch;        // [7][n]: counts, then 6 box planes (large n_top only)
+    mg_lbvh_header *hdr;
     int64_t n;
+    int chunk_log2;
 };
 
-// Bottom-up refit: each leaf writes its box into its parent's record and bumps
-// the parent's arrival counter; the second arrival (acquire/release at agent
-// scope, so boxes written on another XCD are visible) merges the sibling box
-// and climbs.  Counters are reset by the second arrival, so they are zero
-// again when the kernel ends.
-__global__ __launch_bounds__(256) void refit_kernel(RefitArgs a) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
-    f3 lo, hi;
-    const int32_t p0 = a.prim[i];
-    if (a.leaf_faces) {
-        const f3 x = load3(a.verts, a.nv, a.leaf_faces[i]);
-        const f3 y = load3(a.verts, a.nv, a.leaf_faces[a.n + i]);
-        const f3 z = load3(a.verts, a.nv, a.leaf_faces[2 * a.n + i]);
-        lo = fmin3(fmin3(x, y), z);
-        hi = fmax3(fmax3(x, y), z);
+constexpr int kTopLds = 2048;     // top nodes handled with LDS accumulators
+
+__device__ __forceinline__ void write_root(mg_lbvh_header *hdr, f3 lo, f3 hi) {
+    hdr->root_lo[0] = lo.x; hdr->root_lo[1] = lo.y; hdr->root_lo[2] = lo.z;
+    hdr->root_hi[0] = hi.x; hdr->root_hi[1] = hi.y; hdr->root_hi[2] = hi.z;
+}
+
+// Box of the child stored in a record slot: a leaf triangle's vertices or a
+// box (internal children and points store lo/hi in the first two float4).
+template <bool kTri>
+__device__ __forceinline__ void slot_box(const float4 *slot, f3 &lo, f3 &hi) {
+    const float4 f0 = slot[0], f1 = slot[1];
+    const f3 a = f3{f0.x, f0.y, f0.z}, b = f3{f1.x, f1.y, f1.z};
+    if (kTri && __float_as_int(f0.w) < 0) {
+        const float4 f2 = slot[2];
+        const f3 c = f3{f2.x, f2.y, f2.z};
+        lo = fmin3(fmin3(a, b), c);
+        hi = fmax3(fmax3(a, b), c);
     } else {
-        lo = hi = load3(a.verts, a.nv, p0);
+        lo = a;
+        hi = b;
     }
-    int32_t tag = a.leaf_parent[i];
-    int32_t ref = ~static_cast<int32_t>(i), aux = p0;
-    // A valid tree is at most 62 levels deep; the cap and the range check only
-    // turn a corrupted buffer into an error word instead of a fault or a hang.
-    for (int level = 0;; ++level) {
-        if (level > 64 || (tag >= 0 && (tag >> 1) >= a.n - 1)) {
-            atomicOr(&a.hdr->status, 4);
-            return;
+}
+
+// Phase 1: workgroup b owns leaves [b C, b C + C) and every internal node whose
+// range lies inside them.  Arrival counters live in LDS (index node - b C: a
+// local node is one end of its own range), so all synchronisation is at
+// workgroup scope.  A climb stops at the first top node; its child's data is
+// already in the top node's record for phase 2.
+template <bool kTri>
+__global__ __launch_bounds__(256) void refit_local_kernel(RefitArgs a) {
+    extern __shared__ uint32_t s_cnt[];
+    const int64_t C = int64_t(1) << a.chunk_log2;
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * C;
+    const int64_t end = base + C < a.n ? base + C : a.n;
+    for (int64_t k = threadIdx.x; k < C; k += blockDim.x) s_cnt[k] = 0;
+    __syncthreads();
+    for (int64_t i = base + threadIdx.x; i < end; i += blockDim.x) {
+        const int32_t id = a.prim[i];
+        f3 x, y, z;
+        if (kTri) {
+            x = load3(a.verts, a.nv, a.leaf_faces[i]);
+            y = load3(a.verts, a.nv, a.leaf_faces[a.n + i]);
+            z = load3(a.verts, a.nv, a.leaf_faces[2 * a.n + i]);
+        } else {
+            x = y = z = load3(a.verts, a.nv, id);
         }
-        if (tag < 0) {
-            a.hdr->root_lo[0] = lo.x; a.hdr->root_lo[1] = lo.y; a.hdr->root_lo[2] = lo.z;
-            a.hdr->root_hi[0] = hi.x; a.hdr->root_hi[1] = hi.y; a.hdr->root_hi[2] = hi.z;
-            return;
+        f3 lo = fmin3(fmin3(x, y), z), hi = fmax3(fmax3(x, y), z);
+        int32_t tag = a.leaf_parent[i];
+        if (tag < 0) {            // a single leaf is the root
+            write_root(a.hdr, lo, hi);
+            continue;
         }
-        const int32_t p = tag >> 1, slot = tag & 1;
-        float4 *rec = a.nodes + 4 * static_cast<int64_t>(p);
-        rec[2 * slot] = make_float4(lo.x, lo.y, lo.z, __int_as_float(ref));
-        rec[2 * slot + 1] = make_float4(hi.x, hi.y, hi.z, __int_as_float(aux));
-        const uint32_t old = __hip_atomic_fetch_add(a.counters + p, 1u, __ATOMIC_ACQ_REL,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-        if (old == 0) return;
-        __hip_atomic_store(a.counters + p, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const float4 s0 = rec[2 * (1 - slot)], s1 = rec[2 * (1 - slot) + 1];
-        lo = fmin3(lo, f3{s0.x, s0.y, s0.z});
-        hi = fmax3(hi, f3{s1.x, s1.y, s1.z});
-        ref = p;
-        aux = 0;
-        tag = a.node_parent[p];
+        int32_t p = tag >> 1, slot = tag & 1;
+        if (p >= a.n - 1) { atomicOr(&a.hdr->status, 4); continue; }
+        float4 *rec = a.nodes + 6 * static_cast<int64_t>(p) + 3 * slot;
+        rec[0] = make_float4(x.x, x.y, x.z, __int_as_float(~static_cast<int32_t>(i)));
+        rec[1] = make_float4(y.x, y.y, y.z, __int_as_float(id));
+        if (kTri) rec[2] = make_float4(z.x, z.y, z.z, 0.0f);
+        // a valid tree is at most 62 levels deep; the cap and range checks turn a
+        // corrupted buffer into an error word instead of a fault or a hang
+        for (int level = 0; level < 64; ++level) {
+            if (p < base || p >= end || a.node_aux[p] >= 0) break;     // top node: phase 2
+            const uint32_t old = __hip_atomic_fetch_add(&s_cnt[p - base], 1u, __ATOMIC_ACQ_REL,
+                                                        __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (old == 0) break;
+            f3 slo, shi;
+            slot_box<kTri>(a.nodes + 6 * static_cast<int64_t>(p) + 3 * (1 - slot), slo, shi);
+            lo = fmin3(lo, slo);
+            hi = fmax3(hi, shi);
+            tag = a.node_parent[p];
+            if (tag < 0) {
+                write_root(a.hdr, lo, hi);
+                break;
+            }
+            const int32_t c = p;
+            p = tag >> 1;
+            slot = tag & 1;
+            if (p >= a.n - 1) { atomicOr(&a.hdr->status, 4); break; }
+            rec = a.nodes + 6 * static_cast<int64_t>(p) + 3 * slot;
+            rec[0] = make_float4(lo.x, lo.y, lo.z, __int_as_float(c));
+            rec[1] = make_float4(hi.x, hi.y, hi.z, 0.0f);
+        }
     }
+}
+
+// Phase 2 body: cnt [T] and box planes bx[k * stride + t] either in LDS or in
+// the BVH's scratch section; one workgroup, so workgroup scope suffices.
+template <bool kTri>
+__device__ void refit_top_body(const RefitArgs &a, int T, uint32_t *cnt, uint32_t *bx, int64_t stride) {
+    constexpr uint32_t kReady = 0x80000000u;
+    for (int t = threadIdx.x; t < T; t += blockDim.x) {
+        const int32_t p = a.top_nodes[t];
+        f3 lo = f3{INFINITY, INFINITY, INFINITY}, hi = f3{-INFINITY, -INFINITY, -INFINITY};
+        uint32_t count = 0;
+        for (int slot = 0; slot < 2; ++slot) {
+            const float4 *sl = a.nodes + 6 * static_cast<int64_t>(p) + 3 * slot;
+            const int32_t ref = __float_as_int(sl[0].w);
+            if (ref >= a.n - 1 || ~ref >= a.n) { atomicOr(&a.hdr->status, 16); continue; }
+            if (ref >= 0 && a.node_aux[ref] >= 0) continue;       // a top child arrives later
+            f3 clo, chi;
+            slot_box<kTri>(sl, clo, chi);
+            lo = fmin3(lo, clo);
+            hi = fmax3(hi, chi);
+            ++count;
+        }
+        bx[0 * stride + t] = f2ord(lo.x); bx[1 * stride + t] = f2ord(lo.y); bx[2 * stride + t] = f2ord(lo.z);
+        bx[3 * stride + t] = f2ord(hi.x); bx[4 * stride + t] = f2ord(hi.y); bx[5 * stride + t] = f2ord(hi.z);
+        cnt[t] = count == 2 ? (kReady | 2u) : count;
+    }
+    __syncthreads();
+    for (int t0 = threadIdx.x; t0 < T; t0 += blockDim.x) {
+        if ((__hip_atomic_load(&cnt[t0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) & kReady) == 0) continue;
+        int t = t0;
+        for (int level = 0; level < 64; ++level) {
+            const int32_t p = a.top_nodes[t];
+            const f3 lo = f3{ord2f(bx[0 * stride + t]), ord2f(bx[1 * stride + t]), ord2f(bx[2 * stride + t])};
+            const f3 hi = f3{ord2f(bx[3 * stride + t]), ord2f(bx[4 * stride + t]), ord2f(bx[5 * stride + t])};
+            const int32_t tag = a.node_parent[p];
+            if (tag < 0) {
+                write_root(a.hdr, lo, hi);
+                break;
+            }
+            const int32_t pp = tag >> 1, slot = tag & 1;
+            float4 *rec = a.nodes + 6 * static_cast<int64_t>(pp) + 3 * slot;
+            rec[0] = make_float4(lo.x, lo.y, lo.z, __int_as_float(p));
+            rec[1] = make_float4(hi.x, hi.y, hi.z, 0.0f);
+            const int32_t tt = a.node_aux[pp];
+            if (tt < 0 || tt >= T) { atomicOr(&a.hdr->status, 8); break; }
+            __hip_atomic_fetch_min(&bx[0 * stride + tt], f2ord(lo.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_min(&bx[1 * stride + tt], f2ord(lo.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_min(&bx[2 * stride + tt], f2ord(lo.z), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_max(&bx[3 * stride + tt], f2ord(hi.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_max(&bx[4 * stride + tt], f2ord(hi.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_max(&bx[5 * stride + tt], f2ord(hi.z), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const uint32_t old = __hip_atomic_fetch_add(&cnt[tt], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (old != 1u) break;                                 // the sibling is still on its way
+            t = tt;
+        }
+    }
+}
+
+template <bool kTri>
+__global__ __launch_bounds__(1024) void refit_top_kernel(RefitArgs a) {
+    __shared__ uint32_t s_cnt[kTopLds];
+    __shared__ uint32_t s_box[6 * kTopLds];
+    const int T = a.hdr->n_top;
+    if (T <= kTopLds) refit_top_body<kTri>(a, T, s_cnt, s_box, kTopLds);
+    else refit_top_body<kTri>(a, T, a.top_scratch, a.top_scratch + a.n, a.n);
 }
 
 mg_status check_kind(int32_t kind) {
@@ -468,10 +607,25 @@ mg_status launch_refit(const float *verts, int64_t nv, void *bvh, int64_t n, int
     a.leaf_parent = at<int32_t>(bvh, L.off_leaf_parent);
     a.node_parent = at<int32_t>(bvh, L.off_node_parent);
     a.nodes = at<float4>(bvh, L.off_nodes);
-    a.counters = at<uint32_t>(bvh, L.off_counters);
+    a.node_aux = at<int32_t>(bvh, L.off_node_aux);
+    a.top_nodes = at<int32_t>(bvh, L.off_top_nodes);
+    a.top_scratch = at<uint32_t>(bvh, L.off_top_scratch);
     a.hdr = at<mg_lbvh_header>(bvh, L.off_header);
     a.n = n;
-    hipLaunchKernelGGL(refit_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, a);
+    a.chunk_log2 = chunk_log2_for(n);
+    const int64_t C = int64_t(1) << a.chunk_log2;
+    const int chunks = static_cast<int>((n + C - 1) / C);
+    const size_t lds = static_cast<size_t>(C) * sizeof(uint32_t);
+    if (kind == MG_PRIM_TRIANGLES)
+        hipLaunchKernelGGL(refit_local_kernel<true>, dim3(chunks), dim3(256), lds, s, a);
+    else
+        hipLaunchKernelGGL(refit_local_kernel<false>, dim3(chunks), dim3(256), lds, s, a);
+    if (n > C) {   // otherwise the whole tree is one chunk and phase 1 reached the root
+        if (kind == MG_PRIM_TRIANGLES)
+            hipLaunchKernelGGL(refit_top_kernel<true>, dim3(1), dim3(1024), 0, s, a);
+        else
+            hipLaunchKernelGGL(refit_top_kernel<false>, dim3(1), dim3(1024), 0, s, a);
+    }
     return launch_status();
 }
 
@@ -513,7 +667,7 @@ extern "C" mg_status mg_lbvh_build(const float *verts, int32_t n_verts, const in
     uint32_t *lookback = n ? at<uint32_t>(ws, W.lookback) : nullptr;
     const int64_t n_lookback = 4 * 256 * W.tiles;
     hipLaunchKernelGGL(build_init_kernel, dim3(n_lookback > 65536 ? 256 : 16), dim3(256), 0, s, hdr,
-                       hist, lookback, n_lookback, n_prims, prim_kind);
+                       hist, lookback, n_lookback, n_prims, prim_kind, chunk_log2_for(n_prims));
     if (launch_status() != MG_OK) return MG_ERR_HIP;
     if (n == 0) return MG_OK;
     const int32_t *fz = prim_kind == MG_PRIM_TRIANGLES ? faces : nullptr;
@@ -538,7 +692,8 @@ extern "C" mg_status mg_lbvh_build(const float *verts, int32_t n_verts, const in
     }
     hipLaunchKernelGGL(hierarchy_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, codes, prim, n, fz,
                        fz ? at<int32_t>(bvh, L.off_leaf_faces) : nullptr, at<int32_t>(bvh, L.off_leaf_parent),
-                       at<int32_t>(bvh, L.off_node_parent), at<uint32_t>(bvh, L.off_counters));
+                       at<int32_t>(bvh, L.off_node_parent), at<int32_t>(bvh, L.off_node_aux),
+                       at<int32_t>(bvh, L.off_top_nodes), at<float>(bvh, L.off_nodes), hdr, chunk_log2_for(n));
     if (launch_status() != MG_OK) return MG_ERR_HIP;
     return launch_refit(verts, n_verts, bvh, n, prim_kind, s);
 }

@@ -169,14 +169,14 @@ extern "C" mg_status mg_mean(const float *x, int64_t n, double *out, void *ws, s
 extern "C" mg_status mg_chamfer(const float *a, int32_t na, const void *bvh_a, size_t bvh_a_bytes, const float *b,
                                 int32_t nb, const void *bvh_b, size_t bvh_b_bytes, int32_t *nn_ab, float *d_ab,
                                 int32_t *nn_ba, float *d_ba, double *out, void *ws, size_t ws_bytes,
-                                void *stream) {
+                                const mg_query_options *opts, void *stream) {
     if (bad_count(na) || bad_count(nb) || !out || !nn_ab || !nn_ba || !d_ab || !d_ba || !bvh_a || !bvh_b)
         return MG_ERR_INVALID_ARGUMENT;
     if ((na > 0 && !a) || (nb > 0 && !b)) return MG_ERR_INVALID_ARGUMENT;
     if (!ws || ws_bytes < sizeof(double) * kReduceMaxBlocks) return MG_ERR_WORKSPACE_TOO_SMALL;
-    mg_status st = mg_nearest_point_query(bvh_b, bvh_b_bytes, nb, b, a, na, INFINITY, nn_ab, d_ab, stream);
+    mg_status st = mg_nearest_point_query(bvh_b, bvh_b_bytes, nb, b, a, na, INFINITY, nn_ab, d_ab, opts, stream);
     if (st != MG_OK) return st;
-    st = mg_nearest_point_query(bvh_a, bvh_a_bytes, na, a, b, nb, INFINITY, nn_ba, d_ba, stream);
+    st = mg_nearest_point_query(bvh_a, bvh_a_bytes, na, a, b, nb, INFINITY, nn_ba, d_ba, opts, stream);
     if (st != MG_OK) return st;
     hipStream_t s = as_stream(stream);
     st = launch_mean(d_ab, na, out, ws, s);

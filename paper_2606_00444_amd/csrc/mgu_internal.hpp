@@ -57,11 +57,14 @@ __device__ __forceinline__ void store3(float *__restrict__ p, int64_t n, int64_t
 // Sec. 5.1.5).  Returns squared distance; w1, w2 are the barycentric weights of
 // b and c (weight of a = 1 - w1 - w2).  A triangle whose interior denominator
 // is not positive (zero area in float32) falls back to the nearest of its edge
-// segments, ties in the order ab, ac, bc.
+// segments, ties in the order ab, ac, bc.  Quotients use the hardware
+// reciprocal (about 1 ulp); vertex regions return the vertex exactly.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 __device__ __forceinline__ float seg_closest(f3 p, f3 a, f3 b, float &t) {
     f3 ab = b - a;
     float den = dot(ab, ab);
-    t = den > 0.0f ? dot(p - a, ab) / den : 0.0f;
+    t = den > 0.0f ? dot(p - a, ab) * rcp(den) : 0.0f;
     t = fminf(fmaxf(t, 0.0f), 1.0f);
     f3 d = p - (a + t * ab);
     return dot(d, d);
@@ -80,7 +83,7 @@ __device__ __forceinline__ float tri_closest(f3 p, f3 a, f3 b, f3 c, float &w1, 
             w1 = 1.0f; w2 = 0.0f;
         } else if (vc <= 0.0f && d1 >= 0.0f && d3 <= 0.0f) {
             float den = d1 - d3;
-            w1 = den != 0.0f ? d1 / den : 0.0f; w2 = 0.0f;
+            w1 = den != 0.0f ? d1 * rcp(den) : 0.0f; w2 = 0.0f;
         } else {
             f3 cp = p - c;
             float d5 = dot(ab, cp), d6 = dot(ac, cp);
@@ -90,15 +93,16 @@ __device__ __forceinline__ float tri_closest(f3 p, f3 a, f3 b, f3 c, float &w1, 
                 w1 = 0.0f; w2 = 1.0f;
             } else if (vb <= 0.0f && d2 >= 0.0f && d6 <= 0.0f) {
                 float den = d2 - d6;
-                w1 = 0.0f; w2 = den != 0.0f ? d2 / den : 0.0f;
+                w1 = 0.0f; w2 = den != 0.0f ? d2 * rcp(den) : 0.0f;
             } else if (va <= 0.0f && (d4 - d3) >= 0.0f && (d5 - d6) >= 0.0f) {
                 float den = (d4 - d3) + (d5 - d6);
-                float t = den != 0.0f ? (d4 - d3) / den : 0.0f;
+                float t = den != 0.0f ? (d4 - d3) * rcp(den) : 0.0f;
                 w1 = 1.0f - t; w2 = t;
             } else {
                 float den = va + vb + vc;
                 if (den > 0.0f) {
-                    w1 = vb / den; w2 = vc / den;
+                    float r = rcp(den);
+                    w1 = vb * r; w2 = vc * r;
                 } else {
                     float t, best = seg_closest(p, a, b, t);
                     w1 = t; w2 = 0.0f;

@@ -76,11 +76,22 @@ def decode_bvh(bvh):
     out["n_prims"], out["status"] = int(hdr_i[0]), int(hdr_i[2])
     root = np.concatenate([hdr[4:7], hdr[8:11]]).astype(np.float64)
     out["root_box"] = root
-    nodes = host(bvh.section("nodes", torch.float32, 16 * m)).reshape(m, 2, 2, 4)   # [node][slot][lo|hi][xyzw]
+    nodes = host(bvh.section("nodes", torch.float32, 24 * m)).reshape(m, 2, 3, 4)   # [node][slot][f4][xyzw]
     ints = nodes.view(np.int32)
     out["child"] = np.stack([ints[:, 0, 0, 3], ints[:, 1, 0, 3]]) if m else np.zeros((2, 0), np.int32)
     out["aux"] = np.stack([ints[:, 0, 1, 3], ints[:, 1, 1, 3]]) if m else np.zeros((2, 0), np.int32)
-    slot_box = np.concatenate([nodes[:, :, 0, :3], nodes[:, :, 1, :3]], axis=2).astype(np.float64)  # [m][2][6]
+    # box of the child in each slot: a leaf triangle's min/max, else (lo, hi) of the first two float4
+    xyz = nodes[:, :, :, :3].astype(np.float64)                                      # [m][2][3][3]
+    leaf = (ints[:, :, 0, 3] < 0)[..., None]
+    if bvh.kind == 0:
+        lo = np.where(leaf, xyz.min(axis=2), xyz[:, :, 0])
+        hi = np.where(leaf, xyz.max(axis=2), xyz[:, :, 1])
+    else:
+        lo, hi = xyz[:, :, 0], xyz[:, :, 1]
+    slot_box = np.concatenate([lo, hi], axis=2)                                        # [m][2][6]
+    if m:
+        # leaf slots carry the primitive itself: triangle vertices (or the point) bitwise
+        out["slot_vertices"] = xyz
     ib = np.zeros((m, 6))
     lb = np.zeros((n, 6))
     if m:

@@ -66,9 +66,14 @@ def test_argument_errors_before_any_hip_call(lib):
     assert lib.mg_lbvh_build(fake, 3, None, 4, 1, fake, 1 << 20, fake, 1 << 20, None) == 1   # points: n mismatch
     assert lib.mg_lbvh_refit(fake, 5, fake, 1 << 20, 7, 1, None) == 5                   # points, n mismatch
     assert lib.mg_closest_point_query(fake, 10, 100, fake, 3, fake, 5, ctypes.c_float(-1.0), fake, None, None,
-                                      None, None, None) == 1
+                                      None, None, None, None) == 1
     assert lib.mg_closest_point_query(fake, 10, 100, fake, 3, fake, 5, ctypes.c_float(1.0), fake, None, None,
-                                      None, None, None) == 2
+                                      None, None, None, None) == 2
+    from paper_2606_00444_amd import _lib
+    bad = _lib.QueryOptions()
+    bad.kernel, bad.batch = 2, 3          # batch must be 0, 1, 2, 4, 8, 16 or 32
+    assert lib.mg_closest_point_query(fake, 1 << 20, 100, fake, 3, fake, 5, ctypes.c_float(1.0), fake, None, None,
+                                      None, None, ctypes.byref(bad), None) == 1
     assert lib.mg_vertex_buffer_update(fake, 4, 10, 4, fake, None) == 1                 # k out of range
     assert lib.mg_adam_step(fake, fake, fake, fake, 10, 0, ctypes.c_float(1e-3), ctypes.c_float(0.9),
                             ctypes.c_float(0.999), ctypes.c_float(1e-8), None) == 1

@@ -58,18 +58,30 @@ def check_closest(got, verts, faces, queries, max_dist2=math.inf):
     return ref
 
 
-def test_c1_all_queries(device):
+KERNELS = [("lane", 0), ("batch", 1), ("batch", 8), ("batch", 32), ("seeded", 4)]
+
+
+def qa(kernel, batch):
+    """Traversal keyword arguments: "seeded" is the batch kernel with a greedy first descent."""
+    if kernel == "seeded":
+        return {"kernel": "batch", "batch": batch, "seed": True}
+    return {"kernel": kernel, "batch": batch}
+
+
+@pytest.mark.parametrize("kernel,batch", KERNELS)
+def test_c1_all_queries(device, kernel, batch):
     import paper_2606_00444_amd as mg
     sc = make_config(1)
     V = sc.frames([22])[0]
     bvh = mg.lbvh_build(dev(sc.verts0, device), dev(sc.faces, device))
     Vd = dev(V, device)
     mg.lbvh_refit(bvh, Vd)
-    got = mg.closest_point_query(bvh, Vd, dev(sc.queries, device), normal=True)
+    got = mg.closest_point_query(bvh, Vd, dev(sc.queries, device), normal=True, **qa(kernel, batch))
     check_closest(got, V, sc.faces, sc.queries)
 
 
-def test_c2_collision_and_template_projection_sampled(device):
+@pytest.mark.parametrize("kernel,batch", [("lane", 0), ("batch", 8), ("seeded", 4)])
+def test_c2_collision_and_template_projection_sampled(device, kernel, batch):
     import paper_2606_00444_amd as mg
     sc = make_config(2)
     V = sc.frames([71])[0]
@@ -77,26 +89,27 @@ def test_c2_collision_and_template_projection_sampled(device):
     bvh = mg.lbvh_build(dev(sc.verts0, device), F)
     Vd = dev(V, device)
     mg.lbvh_refit(bvh, Vd)
-    got = mg.closest_point_query(bvh, Vd, dev(sc.queries, device), normal=True)
+    got = mg.closest_point_query(bvh, Vd, dev(sc.queries, device), normal=True, **qa(kernel, batch))
     idx = np.random.default_rng(50).choice(sc.queries.shape[1], 1500, replace=False)
     sub = {k: (v[..., idx] if v is not None else None) for k, v in got.items()}
     check_closest(sub, V, sc.faces, sc.queries[:, idx])
     # template projection (Eq. 2): every template vertex onto the rebuilt varying target
     tv, tf = sc.target(71)
     tb = mg.lbvh_build(dev(tv, device), dev(tf, device))
-    proj = mg.closest_point_query(tb, dev(tv, device), dev(sc.verts0, device))
+    proj = mg.closest_point_query(tb, dev(tv, device), dev(sc.verts0, device), **qa(kernel, batch))
     idx = np.random.default_rng(51).choice(sc.n_verts, 1500, replace=False)
     sub = {k: (v[..., idx] if v is not None else None) for k, v in proj.items()}
     check_closest(sub, tv, tf, sc.verts0[:, idx])
 
 
-def test_traversal_equals_bruteforce_kernel(device):
+@pytest.mark.parametrize("kernel,batch", KERNELS)
+def test_traversal_equals_bruteforce_kernel(device, kernel, batch):
     import paper_2606_00444_amd as mg
     sc = make_config(2, small=True)
     tv, tf = sc.target(5)
     q = dev(sc.queries, device)
     bvh = mg.lbvh_build(dev(tv, device), dev(tf, device))
-    a = mg.closest_point_query(bvh, dev(tv, device), q)
+    a = mg.closest_point_query(bvh, dev(tv, device), q, **qa(kernel, batch))
     b = mg.closest_point_bruteforce(dev(tv, device), dev(tf, device), q)
     fa, fb = host(a["face"]), host(b["face"])
     same = fa == fb
@@ -105,52 +118,56 @@ def test_traversal_equals_bruteforce_kernel(device):
     np.testing.assert_array_equal(host(a["point"])[:, same], host(b["point"])[:, same])
 
 
-def test_queries_on_vertices_and_far_away(device):
+@pytest.mark.parametrize("kernel,batch", KERNELS)
+def test_queries_on_vertices_and_far_away(device, kernel, batch):
     import paper_2606_00444_amd as mg
     sc = make_config(1, small=True)
     V = sc.verts0
     bvh = mg.lbvh_build(dev(V, device), dev(sc.faces, device))
     # queries exactly on vertices: distance 0 and the vertex itself
-    got = mg.closest_point_query(bvh, dev(V, device), dev(V, device))
+    got = mg.closest_point_query(bvh, dev(V, device), dev(V, device), **qa(kernel, batch))
     assert (host(got["dist2"]) == 0).all()
     np.testing.assert_array_equal(host(got["point"]), V)
     check_closest(got, V, sc.faces, V)
     far = (np.random.default_rng(52).normal(size=(3, 300)) * 100).astype(np.float32)
-    got = mg.closest_point_query(bvh, dev(V, device), dev(far, device))
+    got = mg.closest_point_query(bvh, dev(V, device), dev(far, device), **qa(kernel, batch))
     check_closest(got, V, sc.faces, far)
 
 
-def test_max_dist2_and_empty(device):
+@pytest.mark.parametrize("kernel,batch", [("lane", 0), ("batch", 4), ("seeded", 2)])
+def test_max_dist2_and_empty(device, kernel, batch):
     import paper_2606_00444_amd as mg
     sc = make_config(1, small=True)
     V = sc.verts0
     bvh = mg.lbvh_build(dev(V, device), dev(sc.faces, device))
     q = dev(sc.queries, device)
-    got = mg.closest_point_query(bvh, dev(V, device), q, max_dist2=0.01, normal=True)
+    got = mg.closest_point_query(bvh, dev(V, device), q, max_dist2=0.01, normal=True, **qa(kernel, batch))
     check_closest(got, V, sc.faces, sc.queries, max_dist2=0.01)
     e = mg.closest_point_query(bvh, dev(V, device), torch.empty(3, 0, device=device))
     assert e["face"].numel() == 0
 
 
 @pytest.mark.parametrize("nf", [1, 2, 3])
-def test_tiny_meshes(device, nf):
+@pytest.mark.parametrize("kernel,batch", [("lane", 0), ("batch", 16), ("seeded", 2)])
+def test_tiny_meshes(device, nf, kernel, batch):
     import paper_2606_00444_amd as mg
     rng = np.random.default_rng(60 + nf)
     V = rng.normal(size=(3, 3 * nf)).astype(np.float32)
     F = np.arange(3 * nf, dtype=np.int32).reshape(nf, 3).T.copy()
     q = rng.normal(size=(3, 500)).astype(np.float32) * 2
     bvh = mg.lbvh_build(dev(V, device), dev(F, device))
-    got = mg.closest_point_query(bvh, dev(V, device), dev(q, device), normal=True)
+    got = mg.closest_point_query(bvh, dev(V, device), dev(q, device), normal=True, **qa(kernel, batch))
     check_closest(got, V, F, q)
 
 
-def test_nearest_point_query(device):
+@pytest.mark.parametrize("kernel,batch", KERNELS)
+def test_nearest_point_query(device, kernel, batch):
     import paper_2606_00444_amd as mg
     rng = np.random.default_rng(70)
     P = rng.random((3, 30000)).astype(np.float32)
     Q = rng.random((3, 5000)).astype(np.float32)
     bvh = mg.lbvh_build(dev(P, device), None)
-    idx, d2 = mg.nearest_point_query(bvh, dev(P, device), dev(Q, device))
+    idx, d2 = mg.nearest_point_query(bvh, dev(P, device), dev(Q, device), **qa(kernel, batch))
     ri, rd = oc.nearest_points(Q, P)
     idx = host(idx)
     d_dev = ((P[:, idx].astype(np.float64) - Q) ** 2).sum(0)
@@ -159,7 +176,8 @@ def test_nearest_point_query(device):
     assert_positions(np.sqrt(host(d2)), np.sqrt(rd), 1.0, "nn distance")
 
 
-def test_c5_large_sampled(device):
+@pytest.mark.parametrize("kernel,batch", [("lane", 0), ("batch", 8), ("seeded", 4)])
+def test_c5_large_sampled(device, kernel, batch):
     import paper_2606_00444_amd as mg
     sc = make_config(5)
     F = dev(sc.faces, device)
@@ -167,10 +185,48 @@ def test_c5_large_sampled(device):
     V = sc.frames([37])[0]
     Vd = dev(V, device)
     mg.lbvh_refit(bvh, Vd)
-    got = mg.closest_point_query(bvh, Vd, dev(sc.queries, device))
+    got = mg.closest_point_query(bvh, Vd, dev(sc.queries, device), **qa(kernel, batch))
     idx = np.random.default_rng(80).choice(sc.queries.shape[1], 48, replace=False)
     sub = {k: (v[..., idx] if v is not None else None) for k, v in got.items()}
     check_closest(sub, V, sc.faces, sc.queries[:, idx])
     # every query got a face and a finite distance
     assert (host(got["face"]) >= 0).all()
     assert np.isfinite(host(got["dist2"])).all()
+
+
+@pytest.mark.parametrize("kernel,batch", [("lane", 0), ("batch", 8), ("seeded", 4)])
+def test_query_order_and_counters(device, kernel, batch):
+    import paper_2606_00444_amd as mg
+    sc = make_config(2, small=True)
+    V = sc.frames([9])[0]
+    Vd, F, q = dev(V, device), dev(sc.faces, device), dev(sc.queries, device)
+    bvh = mg.lbvh_build(Vd, F)
+    order = mg.query_order(q)
+    # a permutation of the query indices
+    np.testing.assert_array_equal(np.sort(host(order)), np.arange(q.shape[1]))
+    cnt = torch.zeros(4, dtype=torch.int64, device=device)
+    a = mg.closest_point_query(bvh, Vd, q, **qa(kernel, batch))
+    b = mg.closest_point_query(bvh, Vd, q, order=order, counters=cnt, **qa(kernel, batch))
+    # results land at each query's own index whatever the processing order
+    same = host(a["face"]) == host(b["face"])
+    assert same.mean() > 0.999
+    np.testing.assert_array_equal(host(a["dist2"])[same], host(b["dist2"])[same])
+    check_closest(b, V, sc.faces, sc.queries)
+    c = host(cnt)
+    assert c[3] == q.shape[1]
+    assert c[0] >= q.shape[1] and 0 < c[2] <= c[1]
+
+
+def test_autotuner_picks_a_valid_traversal(device, tmp_path, monkeypatch):
+    import paper_2606_00444_amd as mg
+    from paper_2606_00444_amd import autotune
+    monkeypatch.setenv("MGU_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    sc = make_config(1, small=True)
+    Vd, q = dev(sc.verts0, device), dev(sc.queries, device)
+    bvh = mg.lbvh_build(Vd, dev(sc.faces, device))
+    res = autotune.tune_closest(bvh, Vd, q, reps=2)
+    assert res["kernel"] in ("lane", "batch") and len(res["timings"]) == len(autotune.CANDIDATES)
+    assert res["order"] == "given"
+    assert autotune.tune_closest(bvh, Vd, q, reps=2) == res       # cached
+    got = mg.closest_point_query(bvh, Vd, q, **autotune.options(res))
+    check_closest(got, sc.verts0, sc.faces, sc.queries)
