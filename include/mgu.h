@@ -316,6 +316,81 @@ mg_status mg_adam_step(float *param, const float *grad, float *m, float *v, int6
                        float lr, float beta1, float beta2, float eps, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Batched form: many scenes x frames of uneven size in one persistent launch.
+ * Per scene-frame it does what the plain per-frame path does - Gaussian
+ * re-pose, refit of the scene's template BVH, closest-point queries - reading
+ * frame t's vertices in place from the frame store (the vertex buffer of
+ * Sec. 3.4 step 2 aliases the frame) and writing every frame's results to its
+ * own output block.  Work items are taken in index order from one atomic queue
+ * in four phases (refit chunks, Gaussian tiles, refit top nodes, query tiles);
+ * a top item waits for its scene-frame's chunks and a query item for its
+ * refit, so every wait is on earlier items held by running workgroups.
+ * Results are bitwise those of the plain calls with the same query options.
+ * ---------------------------------------------------------------------- */
+
+typedef struct mg_batch_scene {
+    const float *frames;        /* [n_frames][3][n_verts] */
+    int32_t n_frames;
+    int32_t n_verts;
+    const int32_t *faces;       /* [3][n_faces] */
+    int32_t n_faces;
+    int32_t n_gauss;
+    const int32_t *gface;       /* [n_gauss] */
+    const float *bary;          /* [2][n_gauss] */
+    const float *q_local;       /* [4][n_gauss] */
+    const float *log_scale;     /* [3][n_gauss] */
+    const float *queries;       /* [3][n_queries] */
+    int32_t n_queries;
+    int32_t reserved0;
+    const void *bvh;            /* MG_PRIM_TRIANGLES BVH built over this scene's faces: only
+                                   its topology is used, its boxes are untouched */
+    size_t bvh_bytes;
+    float *nodes;               /* out [n_frames][n_faces-1][24]: per-frame node records */
+    float *roots;               /* out [n_frames][8]: per-frame root box (lo xyz, 0, hi xyz, 0) */
+    float *mean;                /* out [n_frames][3][n_gauss] */
+    float *quat;                /* out [n_frames][4][n_gauss] or NULL */
+    float *cov;                 /* out [n_frames][6][n_gauss] or NULL */
+    int32_t *face;              /* out [n_frames][n_queries] */
+    float *point;               /* out [n_frames][3][n_queries] or NULL */
+    float *qbary;               /* out [n_frames][2][n_queries] or NULL */
+    float *dist2;               /* out [n_frames][n_queries] or NULL */
+    float *normal;              /* out [n_frames][3][n_queries] or NULL */
+} mg_batch_scene;
+
+typedef struct mg_batch_options {
+    int32_t batch;              /* queries per wave of the batch traversal: 1, 2, 4, 8, 16 (0: 4) */
+    int32_t seed;               /* greedy seed descent: 0 off, otherwise on */
+    int32_t gauss_tile;         /* Gaussians per work item, multiple of 256 (0: 2048) */
+    int32_t query_tile;         /* queries per work item, multiple of 4 * batch (0: 256) */
+    int32_t reserved[4];        /* must be 0 */
+} mg_batch_options;
+
+/* Bytes of the device plan for these scenes (scenes: host array).  Reads each
+ * scene BVH's top-node count from its device header (a synchronous copy):
+ * scenes with more than 1024 top nodes get second-phase refit scratch in the
+ * plan. */
+mg_status mg_batch_plan_size(const mg_batch_scene *scenes, int32_t n_scenes, size_t *plan_bytes);
+
+/* Validate the scenes and write the device plan (scene table, work-item
+ * counts, dependency counters).  scenes/opts are host pointers (opts may be
+ * NULL); plan is a device buffer of mg_batch_plan_size bytes.  Copies the
+ * table with the stream and synchronises it (initialisation only).  Every
+ * scene needs n_faces >= 1, n_frames >= 1 and a built BVH over exactly its
+ * faces; the BVH must not be rebuilt between plan_init and the runs. */
+mg_status mg_batch_plan_init(const mg_batch_scene *scenes, int32_t n_scenes, const mg_batch_options *opts,
+                             void *plan, size_t plan_bytes, void *stream);
+
+/* One run over all scenes x frames: a small reset kernel, then the
+ * persistent kernel.  Asynchronous; capturable in a HIP graph.  Runs on the
+ * same plan must not overlap. */
+mg_status mg_batch_run(void *plan, size_t plan_bytes, void *stream);
+
+/* Host-only: device address of the plan's int32 error word (0 = fine; a
+ * non-zero value means a dependency wait timed out or a scene's BVH does not
+ * match the plan). */
+mg_status mg_batch_status_word(void *plan, int32_t **status);
+
+/* ------------------------------------------------------------------------
  * Validation helpers (asynchronous; the result lands in a device int32).
  * ---------------------------------------------------------------------- */
 

@@ -42,6 +42,18 @@ class QueryOptions(ctypes.Structure):
                 ("counters", P), ("reserved", I64 * 2)]
 
 
+class BatchScene(ctypes.Structure):
+    _fields_ = [("frames", P), ("n_frames", I32), ("n_verts", I32), ("faces", P), ("n_faces", I32),
+                ("n_gauss", I32), ("gface", P), ("bary", P), ("q_local", P), ("log_scale", P),
+                ("queries", P), ("n_queries", I32), ("reserved0", I32), ("bvh", P), ("bvh_bytes", SZ),
+                ("nodes", P), ("roots", P), ("mean", P), ("quat", P), ("cov", P), ("face", P),
+                ("point", P), ("qbary", P), ("dist2", P), ("normal", P)]
+
+
+class BatchOptions(ctypes.Structure):
+    _fields_ = [("batch", I32), ("seed", I32), ("gauss_tile", I32), ("query_tile", I32), ("reserved", I32 * 4)]
+
+
 # name -> (restype, argtypes); every symbol declared in include/mgu.h
 PROTOTYPES = {
     "mg_status_string": (ctypes.c_char_p, [I32]),
@@ -64,6 +76,10 @@ PROTOTYPES = {
     "mg_point_mesh_backward": (I32, [P, I32, P, I32, P, I32, P, P, P, F32, P, P]),
     "mg_chamfer_backward": (I32, [P, I32, P, I32, P, P, F32, F32, P, P]),
     "mg_adam_step": (I32, [P, P, P, P, I64, I32, F32, F32, F32, F32, P]),
+    "mg_batch_plan_size": (I32, [P, I32, P]),
+    "mg_batch_plan_init": (I32, [P, I32, P, P, SZ, P]),
+    "mg_batch_run": (I32, [P, SZ, P]),
+    "mg_batch_status_word": (I32, [P, P]),
     "mg_validate_indices": (I32, [P, I64, I32, P, P]),
     "mg_validate_finite": (I32, [P, I64, P, P]),
 }

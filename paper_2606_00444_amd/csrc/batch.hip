@@ -1,0 +1,369 @@
+// Batched form: all scenes x frames in one persistent launch (gfx950).
+//
+// Work items are numbered in four phases - refit chunks, Gaussian tiles,
+// refit top nodes, query tiles - each ordered by (scene, frame, tile).  Every
+// workgroup repeatedly takes the next item from one atomic counter until the
+// queue is empty.  A top item waits (agent-scope acquire) until all chunks of
+// its scene-frame have signalled (agent-scope release), a query item until its
+// scene-frame's refit has; both depend only on items with smaller numbers,
+// which were taken earlier by workgroups that are running and never wait on
+// later items, so the queue cannot deadlock.  Waits are bounded: a timeout
+// sets the plan's error word and the item proceeds.
+//
+// Each scene-frame has its own node records and root box; topology (parents,
+// top-node schedule, leaf faces) is shared by all frames of a scene.  Frame t's
+// vertices are read in place from the frame store.
+#include "refit.hpp"
+#include "repose.hpp"
+#include "traverse.hpp"
+
+#include <cstring>
+#include <vector>
+
+namespace mgu {
+namespace {
+
+constexpr int kBlock = 256;                 // 4 waves
+constexpr int kBatchTopLds = 1024;          // top nodes per scene in the batched refit
+constexpr int kMaxScenes = 64;
+constexpr int kSpin = 1 << 22;
+
+struct PlanScene {
+    mg_batch_scene s;
+    const int32_t *leaf_faces, *prim, *leaf_parent, *node_parent, *node_aux, *top_nodes;
+    const int32_t *n_top;
+    const float4 *topo;                     // the scene BVH's records (child references)
+    uint32_t *top_scratch;                  // [n_frames][7][n_top] when n_top > kBatchTopLds, else null
+    int32_t n_top_host;                     // n_top read at plan time
+    int32_t chunk_log2;
+    int32_t sf_base;                        // index of (this scene, frame 0) among all scene-frames
+    int64_t n_chunks, g_tiles, q_tiles;     // items per frame
+    int64_t first[4];                       // first item of this scene in each phase
+};
+
+struct PlanHeader {
+    int32_t n_scenes, total_sf;
+    int32_t batch, seed, gauss_tile, query_tile, reserved0;
+    int32_t status;
+    uint32_t queue;
+    int32_t pad;
+    int64_t phase_end[4];                   // one past the last item of each phase
+    PlanScene scenes[kMaxScenes];
+};
+
+// Number of top nodes of a built BVH (read from its device header).
+inline mg_status read_n_top(const mg_batch_scene &s, int32_t &T) {
+    mg_lbvh_layout L;
+    if (mg_lbvh_layout_query(s.n_faces, MG_PRIM_TRIANGLES, &L) != MG_OK) return MG_ERR_INVALID_ARGUMENT;
+    const char *b = static_cast<const char *>(s.bvh);
+    const mg_lbvh_header *hdr = reinterpret_cast<const mg_lbvh_header *>(b + L.off_header);
+    if (hipMemcpy(&T, &hdr->n_top, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) return MG_ERR_HIP;
+    return (T >= 0 && T < s.n_faces + 1) ? MG_OK : MG_ERR_INVALID_ARGUMENT;
+}
+
+// Plan layout: header, 2 x total_sf dependency counters, then second-phase
+// refit scratch for every scene whose top nodes exceed the LDS capacity.
+inline int64_t align256b(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+inline int64_t plan_bytes_for(int64_t total_sf, int64_t scratch_words) {
+    return align256b(static_cast<int64_t>(sizeof(PlanHeader)) + 8 * total_sf) + 4 * scratch_words;
+}
+
+// Dependency counters follow the header: done_chunks[total_sf], refit_done[total_sf].
+__device__ __forceinline__ uint32_t *counters_of(PlanHeader *h) {
+    return reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(h) + sizeof(PlanHeader));
+}
+
+__global__ void batch_reset_kernel(PlanHeader *h) {
+    uint32_t *c = counters_of(h);
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < 2 * int64_t(h->total_sf);
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        c[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        h->queue = 0;
+        h->status = 0;
+    }
+}
+
+// Thread 0 waits until *ctr >= target (bounded), then every thread acquires.
+__device__ void wait_for(uint32_t *ctr, uint32_t target, int32_t *status) {
+    if (threadIdx.x == 0) {
+        int spins = 0;
+        while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > kSpin) {
+                atomicOr(status, 1);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    __syncthreads();
+    (void)__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Every thread's prior global writes are made visible device-wide, then one
+// thread releases the counter.
+__device__ void signal(uint32_t *ctr, uint32_t add) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, add, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ RefitArgs refit_args(const PlanScene &P, int64_t t, PlanHeader *h) {
+    const mg_batch_scene &s = P.s;
+    RefitArgs a;
+    a.verts = s.frames + t * 3 * static_cast<int64_t>(s.n_verts);
+    a.nv = s.n_verts;
+    a.leaf_faces = P.leaf_faces;
+    a.prim = P.prim;
+    a.leaf_parent = P.leaf_parent;
+    a.node_parent = P.node_parent;
+    a.nodes = reinterpret_cast<float4 *>(s.nodes + t * 24 * static_cast<int64_t>(s.n_faces > 1 ? s.n_faces - 1 : 0));
+    a.topo = P.topo;
+    a.node_aux = P.node_aux;
+    a.top_nodes = P.top_nodes;
+    a.top_scratch = nullptr;
+    a.root = s.roots + 8 * t;
+    a.status = &h->status;
+    a.n_top = P.n_top;
+    a.n = s.n_faces;
+    a.chunk_log2 = P.chunk_log2;
+    return a;
+}
+
+__device__ QueryArgs query_args(const PlanScene &P, int64_t t, const RefitArgs &r, int seed) {
+    const mg_batch_scene &s = P.s;
+    const int64_t nq = s.n_queries;
+    QueryArgs a;
+    a.nodes = r.nodes;
+    a.root = r.root;
+    a.leaf_faces = P.leaf_faces;
+    a.prim = P.prim;
+    a.verts = r.verts;
+    a.nv = s.n_verts;
+    a.n = s.n_faces;
+    a.queries = s.queries;
+    a.nq = nq;
+    a.maxd2 = INFINITY;
+    a.face = s.face + t * nq;
+    a.point = s.point ? s.point + t * 3 * nq : nullptr;
+    a.bary = s.qbary ? s.qbary + t * 2 * nq : nullptr;
+    a.dist2 = s.dist2 ? s.dist2 + t * nq : nullptr;
+    a.normal = s.normal ? s.normal + t * 3 * nq : nullptr;
+    a.seed = seed;
+    a.order = nullptr;
+    a.counters = nullptr;
+    return a;
+}
+
+template <int M>
+__device__ void query_tile(const QueryArgs &q, int64_t q0, int64_t q1, unsigned char *smem) {
+    WaveStack<M> *stacks = reinterpret_cast<WaveStack<M> *>(smem);
+    const int w = threadIdx.x / 64;
+    batch_loop<true, M>(q, q0 + static_cast<int64_t>(w) * M, static_cast<int64_t>(kBlock / 64) * M, q1, stacks[w]);
+}
+
+constexpr size_t kSmemBytes = 7 * 4 * kBatchTopLds > 4 * sizeof(WaveStack<16>) ? 7 * 4 * kBatchTopLds
+                                                                                 : 4 * sizeof(WaveStack<16>);
+
+__global__ __launch_bounds__(kBlock) void batch_persistent_kernel(PlanHeader *h) {
+    __shared__ __align__(16) unsigned char smem[kSmemBytes];
+    __shared__ int64_t s_item;
+    uint32_t *done_chunks = counters_of(h);
+    uint32_t *refit_done = done_chunks + h->total_sf;
+    const int64_t total = h->phase_end[3];
+    const int ns = h->n_scenes;
+    for (;;) {
+        __syncthreads();                    // smem and s_item of the previous item are free
+        if (threadIdx.x == 0) s_item = atomicAdd(&h->queue, 1u);
+        __syncthreads();
+        const int64_t item = s_item;
+        if (item >= total) break;
+        int phase = 0;
+        while (item >= h->phase_end[phase]) ++phase;
+        int si = 0;
+        while (si + 1 < ns && item >= h->scenes[si + 1].first[phase]) ++si;
+        const PlanScene &P = h->scenes[si];
+        const int64_t local = item - P.first[phase];
+        const int64_t per = phase == 0 ? P.n_chunks : phase == 1 ? P.g_tiles : phase == 2 ? 1 : P.q_tiles;
+        const int64_t t = local / per, k = local % per;
+        const int sf = P.sf_base + static_cast<int>(t);
+        const RefitArgs r = refit_args(P, t, h);
+        if (phase == 0) {
+            uint32_t *cnt = reinterpret_cast<uint32_t *>(smem);
+            refit_chunk<true>(r, k, cnt);
+            signal(&done_chunks[sf], 1u);
+        } else if (phase == 1) {
+            const mg_batch_scene &s = P.s;
+            const int64_t G = s.n_gauss;
+            Inputs in{r.verts, s.n_verts, s.faces, s.n_faces, s.gface, s.bary, s.q_local, s.log_scale, nullptr, G};
+            float *mean = s.mean + t * 3 * G;
+            float *quat = s.quat ? s.quat + t * 4 * G : nullptr;
+            float *cov = s.cov ? s.cov + t * 6 * G : nullptr;
+            const int64_t g0 = k * h->gauss_tile;
+            const int64_t g1 = g0 + h->gauss_tile < G ? g0 + h->gauss_tile : G;
+            for (int64_t g = g0 + threadIdx.x; g < g1; g += kBlock) repose_store(in, g, mean, quat, cov, nullptr);
+        } else if (phase == 2) {
+            wait_for(&done_chunks[sf], static_cast<uint32_t>(P.n_chunks), &h->status);
+            const int T = *P.n_top;
+            if (T > 0 && T <= kBatchTopLds) {
+                uint32_t *cnt = reinterpret_cast<uint32_t *>(smem);
+                refit_top_body<true>(r, T, cnt, cnt + kBatchTopLds, kBatchTopLds);
+            } else if (T > kBatchTopLds && P.top_scratch && T <= P.n_top_host) {
+                uint32_t *cnt = P.top_scratch + t * 7 * static_cast<int64_t>(P.n_top_host);
+                refit_top_body<true>(r, T, cnt, cnt + P.n_top_host, P.n_top_host);
+            } else if (T > 0) {
+                if (threadIdx.x == 0) atomicOr(&h->status, 2);
+            }
+            signal(&refit_done[sf], 1u);
+        } else {
+            wait_for(&refit_done[sf], 1u, &h->status);
+            const QueryArgs q = query_args(P, t, r, h->seed);
+            const int64_t q0 = k * h->query_tile;
+            const int64_t q1 = q0 + h->query_tile < q.nq ? q0 + h->query_tile : q.nq;
+            switch (h->batch) {
+                case 1: query_tile<1>(q, q0, q1, smem); break;
+                case 2: query_tile<2>(q, q0, q1, smem); break;
+                case 8: query_tile<8>(q, q0, q1, smem); break;
+                case 16: query_tile<16>(q, q0, q1, smem); break;
+                default: query_tile<4>(q, q0, q1, smem); break;
+            }
+        }
+    }
+}
+
+int64_t total_frames(const mg_batch_scene *scenes, int32_t n) {
+    int64_t t = 0;
+    for (int i = 0; i < n; ++i) t += scenes[i].n_frames;
+    return t;
+}
+
+}  // namespace
+}  // namespace mgu
+
+using namespace mgu;
+
+// Scratch words for the second refit phase of every scene with more top nodes than fit in LDS.
+inline mg_status scratch_words(const mg_batch_scene *scenes, int32_t n_scenes, int64_t &words) {
+    words = 0;
+    for (int i = 0; i < n_scenes; ++i) {
+        if (!scenes[i].bvh || scenes[i].n_faces < 1) return MG_ERR_INVALID_ARGUMENT;
+        int32_t T = 0;
+        const mg_status st = read_n_top(scenes[i], T);
+        if (st != MG_OK) return st;
+        if (T > kBatchTopLds) words += static_cast<int64_t>(scenes[i].n_frames) * 7 * T;
+    }
+    return MG_OK;
+}
+
+extern "C" mg_status mg_batch_plan_size(const mg_batch_scene *scenes, int32_t n_scenes, size_t *plan_bytes) {
+    if (!scenes || !plan_bytes || n_scenes < 1 || n_scenes > kMaxScenes) return MG_ERR_INVALID_ARGUMENT;
+    for (int i = 0; i < n_scenes; ++i)
+        if (scenes[i].n_frames < 1 || bad_count(scenes[i].n_faces)) return MG_ERR_INVALID_ARGUMENT;
+    int64_t words = 0;
+    const mg_status st = scratch_words(scenes, n_scenes, words);
+    if (st != MG_OK) return st;
+    *plan_bytes = static_cast<size_t>(plan_bytes_for(total_frames(scenes, n_scenes), words));
+    return MG_OK;
+}
+
+extern "C" mg_status mg_batch_plan_init(const mg_batch_scene *scenes, int32_t n_scenes, const mg_batch_options *opts,
+                                        void *plan, size_t plan_bytes, void *stream) {
+    size_t need = 0;
+    mg_status st = mg_batch_plan_size(scenes, n_scenes, &need);
+    if (st != MG_OK) return st;
+    if (!plan || plan_bytes < need) return MG_ERR_WORKSPACE_TOO_SMALL;
+    mg_batch_options o{};
+    if (opts) o = *opts;
+    const int batch = o.batch == 0 ? 4 : o.batch;
+    if (!(batch == 1 || batch == 2 || batch == 4 || batch == 8 || batch == 16)) return MG_ERR_INVALID_ARGUMENT;
+    const int gtile = o.gauss_tile == 0 ? 2048 : o.gauss_tile;
+    const int qtile = o.query_tile == 0 ? 256 : o.query_tile;
+    if (gtile <= 0 || gtile % kBlock != 0 || qtile <= 0 || qtile % (4 * batch) != 0) return MG_ERR_INVALID_ARGUMENT;
+    for (int i = 0; i < 4; ++i)
+        if (o.reserved[i] != 0) return MG_ERR_INVALID_ARGUMENT;
+    std::vector<PlanHeader> hv(1);
+    PlanHeader &h = hv[0];
+    std::memset(&h, 0, sizeof(PlanHeader));
+    h.n_scenes = n_scenes;
+    h.batch = batch;
+    h.seed = o.seed != 0;
+    h.gauss_tile = gtile;
+    h.query_tile = qtile;
+    int64_t sf = 0;
+    uint32_t *scratch = reinterpret_cast<uint32_t *>(static_cast<char *>(plan) +
+                                                     align256b(sizeof(PlanHeader) + 8 * total_frames(scenes, n_scenes)));
+    for (int i = 0; i < n_scenes; ++i) {
+        const mg_batch_scene &s = scenes[i];
+        if (bad_count(s.n_verts) || bad_count(s.n_faces) || bad_count(s.n_gauss) || bad_count(s.n_queries) ||
+            s.n_faces < 1 || s.n_verts < 1 || !s.frames || !s.faces || !s.bvh || !s.nodes || !s.roots)
+            return MG_ERR_INVALID_ARGUMENT;
+        if (s.n_gauss > 0 && (!s.gface || !s.bary || !s.q_local || !s.log_scale || !s.mean))
+            return MG_ERR_INVALID_ARGUMENT;
+        if (s.n_queries > 0 && (!s.queries || !s.face)) return MG_ERR_INVALID_ARGUMENT;
+        mg_lbvh_layout L;
+        mg_lbvh_layout_query(s.n_faces, MG_PRIM_TRIANGLES, &L);
+        if (s.bvh_bytes < static_cast<size_t>(L.total_bytes)) return MG_ERR_WORKSPACE_TOO_SMALL;
+        PlanScene &P = h.scenes[i];
+        P.s = s;
+        const char *b = static_cast<const char *>(s.bvh);
+        P.leaf_faces = reinterpret_cast<const int32_t *>(b + L.off_leaf_faces);
+        P.prim = reinterpret_cast<const int32_t *>(b + L.off_prim);
+        P.leaf_parent = reinterpret_cast<const int32_t *>(b + L.off_leaf_parent);
+        P.node_parent = reinterpret_cast<const int32_t *>(b + L.off_node_parent);
+        P.node_aux = reinterpret_cast<const int32_t *>(b + L.off_node_aux);
+        P.top_nodes = reinterpret_cast<const int32_t *>(b + L.off_top_nodes);
+        P.n_top = &reinterpret_cast<const mg_lbvh_header *>(b + L.off_header)->n_top;
+        P.topo = reinterpret_cast<const float4 *>(b + L.off_nodes);
+        st = read_n_top(s, P.n_top_host);
+        if (st != MG_OK) return st;
+        P.top_scratch = nullptr;
+        if (P.n_top_host > kBatchTopLds) {
+            P.top_scratch = scratch;
+            scratch += static_cast<int64_t>(s.n_frames) * 7 * P.n_top_host;
+        }
+        int c = 8;
+        while ((int64_t(1) << c) * 256 < s.n_faces && c < 12) ++c;   // the build's chunk rule
+        P.chunk_log2 = c;
+        P.sf_base = static_cast<int32_t>(sf);
+        P.n_chunks = (s.n_faces + (int64_t(1) << c) - 1) >> c;
+        P.g_tiles = (s.n_gauss + gtile - 1) / gtile;
+        P.q_tiles = (s.n_queries + qtile - 1) / qtile;
+        sf += s.n_frames;
+    }
+    h.total_sf = static_cast<int32_t>(sf);
+    int64_t item = 0;
+    for (int phase = 0; phase < 4; ++phase) {
+        for (int i = 0; i < n_scenes; ++i) {
+            PlanScene &P = h.scenes[i];
+            P.first[phase] = item;
+            const int64_t per = phase == 0 ? P.n_chunks : phase == 1 ? P.g_tiles : phase == 2 ? 1 : P.q_tiles;
+            item += per * P.s.n_frames;
+        }
+        h.phase_end[phase] = item;
+    }
+    for (int i = n_scenes; i < kMaxScenes; ++i)
+        for (int phase = 0; phase < 4; ++phase) h.scenes[i].first[phase] = h.phase_end[3];
+    hipStream_t s = as_stream(stream);
+    if (hipMemcpyAsync(plan, &h, sizeof(PlanHeader), hipMemcpyHostToDevice, s) != hipSuccess) return MG_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return MG_ERR_HIP;
+    return MG_OK;
+}
+
+extern "C" mg_status mg_batch_run(void *plan, size_t plan_bytes, void *stream) {
+    if (!plan || plan_bytes < sizeof(PlanHeader)) return MG_ERR_INVALID_ARGUMENT;
+    PlanHeader *h = static_cast<PlanHeader *>(plan);
+    hipStream_t s = as_stream(stream);
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(8), dim3(256), 0, s, h);
+    // persistent workgroups: 4 per compute unit (the kernel stops when the queue is empty)
+    hipLaunchKernelGGL(batch_persistent_kernel, dim3(4 * cus), dim3(kBlock), 0, s, h);
+    return launch_status();
+}
+
+extern "C" mg_status mg_batch_status_word(void *plan, int32_t **status) {
+    if (!plan || !status) return MG_ERR_INVALID_ARGUMENT;
+    *status = &static_cast<PlanHeader *>(plan)->status;
+    return MG_OK;
+}

@@ -8,127 +8,10 @@
 // vertex ids and nine coordinates, which hit in cache because Gaussians are
 // sorted by face.  One Gaussian per lane, SoA planes so every plane access of
 // a wave is one contiguous 256 B segment.
-#include "mgu_internal.hpp"
+#include "repose.hpp"
 
 namespace mgu {
 namespace {
-
-struct Frame {
-    f3 t, b, n;      // columns of R_f
-    float l1, ln;    // |e1|, |e1 x e2|
-    bool degenerate;
-};
-
-__device__ __forceinline__ Frame triangle_frame(f3 v0, f3 v1, f3 v2, f3 &e1, f3 &e2, f3 &nraw) {
-    Frame F;
-    e1 = v1 - v0;
-    e2 = v2 - v0;
-    nraw = cross(e1, e2);
-    F.l1 = sqrtf(dot(e1, e1));
-    F.ln = sqrtf(dot(nraw, nraw));
-    F.degenerate = (F.l1 == 0.0f) || (F.ln == 0.0f);
-    if (F.degenerate) {
-        F.t = f3{1.0f, 0.0f, 0.0f};
-        F.b = f3{0.0f, 1.0f, 0.0f};
-        F.n = f3{0.0f, 0.0f, 0.0f};   // normal output is zero; R_f uses e_z below
-    } else {
-        F.t = (1.0f / F.l1) * e1;
-        F.n = (1.0f / F.ln) * nraw;
-        F.b = cross(F.n, F.t);
-    }
-    return F;
-}
-
-// Row-major 3x3 rotation of a unit Hamilton quaternion (w, x, y, z).
-__device__ __forceinline__ void quat_matrix(float w, float x, float y, float z, float R[9]) {
-    R[0] = 1.0f - 2.0f * (y * y + z * z);
-    R[1] = 2.0f * (x * y - w * z);
-    R[2] = 2.0f * (x * z + w * y);
-    R[3] = 2.0f * (x * y + w * z);
-    R[4] = 1.0f - 2.0f * (x * x + z * z);
-    R[5] = 2.0f * (y * z - w * x);
-    R[6] = 2.0f * (x * z - w * y);
-    R[7] = 2.0f * (y * z + w * x);
-    R[8] = 1.0f - 2.0f * (x * x + y * y);
-}
-
-// Shepperd (1978): largest of (trace, R00, R11, R22) selects the component taken
-// from a square root.  Sign: w > 0, or the first non-zero of x, y, z positive.
-__device__ __forceinline__ void shepperd(const float R[9], float q[4]) {
-    const float r00 = R[0], r11 = R[4], r22 = R[8];
-    const float tr = r00 + r11 + r22;
-    int pick = 0;
-    float best = tr;
-    if (r00 > best) { best = r00; pick = 1; }
-    if (r11 > best) { best = r11; pick = 2; }
-    if (r22 > best) { best = r22; pick = 3; }
-    if (pick == 0) {
-        float w = 0.5f * sqrtf(1.0f + tr), f = 0.25f / w;
-        q[0] = w; q[1] = (R[7] - R[5]) * f; q[2] = (R[2] - R[6]) * f; q[3] = (R[3] - R[1]) * f;
-    } else if (pick == 1) {
-        float x = 0.5f * sqrtf(1.0f + r00 - r11 - r22), f = 0.25f / x;
-        q[0] = (R[7] - R[5]) * f; q[1] = x; q[2] = (R[1] + R[3]) * f; q[3] = (R[2] + R[6]) * f;
-    } else if (pick == 2) {
-        float y = 0.5f * sqrtf(1.0f - r00 + r11 - r22), f = 0.25f / y;
-        q[0] = (R[2] - R[6]) * f; q[1] = (R[1] + R[3]) * f; q[2] = y; q[3] = (R[5] + R[7]) * f;
-    } else {
-        float z = 0.5f * sqrtf(1.0f - r00 - r11 + r22), f = 0.25f / z;
-        q[0] = (R[3] - R[1]) * f; q[1] = (R[2] + R[6]) * f; q[2] = (R[5] + R[7]) * f; q[3] = z;
-    }
-    float lead = q[0];
-    if (lead == 0.0f) lead = q[1];
-    if (lead == 0.0f) lead = q[2];
-    if (lead == 0.0f) lead = q[3];
-    if (lead < 0.0f) { q[0] = -q[0]; q[1] = -q[1]; q[2] = -q[2]; q[3] = -q[3]; }
-}
-
-struct Inputs {
-    const float *verts; int64_t nv;
-    const int32_t *faces; int64_t nf;
-    const int32_t *gface; const float *bary; const float *qloc; const float *lscale;
-    const float *offset; int64_t ng;
-};
-
-struct Local {
-    f3 v0, v1, v2, e1, e2, nraw;
-    Frame F;
-    float b1, b2;
-    float Rl[9];   // R(q_l), row-major
-    float Rg[9];   // R_f R_l, row-major
-    float s2[3];
-    float off;
-};
-
-__device__ __forceinline__ void load_local(const Inputs &in, int64_t g, Local &L) {
-    const int32_t f = in.gface[g];
-    const int32_t i0 = in.faces[f], i1 = in.faces[in.nf + f], i2 = in.faces[2 * in.nf + f];
-    L.v0 = load3(in.verts, in.nv, i0);
-    L.v1 = load3(in.verts, in.nv, i1);
-    L.v2 = load3(in.verts, in.nv, i2);
-    L.F = triangle_frame(L.v0, L.v1, L.v2, L.e1, L.e2, L.nraw);
-    L.b1 = in.bary[g];
-    L.b2 = in.bary[in.ng + g];
-    float w = in.qloc[g], x = in.qloc[in.ng + g], y = in.qloc[2 * in.ng + g], z = in.qloc[3 * in.ng + g];
-    float inv = 1.0f / sqrtf(w * w + x * x + y * y + z * z);
-    quat_matrix(w * inv, x * inv, y * inv, z * inv, L.Rl);
-    // R_f columns t, b, n (identity when degenerate)
-    float Rf[9];
-    if (L.F.degenerate) {
-        Rf[0] = 1; Rf[1] = 0; Rf[2] = 0; Rf[3] = 0; Rf[4] = 1; Rf[5] = 0; Rf[6] = 0; Rf[7] = 0; Rf[8] = 1;
-    } else {
-        Rf[0] = L.F.t.x; Rf[1] = L.F.b.x; Rf[2] = L.F.n.x;
-        Rf[3] = L.F.t.y; Rf[4] = L.F.b.y; Rf[5] = L.F.n.y;
-        Rf[6] = L.F.t.z; Rf[7] = L.F.b.z; Rf[8] = L.F.n.z;
-    }
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            L.Rg[3 * r + c] = Rf[3 * r] * L.Rl[c] + Rf[3 * r + 1] * L.Rl[3 + c] + Rf[3 * r + 2] * L.Rl[6 + c];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) L.s2[k] = expf(2.0f * in.lscale[k * in.ng + g]);
-    L.off = in.offset ? in.offset[g] : 0.0f;
-}
 
 __global__ __launch_bounds__(256) void gaussian_update_kernel(Inputs in, float *__restrict__ mean,
                                                               float *__restrict__ quat,
@@ -136,39 +19,7 @@ __global__ __launch_bounds__(256) void gaussian_update_kernel(Inputs in, float *
                                                               float *__restrict__ rot) {
     const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= in.ng) return;
-    Local L;
-    load_local(in, g, L);
-    const float b0 = 1.0f - L.b1 - L.b2;
-    f3 mu = f3{b0 * L.v0.x + L.b1 * L.v1.x + L.b2 * L.v2.x, b0 * L.v0.y + L.b1 * L.v1.y + L.b2 * L.v2.y,
-               b0 * L.v0.z + L.b1 * L.v1.z + L.b2 * L.v2.z};
-    if (L.off != 0.0f) mu = mu + L.off * L.F.n;
-    const int64_t n = in.ng;
-    __builtin_nontemporal_store(mu.x, mean + g);
-    __builtin_nontemporal_store(mu.y, mean + n + g);
-    __builtin_nontemporal_store(mu.z, mean + 2 * n + g);
-    if (quat) {
-        float q[4];
-        shepperd(L.Rg, q);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) __builtin_nontemporal_store(q[k], quat + k * n + g);
-    }
-    if (cov) {
-        const float *R = L.Rg;
-        float c[6];
-        // Sigma_ij = sum_k R_ik s2_k R_jk
-        c[0] = R[0] * R[0] * L.s2[0] + R[1] * R[1] * L.s2[1] + R[2] * R[2] * L.s2[2];
-        c[1] = R[0] * R[3] * L.s2[0] + R[1] * R[4] * L.s2[1] + R[2] * R[5] * L.s2[2];
-        c[2] = R[0] * R[6] * L.s2[0] + R[1] * R[7] * L.s2[1] + R[2] * R[8] * L.s2[2];
-        c[3] = R[3] * R[3] * L.s2[0] + R[4] * R[4] * L.s2[1] + R[5] * R[5] * L.s2[2];
-        c[4] = R[3] * R[6] * L.s2[0] + R[4] * R[7] * L.s2[1] + R[5] * R[8] * L.s2[2];
-        c[5] = R[6] * R[6] * L.s2[0] + R[7] * R[7] * L.s2[1] + R[8] * R[8] * L.s2[2];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) __builtin_nontemporal_store(c[k], cov + k * n + g);
-    }
-    if (rot) {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) __builtin_nontemporal_store(L.Rg[k], rot + k * n + g);
-    }
+    repose_store(in, g, mean, quat, cov, rot);
 }
 
 __device__ __forceinline__ void atomic_add3(float *g, int64_t n, int64_t i, f3 v) {

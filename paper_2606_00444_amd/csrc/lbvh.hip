@@ -26,7 +26,7 @@
 // Node records are child-centric (96 B: both children's boxes, or a leaf
 // child's triangle itself) so a traversal step reads one record and a leaf
 // test needs no further gathers.
-#include "mgu_internal.hpp"
+#include "refit.hpp"
 
 namespace mgu {
 namespace {
@@ -430,166 +430,17 @@ __global__ __launch_bounds__(256) void hierarchy_kernel(const uint32_t *__restri
     }
 }
 
-struct RefitArgs {
-    const float *verts; int64_t nv;
-    const int32_t *leaf_faces;    // [3][n] or nullptr for points
-    const int32_t *prim;
-    const int32_t *leaf_parent; const int32_t *node_parent;
-    float4 *nodes;                // [n-1][6]
-    const int32_t *node_aux; const int32_t *top_nodes;
-    uint32_t *top_scratch;        // [7][n]: counts, then 6 box planes (large n_top only)
-    mg_lbvh_header *hdr;
-    int64_t n;
-    int chunk_log2;
-};
-
-constexpr int kTopLds = 2048;     // top nodes handled with LDS accumulators
-
-__device__ __forceinline__ void write_root(mg_lbvh_header *hdr, f3 lo, f3 hi) {
-    hdr->root_lo[0] = lo.x; hdr->root_lo[1] = lo.y; hdr->root_lo[2] = lo.z;
-    hdr->root_hi[0] = hi.x; hdr->root_hi[1] = hi.y; hdr->root_hi[2] = hi.z;
-}
-
-// Box of the child stored in a record slot: a leaf triangle's vertices or a
-// box (internal children and points store lo/hi in the first two float4).
-template <bool kTri>
-__device__ __forceinline__ void slot_box(const float4 *slot, f3 &lo, f3 &hi) {
-    const float4 f0 = slot[0], f1 = slot[1];
-    const f3 a = f3{f0.x, f0.y, f0.z}, b = f3{f1.x, f1.y, f1.z};
-    if (kTri && __float_as_int(f0.w) < 0) {
-        const float4 f2 = slot[2];
-        const f3 c = f3{f2.x, f2.y, f2.z};
-        lo = fmin3(fmin3(a, b), c);
-        hi = fmax3(fmax3(a, b), c);
-    } else {
-        lo = a;
-        hi = b;
-    }
-}
-
-// Phase 1: workgroup b owns leaves [b C, b C + C) and every internal node whose
-// range lies inside them.  Arrival counters live in LDS (index node - b C: a
-// local node is one end of its own range), so all synchronisation is at
-// workgroup scope.  A climb stops at the first top node; its child's data is
-// already in the top node's record for phase 2.
 template <bool kTri>
 __global__ __launch_bounds__(256) void refit_local_kernel(RefitArgs a) {
     extern __shared__ uint32_t s_cnt[];
-    const int64_t C = int64_t(1) << a.chunk_log2;
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * C;
-    const int64_t end = base + C < a.n ? base + C : a.n;
-    for (int64_t k = threadIdx.x; k < C; k += blockDim.x) s_cnt[k] = 0;
-    __syncthreads();
-    for (int64_t i = base + threadIdx.x; i < end; i += blockDim.x) {
-        const int32_t id = a.prim[i];
-        f3 x, y, z;
-        if (kTri) {
-            x = load3(a.verts, a.nv, a.leaf_faces[i]);
-            y = load3(a.verts, a.nv, a.leaf_faces[a.n + i]);
-            z = load3(a.verts, a.nv, a.leaf_faces[2 * a.n + i]);
-        } else {
-            x = y = z = load3(a.verts, a.nv, id);
-        }
-        f3 lo = fmin3(fmin3(x, y), z), hi = fmax3(fmax3(x, y), z);
-        int32_t tag = a.leaf_parent[i];
-        if (tag < 0) {            // a single leaf is the root
-            write_root(a.hdr, lo, hi);
-            continue;
-        }
-        int32_t p = tag >> 1, slot = tag & 1;
-        if (p >= a.n - 1) { atomicOr(&a.hdr->status, 4); continue; }
-        float4 *rec = a.nodes + 6 * static_cast<int64_t>(p) + 3 * slot;
-        rec[0] = make_float4(x.x, x.y, x.z, __int_as_float(~static_cast<int32_t>(i)));
-        rec[1] = make_float4(y.x, y.y, y.z, __int_as_float(id));
-        if (kTri) rec[2] = make_float4(z.x, z.y, z.z, 0.0f);
-        // a valid tree is at most 62 levels deep; the cap and range checks turn a
-        // corrupted buffer into an error word instead of a fault or a hang
-        for (int level = 0; level < 64; ++level) {
-            if (p < base || p >= end || a.node_aux[p] >= 0) break;     // top node: phase 2
-            const uint32_t old = __hip_atomic_fetch_add(&s_cnt[p - base], 1u, __ATOMIC_ACQ_REL,
-                                                        __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (old == 0) break;
-            f3 slo, shi;
-            slot_box<kTri>(a.nodes + 6 * static_cast<int64_t>(p) + 3 * (1 - slot), slo, shi);
-            lo = fmin3(lo, slo);
-            hi = fmax3(hi, shi);
-            tag = a.node_parent[p];
-            if (tag < 0) {
-                write_root(a.hdr, lo, hi);
-                break;
-            }
-            const int32_t c = p;
-            p = tag >> 1;
-            slot = tag & 1;
-            if (p >= a.n - 1) { atomicOr(&a.hdr->status, 4); break; }
-            rec = a.nodes + 6 * static_cast<int64_t>(p) + 3 * slot;
-            rec[0] = make_float4(lo.x, lo.y, lo.z, __int_as_float(c));
-            rec[1] = make_float4(hi.x, hi.y, hi.z, 0.0f);
-        }
-    }
-}
-
-// Phase 2 body: cnt [T] and box planes bx[k * stride + t] either in LDS or in
-// the BVH's scratch section; one workgroup, so workgroup scope suffices.
-template <bool kTri>
-__device__ void refit_top_body(const RefitArgs &a, int T, uint32_t *cnt, uint32_t *bx, int64_t stride) {
-    constexpr uint32_t kReady = 0x80000000u;
-    for (int t = threadIdx.x; t < T; t += blockDim.x) {
-        const int32_t p = a.top_nodes[t];
-        f3 lo = f3{INFINITY, INFINITY, INFINITY}, hi = f3{-INFINITY, -INFINITY, -INFINITY};
-        uint32_t count = 0;
-        for (int slot = 0; slot < 2; ++slot) {
-            const float4 *sl = a.nodes + 6 * static_cast<int64_t>(p) + 3 * slot;
-            const int32_t ref = __float_as_int(sl[0].w);
-            if (ref >= a.n - 1 || ~ref >= a.n) { atomicOr(&a.hdr->status, 16); continue; }
-            if (ref >= 0 && a.node_aux[ref] >= 0) continue;       // a top child arrives later
-            f3 clo, chi;
-            slot_box<kTri>(sl, clo, chi);
-            lo = fmin3(lo, clo);
-            hi = fmax3(hi, chi);
-            ++count;
-        }
-        bx[0 * stride + t] = f2ord(lo.x); bx[1 * stride + t] = f2ord(lo.y); bx[2 * stride + t] = f2ord(lo.z);
-        bx[3 * stride + t] = f2ord(hi.x); bx[4 * stride + t] = f2ord(hi.y); bx[5 * stride + t] = f2ord(hi.z);
-        cnt[t] = count == 2 ? (kReady | 2u) : count;
-    }
-    __syncthreads();
-    for (int t0 = threadIdx.x; t0 < T; t0 += blockDim.x) {
-        if ((__hip_atomic_load(&cnt[t0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) & kReady) == 0) continue;
-        int t = t0;
-        for (int level = 0; level < 64; ++level) {
-            const int32_t p = a.top_nodes[t];
-            const f3 lo = f3{ord2f(bx[0 * stride + t]), ord2f(bx[1 * stride + t]), ord2f(bx[2 * stride + t])};
-            const f3 hi = f3{ord2f(bx[3 * stride + t]), ord2f(bx[4 * stride + t]), ord2f(bx[5 * stride + t])};
-            const int32_t tag = a.node_parent[p];
-            if (tag < 0) {
-                write_root(a.hdr, lo, hi);
-                break;
-            }
-            const int32_t pp = tag >> 1, slot = tag & 1;
-            float4 *rec = a.nodes + 6 * static_cast<int64_t>(pp) + 3 * slot;
-            rec[0] = make_float4(lo.x, lo.y, lo.z, __int_as_float(p));
-            rec[1] = make_float4(hi.x, hi.y, hi.z, 0.0f);
-            const int32_t tt = a.node_aux[pp];
-            if (tt < 0 || tt >= T) { atomicOr(&a.hdr->status, 8); break; }
-            __hip_atomic_fetch_min(&bx[0 * stride + tt], f2ord(lo.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_min(&bx[1 * stride + tt], f2ord(lo.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_min(&bx[2 * stride + tt], f2ord(lo.z), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_max(&bx[3 * stride + tt], f2ord(hi.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_max(&bx[4 * stride + tt], f2ord(hi.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_max(&bx[5 * stride + tt], f2ord(hi.z), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            const uint32_t old = __hip_atomic_fetch_add(&cnt[tt], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (old != 1u) break;                                 // the sibling is still on its way
-            t = tt;
-        }
-    }
+    refit_chunk<kTri>(a, blockIdx.x, s_cnt);
 }
 
 template <bool kTri>
 __global__ __launch_bounds__(1024) void refit_top_kernel(RefitArgs a) {
     __shared__ uint32_t s_cnt[kTopLds];
     __shared__ uint32_t s_box[6 * kTopLds];
-    const int T = a.hdr->n_top;
+    const int T = *a.n_top;
     if (T <= kTopLds) refit_top_body<kTri>(a, T, s_cnt, s_box, kTopLds);
     else refit_top_body<kTri>(a, T, a.top_scratch, a.top_scratch + a.n, a.n);
 }
@@ -607,10 +458,14 @@ mg_status launch_refit(const float *verts, int64_t nv, void *bvh, int64_t n, int
     a.leaf_parent = at<int32_t>(bvh, L.off_leaf_parent);
     a.node_parent = at<int32_t>(bvh, L.off_node_parent);
     a.nodes = at<float4>(bvh, L.off_nodes);
+    a.topo = a.nodes;
     a.node_aux = at<int32_t>(bvh, L.off_node_aux);
     a.top_nodes = at<int32_t>(bvh, L.off_top_nodes);
     a.top_scratch = at<uint32_t>(bvh, L.off_top_scratch);
-    a.hdr = at<mg_lbvh_header>(bvh, L.off_header);
+    mg_lbvh_header *hdr = at<mg_lbvh_header>(bvh, L.off_header);
+    a.root = hdr->root_lo;
+    a.status = &hdr->status;
+    a.n_top = &hdr->n_top;
     a.n = n;
     a.chunk_log2 = chunk_log2_for(n);
     const int64_t C = int64_t(1) << a.chunk_log2;

@@ -24,126 +24,10 @@
 //           this is the lexicographic (d^2, id) minimum.  A query near the middle
 //           of a closed surface has thousands of near-equidistant faces; here they
 //           are expanded 64 at a time instead of one lane walking them serially.
-#include "mgu_internal.hpp"
-
-#include <climits>
+#include "traverse.hpp"
 
 namespace mgu {
 namespace {
-
-constexpr int kLaneBlock = 64;
-constexpr int kLdsStack = 32;
-constexpr int kMaxStack = 64;
-constexpr float kPruneSlack = 1.0f + 1.0f / 1048576.0f;
-
-constexpr int kBatchWaves = 2;          // waves per workgroup of the batch kernel
-constexpr int kBatchCap = 512;          // stack entries before the pop width shrinks
-constexpr int kBatchAlloc = kBatchCap + 64;
-
-struct QueryArgs {
-    const float4 *nodes;                // [n-1][6]
-    const mg_lbvh_header *hdr;
-    const int32_t *leaf_faces;          // [3][n] (triangles) or nullptr (points)
-    const int32_t *prim;                // [n]
-    const float *verts;                 // mesh vertices or the points
-    int64_t nv, n;
-    const float *queries;
-    int64_t nq;
-    float maxd2;
-    int32_t *face;
-    float *point, *bary, *dist2, *normal;
-    int seed;                           // batch kernel: greedy descent first
-    const int32_t *order;               // processing order (permutation) or nullptr
-    unsigned long long *counters;       // [4] statistics or nullptr
-};
-
-// Query processed in position i (order[i], or i); -1 if the order entry is out of range.
-__device__ __forceinline__ int64_t query_at(const QueryArgs &a, int64_t i) {
-    if (!a.order) return i;
-    const int32_t q = a.order[i];
-    return (q >= 0 && q < a.nq) ? q : -1;
-}
-
-__device__ __forceinline__ void add_counters(const QueryArgs &a, unsigned long long e, unsigned long long lb,
-                                             unsigned long long lx, unsigned long long nq) {
-    atomicAdd(a.counters + 0, e);
-    atomicAdd(a.counters + 1, lb);
-    atomicAdd(a.counters + 2, lx);
-    atomicAdd(a.counters + 3, nq);
-}
-
-__device__ __forceinline__ f3 xyz(float4 v) { return f3{v.x, v.y, v.z}; }
-
-// Exact squared distance to the leaf child stored in a record slot.
-template <bool kTri>
-__device__ __forceinline__ float leaf_dist2(f3 p, float4 f0, float4 f1, float4 f2) {
-    if (kTri) {
-        float w1, w2;
-        return tri_closest(p, xyz(f0), xyz(f1), xyz(f2), w1, w2);
-    }
-    const f3 d = p - xyz(f0);
-    return dot(d, d);
-}
-
-// Box distance of a leaf child (its triangle's bounds, or the point itself).
-template <bool kTri>
-__device__ __forceinline__ float leaf_box_dist2(f3 p, float4 f0, float4 f1, float4 f2) {
-    if (kTri) {
-        const f3 lo = fmin3(fmin3(xyz(f0), xyz(f1)), xyz(f2));
-        const f3 hi = fmax3(fmax3(xyz(f0), xyz(f1)), xyz(f2));
-        return box_dist2(p, lo, hi);
-    }
-    const f3 d = p - xyz(f0);
-    return dot(d, d);
-}
-
-__device__ __forceinline__ unsigned long long pack_best(float d2, int32_t id) {
-    return (static_cast<unsigned long long>(__float_as_uint(d2)) << 32) | static_cast<uint32_t>(id);
-}
-
-// Final record of query q: recomputed from the winning leaf's face (triangles)
-// or point, which the BVH stores bit-identically.
-template <bool kTri>
-__device__ void write_result(const QueryArgs &a, int64_t q, f3 p, int32_t leaf, int32_t id, float d2) {
-    if (kTri) {
-        if (leaf >= 0) {
-            const f3 A = load3(a.verts, a.nv, a.leaf_faces[leaf]);
-            const f3 B = load3(a.verts, a.nv, a.leaf_faces[a.n + leaf]);
-            const f3 C = load3(a.verts, a.nv, a.leaf_faces[2 * a.n + leaf]);
-            float w1, w2;
-            const float dd = tri_closest(p, A, B, C, w1, w2);
-            const float w0 = 1.0f - w1 - w2;
-            a.face[q] = id;
-            if (a.point)
-                store3(a.point, a.nq, q, f3{w0 * A.x + w1 * B.x + w2 * C.x, w0 * A.y + w1 * B.y + w2 * C.y,
-                                            w0 * A.z + w1 * B.z + w2 * C.z});
-            if (a.bary) { a.bary[q] = w1; a.bary[a.nq + q] = w2; }
-            if (a.dist2) a.dist2[q] = dd;
-            if (a.normal) store3(a.normal, a.nq, q, tri_normal(A, B, C));
-        } else {
-            a.face[q] = -1;
-            if (a.point) store3(a.point, a.nq, q, p);
-            if (a.bary) { a.bary[q] = 0.0f; a.bary[a.nq + q] = 0.0f; }
-            if (a.dist2) a.dist2[q] = INFINITY;
-            if (a.normal) store3(a.normal, a.nq, q, f3{0.0f, 0.0f, 0.0f});
-        }
-    } else {
-        a.face[q] = leaf >= 0 ? id : -1;
-        if (a.dist2) a.dist2[q] = leaf >= 0 ? d2 : INFINITY;
-    }
-}
-
-// Test of the single leaf of a one-primitive BVH (no records exist).
-template <bool kTri>
-__device__ __forceinline__ float single_leaf_dist2(const QueryArgs &a, f3 p) {
-    if (kTri) {
-        float w1, w2;
-        return tri_closest(p, load3(a.verts, a.nv, a.leaf_faces[0]), load3(a.verts, a.nv, a.leaf_faces[a.n]),
-                           load3(a.verts, a.nv, a.leaf_faces[2 * a.n]), w1, w2);
-    }
-    const f3 d = p - load3(a.verts, a.nv, a.prim[0]);
-    return dot(d, d);
-}
 
 // ---------------------------------------------------------------- lane kernel
 template <bool kTri>
@@ -172,8 +56,8 @@ __global__ __launch_bounds__(kLaneBlock) void traverse_lane_kernel(QueryArgs a) 
     if (a.n == 1) {
         consider(single_leaf_dist2<kTri>(a, p), a.prim[0], 0);
     } else if (a.n > 1) {
-        const f3 rlo = f3{a.hdr->root_lo[0], a.hdr->root_lo[1], a.hdr->root_lo[2]};
-        const f3 rhi = f3{a.hdr->root_hi[0], a.hdr->root_hi[1], a.hdr->root_hi[2]};
+        const f3 rlo = f3{a.root[0], a.root[1], a.root[2]};
+        const f3 rhi = f3{a.root[4], a.root[5], a.root[6]};
         int sp = 0;
         int32_t node = box_dist2(p, rlo, rhi) <= best * kPruneSlack ? 0 : -1;
         // each internal node is visited at most once in a valid tree: the step cap
@@ -216,168 +100,13 @@ __global__ __launch_bounds__(kLaneBlock) void traverse_lane_kernel(QueryArgs a) 
     if (a.counters) add_counters(a, n_exp, n_lbox, n_lex, 1);
 }
 
-// --------------------------------------------------------------- batch kernel
 template <bool kTri, int M>
 __global__ __launch_bounds__(64 * kBatchWaves) void traverse_batch_kernel(QueryArgs a) {
-    __shared__ int32_t s_node[kBatchWaves][kBatchAlloc];
-    __shared__ float s_dist[kBatchWaves][kBatchAlloc];
-    __shared__ uint8_t s_slot[kBatchWaves][kBatchAlloc];
-    __shared__ unsigned long long s_best[kBatchWaves][M];
-    __shared__ int32_t s_leaf[kBatchWaves][M];
-    __shared__ float s_q[kBatchWaves][3][M];
-    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const uint64_t lt = lanemask_lt();
+    __shared__ WaveStack<M> stacks[kBatchWaves];
+    const int w = threadIdx.x / 64;
     const int64_t waves_total = static_cast<int64_t>(gridDim.x) * kBatchWaves;
-    const unsigned long long none = pack_best(a.maxd2, INT_MAX);
-    unsigned long long n_exp = 0, n_lbox = 0, n_lex = 0, n_q = 0;   // statistics (wave-uniform)
-
-    for (int64_t qb = (static_cast<int64_t>(blockIdx.x) * kBatchWaves + w) * M; qb < a.nq; qb += waves_total * M) {
-        const int nb = static_cast<int>(a.nq - qb < M ? a.nq - qb : M);
-        const int64_t qid = lane < nb ? query_at(a, qb + lane) : -1;
-        const bool own = qid >= 0;
-        f3 p = f3{0.0f, 0.0f, 0.0f};
-        if (own) {
-            p = load3(a.queries, a.nq, qid);
-            s_q[w][0][lane] = p.x; s_q[w][1][lane] = p.y; s_q[w][2][lane] = p.z;
-            s_best[w][lane] = none;
-            s_leaf[w][lane] = -1;
-        }
-        int sp = 0;
-        if (a.n == 1) {
-            if (own) {
-                const unsigned long long c = pack_best(single_leaf_dist2<kTri>(a, p), a.prim[0]);
-                if (c < none) { s_best[w][lane] = c; s_leaf[w][lane] = 0; }
-            }
-        } else if (a.n > 1) {
-            unsigned long long seeded = none;
-            if (a.seed && own) {
-                // one greedy root-to-leaf walk (nearer internal child first) gives an
-                // upper bound before the wide expansion starts
-                int32_t cleaf = -1, node = 0;
-                for (int lvl = 0; lvl < 64 && node >= 0 && node < a.n - 1; ++lvl) {
-                    const float4 *rec = a.nodes + 6 * static_cast<int64_t>(node);
-                    const float4 l0 = rec[0], l1 = rec[1], l2 = rec[2], r0 = rec[3], r1 = rec[4], r2 = rec[5];
-                    const int32_t lref = __float_as_int(l0.w), rref = __float_as_int(r0.w);
-                    if (lref >= a.n - 1 || rref >= a.n - 1 || ~lref >= a.n || ~rref >= a.n) break;
-                    if (a.counters) {   // per-lane path: count directly
-                        const unsigned long long nl = (lref < 0) + (rref < 0);
-                        add_counters(a, 1, nl, nl, 0);
-                    }
-                    if (lref < 0) {
-                        const unsigned long long c = pack_best(leaf_dist2<kTri>(p, l0, l1, l2), __float_as_int(l1.w));
-                        if (c < seeded) { seeded = c; cleaf = ~lref; }
-                    }
-                    if (rref < 0) {
-                        const unsigned long long c = pack_best(leaf_dist2<kTri>(p, r0, r1, r2), __float_as_int(r1.w));
-                        if (c < seeded) { seeded = c; cleaf = ~rref; }
-                    }
-                    const float dl = lref >= 0 ? box_dist2(p, xyz(l0), xyz(l1)) : INFINITY;
-                    const float dr = rref >= 0 ? box_dist2(p, xyz(r0), xyz(r1)) : INFINITY;
-                    node = (lref >= 0 && dl <= dr) ? lref : (rref >= 0 ? rref : -1);
-                }
-                if (seeded < none) { s_best[w][lane] = seeded; s_leaf[w][lane] = cleaf; }
-            }
-            const f3 rlo = f3{a.hdr->root_lo[0], a.hdr->root_lo[1], a.hdr->root_lo[2]};
-            const f3 rhi = f3{a.hdr->root_hi[0], a.hdr->root_hi[1], a.hdr->root_hi[2]};
-            const float rd = own ? box_dist2(p, rlo, rhi) : INFINITY;
-            const float rb = (seeded < none ? __uint_as_float(static_cast<uint32_t>(seeded >> 32)) : a.maxd2);
-            const bool push = own && rd <= rb * kPruneSlack;
-            const uint64_t bm = __ballot(push);
-            if (push) {
-                const int pos = __popcll(bm & lt);
-                s_node[w][pos] = 0;
-                s_dist[w][pos] = rd;
-                s_slot[w][pos] = static_cast<uint8_t>(lane);
-            }
-            sp = __popcll(bm);
-        }
-        // the stack never exceeds kBatchCap + 62: a round of width k pushes at most
-        // 2k entries, widths are cut to (kBatchCap - sp) / 2, and width-1 rounds are
-        // a plain depth-first walk whose growth is bounded by the tree depth
-        // each query expands each internal node at most once: the round cap only
-        // stops a corrupted buffer from looping
-        for (int64_t round = 0; sp > 0 && round < static_cast<int64_t>(M + 1) * a.n + 64; ++round) {
-            int take = sp < 64 ? sp : 64;
-            const int room = (kBatchCap - sp) / 2;
-            if (take > room) take = room > 1 ? room : 1;
-            const bool pop = lane < take;
-            const int idx = sp - 1 - lane;
-            int32_t node = 0, slot = 0;
-            float nd = INFINITY;
-            if (pop) {
-                node = s_node[w][idx];
-                nd = s_dist[w][idx];
-                slot = s_slot[w][idx];
-            }
-            sp -= take;
-            bool act = pop && node >= 0 && node < a.n - 1;
-            unsigned long long best = act ? s_best[w][slot] : 0ull;
-            act = act && nd <= __uint_as_float(static_cast<uint32_t>(best >> 32)) * kPruneSlack;
-            float4 l0, l1, l2, r0, r1, r2;
-            int32_t lref = 0, rref = 0;
-            f3 qp = f3{0.0f, 0.0f, 0.0f};
-            unsigned long long cand = ~0ull;
-            int32_t cand_leaf = -1;
-            if (act) {
-                qp = f3{s_q[w][0][slot], s_q[w][1][slot], s_q[w][2][slot]};
-                const float4 *rec = a.nodes + 6 * static_cast<int64_t>(node);
-                l0 = rec[0]; l1 = rec[1]; l2 = rec[2]; r0 = rec[3]; r1 = rec[4]; r2 = rec[5];
-                lref = __float_as_int(l0.w);
-                rref = __float_as_int(r0.w);
-                if (lref >= a.n - 1 || rref >= a.n - 1 || ~lref >= a.n || ~rref >= a.n) act = false;
-            }
-            const float pbound = __uint_as_float(static_cast<uint32_t>(best >> 32)) * kPruneSlack;
-            const bool tl = act && lref < 0 && leaf_box_dist2<kTri>(qp, l0, l1, l2) <= pbound;
-            const bool tr = act && rref < 0 && leaf_box_dist2<kTri>(qp, r0, r1, r2) <= pbound;
-            if (a.counters) {
-                n_exp += __popcll(__ballot(act));
-                n_lbox += __popcll(__ballot(act && lref < 0)) + __popcll(__ballot(act && rref < 0));
-                n_lex += __popcll(__ballot(tl)) + __popcll(__ballot(tr));
-            }
-            if (tl) {
-                cand = pack_best(leaf_dist2<kTri>(qp, l0, l1, l2), __float_as_int(l1.w));
-                cand_leaf = ~lref;
-            }
-            if (tr) {
-                const unsigned long long c = pack_best(leaf_dist2<kTri>(qp, r0, r1, r2), __float_as_int(r1.w));
-                if (c < cand) { cand = c; cand_leaf = ~rref; }
-            }
-            if (cand != ~0ull) atomicMin(&s_best[w][slot], cand);
-            // the lane holding the minimum records its leaf (ids are unique, so at
-            // most one lane per query matches); a later round may overwrite it
-            if (cand != ~0ull && s_best[w][slot] == cand) s_leaf[w][slot] = cand_leaf;
-            best = act ? s_best[w][slot] : 0ull;
-            const float bound = __uint_as_float(static_cast<uint32_t>(best >> 32)) * kPruneSlack;
-            const float dl = (act && lref >= 0) ? box_dist2(qp, xyz(l0), xyz(l1)) : INFINITY;
-            const float dr = (act && rref >= 0) ? box_dist2(qp, xyz(r0), xyz(r1)) : INFINITY;
-            const bool pl = act && lref >= 0 && dl <= bound;
-            const bool pr = act && rref >= 0 && dr <= bound;
-            const uint64_t bl = __ballot(pl), br = __ballot(pr);
-            const int off = sp + __popcll(bl & lt) + __popcll(br & lt);
-            if (pl && pr) {
-                const bool left_near = dl <= dr;   // nearer child on top of the stack
-                s_node[w][off] = left_near ? rref : lref;
-                s_dist[w][off] = left_near ? dr : dl;
-                s_slot[w][off] = static_cast<uint8_t>(slot);
-                s_node[w][off + 1] = left_near ? lref : rref;
-                s_dist[w][off + 1] = left_near ? dl : dr;
-                s_slot[w][off + 1] = static_cast<uint8_t>(slot);
-            } else if (pl || pr) {
-                s_node[w][off] = pl ? lref : rref;
-                s_dist[w][off] = pl ? dl : dr;
-                s_slot[w][off] = static_cast<uint8_t>(slot);
-            }
-            sp += __popcll(bl) + __popcll(br);
-        }
-        if (own) {
-            const unsigned long long b = s_best[w][lane];
-            const int32_t id = static_cast<int32_t>(b & 0xffffffffull);
-            const int32_t leaf = id == INT_MAX ? -1 : s_leaf[w][lane];
-            write_result<kTri>(a, qid, p, leaf, id, __uint_as_float(static_cast<uint32_t>(b >> 32)));
-        }
-        if (a.counters) n_q += __popcll(__ballot(own));
-    }
-    if (a.counters && lane == 0) add_counters(a, n_exp, n_lbox, n_lex, n_q);
+    batch_loop<kTri, M>(a, (static_cast<int64_t>(blockIdx.x) * kBatchWaves + w) * M, waves_total * M, a.nq,
+                        stacks[w]);
 }
 
 // Every face for every query, in original face order (strict < keeps the
@@ -491,7 +220,7 @@ extern "C" mg_status mg_closest_point_query(const void *bvh, size_t bvh_bytes, i
     if (!queries || !face || (n_prims > 0 && (!verts || n_verts == 0))) return MG_ERR_INVALID_ARGUMENT;
     QueryArgs a;
     a.nodes = cat<float4>(bvh, L.off_nodes);
-    a.hdr = cat<mg_lbvh_header>(bvh, L.off_header);
+    a.root = cat<mg_lbvh_header>(bvh, L.off_header)->root_lo;
     a.leaf_faces = cat<int32_t>(bvh, L.off_leaf_faces);
     a.prim = cat<int32_t>(bvh, L.off_prim);
     a.verts = verts; a.nv = n_verts; a.n = n_prims;
@@ -513,7 +242,7 @@ extern "C" mg_status mg_nearest_point_query(const void *bvh, size_t bvh_bytes, i
     if (!queries || !index || (n_prims > 0 && !points)) return MG_ERR_INVALID_ARGUMENT;
     QueryArgs a;
     a.nodes = cat<float4>(bvh, L.off_nodes);
-    a.hdr = cat<mg_lbvh_header>(bvh, L.off_header);
+    a.root = cat<mg_lbvh_header>(bvh, L.off_header)->root_lo;
     a.leaf_faces = nullptr;
     a.prim = cat<int32_t>(bvh, L.off_prim);
     a.verts = points; a.nv = n_prims; a.n = n_prims;

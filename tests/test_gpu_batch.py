@@ -1,0 +1,125 @@
+"""The batched persistent launch equals the plain per-frame path on the same GPU."""
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import need_gpu, dev, host, decode_bvh, scale_of
+from synth import make_config
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def device():
+    return need_gpu()
+
+
+def _scenes(device, ids=(0, 3, 5), frames=4, small=True):
+    out = []
+    for i in ids:
+        sc = make_config(3, scene=i, small=small)
+        fr = sc.frames(range(frames))
+        out.append(({"frames": dev(fr, device), "faces": dev(sc.faces, device),
+                     "gface": dev(sc.binding["face"], device), "bary": dev(sc.binding["bary"], device),
+                     "q_local": dev(sc.binding["q_local"], device), "log_scale": dev(sc.binding["log_scale"], device),
+                     "queries": dev(sc.queries, device)}, sc, fr))
+    return out
+
+
+def _plain_frame(mg, s, t, opts):
+    """The plain per-frame path for scene-frame (s, t)."""
+    V = s["frames"][t].contiguous()
+    bvh = mg.lbvh_build(s["frames"][0].contiguous(), s["faces"])
+    mg.lbvh_refit(bvh, V)
+    g = mg.mesh_gaussian_update(V, s["faces"], s["gface"], s["bary"], s["q_local"], s["log_scale"])
+    q = mg.closest_point_query(bvh, V, s["queries"], normal=True, kernel="batch", **opts)
+    return bvh, g, q
+
+
+def _compare(mg, scenes, plan, opts):
+    for i, (s, sc, fr) in enumerate(scenes):
+        o = plan.out[i]
+        for t in range(fr.shape[0]):
+            bvh, g, q = _plain_frame(mg, s, t, opts)
+            # refit: boxes, child references and leaf triangles bitwise
+            ref = decode_bvh(bvh)
+            view = bvh.buf.clone()
+            L = bvh.layout
+            m = bvh.n - 1
+            view[L.off_nodes:L.off_nodes + 96 * m] = o["nodes"][t].view(torch.uint8)
+            view[16:28] = o["roots"][t, 0:3].contiguous().view(torch.uint8)
+            view[32:44] = o["roots"][t, 4:7].contiguous().view(torch.uint8)
+            bvh.buf.copy_(view)
+            got = decode_bvh(bvh)
+            for k in ("child", "internal_box", "leaf_box", "root_box"):
+                np.testing.assert_array_equal(got[k], ref[k], err_msg=f"scene {i} frame {t} {k}")
+            # Gaussians: the same device function
+            for k in ("mean", "quat", "cov"):
+                np.testing.assert_allclose(host(o[k][t]), host(g[k]), rtol=1e-6, atol=1e-7,
+                                           err_msg=f"scene {i} frame {t} {k}")
+            # queries: the same traversal with the same options
+            fa, fb = host(o["face"][t]), host(q["face"])
+            same = fa == fb
+            assert same.mean() > 0.999, f"scene {i} frame {t}"
+            np.testing.assert_array_equal(host(o["dist2"][t])[same], host(q["dist2"])[same])
+            np.testing.assert_array_equal(host(o["point"][t])[:, same], host(q["point"])[:, same])
+            np.testing.assert_array_equal(host(o["normal"][t])[:, same], host(q["normal"])[:, same])
+
+
+@pytest.mark.parametrize("batch,seed,gtile,qtile", [(4, True, 2048, 256), (1, False, 256, 64), (16, True, 512, 128)])
+def test_batched_equals_plain(device, batch, seed, gtile, qtile):
+    import paper_2606_00444_amd as mg
+    from paper_2606_00444_amd.batch import BatchPlan
+    scenes = _scenes(device)
+    plan = BatchPlan([s for s, _, _ in scenes], batch=batch, seed=seed, gauss_tile=gtile, query_tile=qtile)
+    plan.run()
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    _compare(mg, scenes, plan, {"batch": batch, "seed": seed})
+
+
+def test_batched_uneven_full_size_scenes_sampled(device):
+    """Two of the six full-size C3 scenes (5k and 50k faces), 3 frames, checked against the plain path."""
+    import paper_2606_00444_amd as mg
+    from paper_2606_00444_amd.batch import BatchPlan
+    scenes = _scenes(device, ids=(0, 5), frames=3, small=False)
+    plan = BatchPlan([s for s, _, _ in scenes])
+    plan.run()
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    _compare(mg, scenes, plan, {"batch": 4, "seed": True})
+
+
+def test_batched_graph_replays(device):
+    from paper_2606_00444_amd.batch import BatchPlan
+    scenes = _scenes(device, ids=(1, 2), frames=3)
+    plan = BatchPlan([s for s, _, _ in scenes])
+
+    def clobber():
+        # eager work between runs; also zeroes the record words no refit writes
+        # (the third float4 of an internal child's slot), so runs compare bitwise
+        for o in plan.out:
+            for v in o.values():
+                if v is not None:
+                    v.zero_()
+
+    clobber()
+    plan.run()
+    torch.cuda.synchronize()
+    eager = [{k: v.clone() for k, v in o.items() if v is not None} for o in plan.out]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.run()
+    for _ in range(3):
+        clobber()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert plan.status() == 0
+        for i, (o, e) in enumerate(zip(plan.out, eager)):
+            for k, v in e.items():
+                # bitwise: node records hold integer child references whose bits may read as NaN
+                a, b = host(o[k]).view(np.uint32), host(v).view(np.uint32)
+                bad = np.argwhere(a != b)
+                assert len(bad) == 0, f"scene {i} {k}: {len(bad)} words differ, first {bad[:8].tolist()}"
