@@ -81,6 +81,10 @@ mg_status mg_frame_index(int64_t step, int64_t f_recon_num, int64_t f_recon_den,
 mg_status mg_vertex_buffer_update(const float *frames, int32_t n_frames, int32_t n_verts, int32_t k,
                                   float *live, void *stream);
 
+/* x[n] <- value on the device (a kernel, not a memset, so it may sit in a
+ * captured HIP graph); used to clear gradient accumulators. */
+mg_status mg_fill(float *x, int64_t n, float value, void *stream);
+
 /* ------------------------------------------------------------------------
  * Face-bound Gaussian re-pose (render side of the dual representation,
  * Sec. 3.2).  The paper states no binding formula; the library computes, per
@@ -110,9 +114,9 @@ mg_status mg_mesh_gaussian_update(const float *verts, int32_t n_verts, const int
                                   float *cov, float *rot, void *stream);
 
 /* Backward of mg_mesh_gaussian_update w.r.t. the vertices: g_verts [3][n_verts]
- * is ACCUMULATED into (+=) from g_mean [3][G] (required), g_rot [9][G]
- * (row-major dL/dR_g) and g_cov [6][G] (dL/d packed Sigma), either NULL for
- * zero.  The quaternion output is not differentiated.  Uses float atomics:
+ * is ACCUMULATED into (+=) from g_mean [3][G], g_rot [9][G] (row-major
+ * dL/dR_g) and g_cov [6][G] (dL/d packed Sigma), each NULL for zero (all
+ * three NULL: no-op).  The quaternion output is not differentiated.  Uses float atomics:
  * results are reproducible to rounding, not bitwise. */
 mg_status mg_mesh_gaussian_update_backward(const float *verts, int32_t n_verts, const int32_t *faces,
                                            int32_t n_faces, const int32_t *gface, const float *bary,
@@ -297,18 +301,24 @@ mg_status mg_chamfer(const float *a, int32_t na, const void *bvh_a, size_t bvh_a
                      int32_t *nn_ab, float *d_ab, int32_t *nn_ba, float *d_ba, double *out,
                      void *ws, size_t ws_bytes, const mg_query_options *opts, void *stream);
 
-/* g_verts [3][n_verts] += scale * sum_q -2 w_k (y_q - c_q) on the three
+/* g_verts [3][n_verts] += scale * g * sum_q -2 w_k (y_q - c_q) on the three
  * vertices of each query's face (queries with face == -1 contribute nothing).
- * face/point/bary as returned by mg_closest_point_query on the same mesh. */
+ * face/point/bary as returned by mg_closest_point_query on the same mesh.
+ * g_loss: optional device float64 scalar (the upstream gradient of the loss,
+ * read on the device so autograd needs no host sync); NULL means g = 1.
+ * Accumulates with float32 atomics, so the summation order (last bits) may
+ * vary between runs. */
 mg_status mg_point_mesh_backward(const float *verts, int32_t n_verts, const int32_t *faces,
                                  int32_t n_faces, const float *queries, int32_t n_queries,
                                  const int32_t *face, const float *point, const float *bary,
-                                 float scale, float *g_verts, void *stream);
+                                 float scale, const double *g_loss, float *g_verts, void *stream);
 
-/* g_a [3][na] += 2 scale_ab (a_i - b_nn_ab(i)) + 2 scale_ba sum_{j: nn_ba(j)=i} (a_i - b_j). */
+/* g_a [3][na] += g * (2 scale_ab (a_i - b_nn_ab(i)) + 2 scale_ba sum_{j: nn_ba(j)=i} (a_i - b_j)),
+ * g = *g_loss (device float64) or 1 when g_loss is NULL.  Swapping the roles
+ * of a and b (and of the two maps and scales) gives the gradient w.r.t. b. */
 mg_status mg_chamfer_backward(const float *a, int32_t na, const float *b, int32_t nb,
                               const int32_t *nn_ab, const int32_t *nn_ba, float scale_ab,
-                              float scale_ba, float *g_a, void *stream);
+                              float scale_ba, const double *g_loss, float *g_a, void *stream);
 
 /* Adam (Kingma & Ba 2015) in torch.optim.Adam's order, in place on param/m/v
  * [n] float32; step counts from 1. */

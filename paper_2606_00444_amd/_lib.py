@@ -61,6 +61,7 @@ PROTOTYPES = {
     "mg_check_device": (I32, []),
     "mg_frame_index": (I32, [I64, I64, I64, I64, I32, P]),
     "mg_vertex_buffer_update": (I32, [P, I32, I32, I32, P, P]),
+    "mg_fill": (I32, [P, I64, F32, P]),
     "mg_mesh_gaussian_update": (I32, [P, I32, P, I32, P, P, P, P, P, I32, U32, P, P, P, P, P]),
     "mg_mesh_gaussian_update_backward": (I32, [P, I32, P, I32, P, P, P, P, P, I32, P, P, P, P, P]),
     "mg_lbvh_layout_query": (I32, [I32, I32, P]),
@@ -73,8 +74,8 @@ PROTOTYPES = {
     "mg_reduce_workspace_size": (I32, [I64, P]),
     "mg_mean": (I32, [P, I64, P, P, SZ, P]),
     "mg_chamfer": (I32, [P, I32, P, SZ, P, I32, P, SZ, P, P, P, P, P, P, SZ, P, P]),
-    "mg_point_mesh_backward": (I32, [P, I32, P, I32, P, I32, P, P, P, F32, P, P]),
-    "mg_chamfer_backward": (I32, [P, I32, P, I32, P, P, F32, F32, P, P]),
+    "mg_point_mesh_backward": (I32, [P, I32, P, I32, P, I32, P, P, P, F32, P, P, P]),
+    "mg_chamfer_backward": (I32, [P, I32, P, I32, P, P, F32, F32, P, P, P]),
     "mg_adam_step": (I32, [P, P, P, P, I64, I32, F32, F32, F32, F32, P]),
     "mg_batch_plan_size": (I32, [P, I32, P]),
     "mg_batch_plan_init": (I32, [P, I32, P, P, SZ, P]),

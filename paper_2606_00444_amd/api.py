@@ -15,7 +15,7 @@ from . import _lib
 from ._lib import MG_PRIM_POINTS, MG_PRIM_TRIANGLES, MG_QUERY_AUTO, MG_QUERY_BATCH, MG_QUERY_LANE, LbvhLayout, QueryOptions
 
 __all__ = [
-    "frame_index", "vertex_buffer_update", "mesh_gaussian_update", "mesh_gaussian_update_backward",
+    "frame_index", "vertex_buffer_update", "fill", "mesh_gaussian_update", "mesh_gaussian_update_backward",
     "LBVH", "query_order", "lbvh_bytes", "lbvh_workspace_bytes", "lbvh_build", "lbvh_refit", "closest_point_query", "closest_point_bruteforce",
     "nearest_point_query", "mean", "chamfer", "point_mesh_backward", "chamfer_backward", "adam_step",
     "validate_indices", "validate_finite", "version", "check_device",
@@ -54,6 +54,14 @@ def _i32(t, name="tensor"):
     return t
 
 
+def _f64(t, name="tensor"):
+    if t is None:
+        return None
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    return t
+
+
 def _call(name, *args):
     lib = _lib.load()
     _lib.check(name, getattr(lib, name)(*args))
@@ -82,6 +90,12 @@ def vertex_buffer_update(frames, k, live):
         raise ValueError("frames must be [T][3][V] and live [3][V]")
     _call("mg_vertex_buffer_update", _ptr(frames), T, V, int(k), _ptr(_f32(live, 3, "live")), _stream())
     return live
+
+
+def fill(x, value=0.0):
+    """x[:] = value on the device (float32, contiguous); graph-capturable."""
+    _call("mg_fill", _ptr(_f32(x)), x.numel(), float(value), _stream())
+    return x
 
 
 def mesh_gaussian_update(verts, faces, gface, bary, q_local, log_scale, offset=None, *, out=None,
@@ -113,7 +127,7 @@ def mesh_gaussian_update_backward(verts, faces, gface, bary, q_local, log_scale,
         g_verts = torch.zeros_like(verts)
     G = gface.shape[0]
     _call("mg_mesh_gaussian_update_backward", _ptr(verts), verts.shape[1], _ptr(faces), faces.shape[1],
-          _ptr(gface), _ptr(bary), _ptr(q_local), _ptr(log_scale), _ptr(offset), G, _ptr(_f32(g_mean, 3)),
+          _ptr(gface), _ptr(bary), _ptr(q_local), _ptr(log_scale), _ptr(offset), G, _ptr(_f32(g_mean, 3, "g_mean")),
           _ptr(_f32(g_rot, 9)), _ptr(_f32(g_cov, 6)), _ptr(_f32(g_verts, 3)), _stream())
     return g_verts
 
@@ -277,36 +291,42 @@ def mean(x, out=None):
     return out
 
 
-def chamfer(a, bvh_a, b, bvh_b, *, kernel=None, batch=0, seed=False):
-    """Two-sided Chamfer pieces: dict nn_ab, d_ab, nn_ba, d_ba and means [2] (float64)."""
-    na, nb = a.shape[1], b.shape[1]
+def chamfer(a, bvh_a, b, bvh_b, *, out=None, kernel=None, batch=0, seed=False):
+    """Two-sided Chamfer pieces: dict nn_ab, d_ab, nn_ba, d_ba and means [2] (float64).
+
+    out: optional dict of preallocated outputs with those keys (means may be any
+    contiguous float64 [2] view)."""
+    na, nb = _f32(a, 3, "a").shape[1], _f32(b, 3, "b").shape[1]
     dev = a.device
-    o = {"nn_ab": torch.empty(na, dtype=torch.int32, device=dev), "d_ab": torch.empty(na, device=dev),
-         "nn_ba": torch.empty(nb, dtype=torch.int32, device=dev), "d_ba": torch.empty(nb, device=dev),
-         "means": torch.empty(2, dtype=torch.float64, device=dev)}
+    o = dict(out or {})
+    for k, n, dt in (("nn_ab", na, torch.int32), ("d_ab", na, torch.float32), ("nn_ba", nb, torch.int32),
+                     ("d_ba", nb, torch.float32), ("means", 2, torch.float64)):
+        if o.get(k) is None:
+            o[k] = torch.empty(n, dtype=dt, device=dev)
     ws = _rws(dev)
-    _call("mg_chamfer", _ptr(_f32(a, 3)), na, _ptr(bvh_a.buf), bvh_a.nbytes, _ptr(_f32(b, 3)), nb, _ptr(bvh_b.buf),
-          bvh_b.nbytes, _ptr(o["nn_ab"]), _ptr(o["d_ab"]), _ptr(o["nn_ba"]), _ptr(o["d_ba"]), _ptr(o["means"]),
-          _ptr(ws), ws.numel(), _opts(kernel, batch, seed), _stream())
+    _call("mg_chamfer", _ptr(a), na, _ptr(bvh_a.buf), bvh_a.nbytes, _ptr(b), nb, _ptr(bvh_b.buf),
+          bvh_b.nbytes, _ptr(_i32(o["nn_ab"])), _ptr(_f32(o["d_ab"])), _ptr(_i32(o["nn_ba"])), _ptr(_f32(o["d_ba"])),
+          _ptr(_f64(o["means"], "means")), _ptr(ws), ws.numel(), _opts(kernel, batch, seed), _stream())
     return o
 
 
-def point_mesh_backward(verts, faces, queries, rec, scale, g_verts=None):
-    """g_verts += scale * d(sum_q d^2_q)/dV from closest-point records rec (face, point, bary)."""
+def point_mesh_backward(verts, faces, queries, rec, scale, g_verts=None, g_loss=None):
+    """g_verts += scale * g * d(sum_q d^2_q)/dV from closest-point records rec (face, point, bary);
+    g = g_loss (a float64 device scalar) or 1."""
     if g_verts is None:
         g_verts = torch.zeros_like(verts)
     _call("mg_point_mesh_backward", _ptr(verts), verts.shape[1], _ptr(faces), faces.shape[1], _ptr(queries),
           queries.shape[1], _ptr(rec["face"]), _ptr(rec["point"]), _ptr(rec["bary"]), float(scale),
-          _ptr(g_verts), _stream())
+          _ptr(_f64(g_loss)), _ptr(g_verts), _stream())
     return g_verts
 
 
-def chamfer_backward(a, b, nn_ab, nn_ba, scale_ab, scale_ba, g_a=None):
-    """g_a += gradient of scale_ab * sum d_ab + scale_ba * sum d_ba w.r.t. a."""
+def chamfer_backward(a, b, nn_ab, nn_ba, scale_ab, scale_ba, g_a=None, g_loss=None):
+    """g_a += g * gradient of scale_ab * sum d_ab + scale_ba * sum d_ba w.r.t. a (g = g_loss or 1)."""
     if g_a is None:
         g_a = torch.zeros_like(a)
     _call("mg_chamfer_backward", _ptr(a), a.shape[1], _ptr(b), b.shape[1], _ptr(nn_ab), _ptr(nn_ba),
-          float(scale_ab), float(scale_ba), _ptr(g_a), _stream())
+          float(scale_ab), float(scale_ba), _ptr(_f64(g_loss)), _ptr(g_a), _stream())
     return g_a
 
 

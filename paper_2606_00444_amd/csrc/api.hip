@@ -24,6 +24,11 @@ __global__ __launch_bounds__(256) void copy1_kernel(const float *__restrict__ sr
         dst[i] = src[i];
 }
 
+__global__ __launch_bounds__(256) void fill_kernel(float *__restrict__ x, int64_t n, float value) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = value;
+}
+
 }  // namespace
 }  // namespace mgu
 
@@ -85,5 +90,13 @@ extern "C" mg_status mg_vertex_buffer_update(const float *frames, int32_t n_fram
         const int grid = static_cast<int>(std::min<int64_t>(blocks_for(n, 256), 2048));
         hipLaunchKernelGGL(copy1_kernel, dim3(grid), dim3(256), 0, s, src, live, n);
     }
+    return launch_status();
+}
+
+extern "C" mg_status mg_fill(float *x, int64_t n, float value, void *stream) {
+    if (n < 0 || (n > 0 && !x)) return MG_ERR_INVALID_ARGUMENT;
+    if (n == 0) return MG_OK;
+    const int grid = static_cast<int>(std::min<int64_t>(blocks_for(n, 256), 2048));
+    hipLaunchKernelGGL(fill_kernel, dim3(grid), dim3(256), 0, as_stream(stream), x, n, value);
     return launch_status();
 }

@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void gaussian_backward_kernel(Inputs in, const
     Local L;
     load_local(in, g, L);
     const int64_t n = in.ng;
-    const f3 gm = load3(gmean, n, g);
+    const f3 gm = gmean ? load3(gmean, n, g) : f3{0, 0, 0};
     float gR[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) gR[k] = grot ? grot[k * n + g] : 0.0f;
@@ -124,8 +124,9 @@ extern "C" mg_status mg_mesh_gaussian_update_backward(const float *verts, int32_
                                                       const float *g_cov, float *g_verts, void *stream) {
     if (bad_count(n_verts) || bad_count(n_faces) || bad_count(n_gauss)) return MG_ERR_INVALID_ARGUMENT;
     if (n_gauss == 0) return MG_OK;
-    if (!verts || !faces || !gface || !bary || !q_local || !log_scale || !g_mean || !g_verts ||
-        n_faces == 0 || n_verts == 0)
+    if (!g_mean && !g_rot && !g_cov) return MG_OK;   // no upstream gradient: nothing to add
+    if (!verts || !faces || !gface || !bary || !q_local || !log_scale || !g_verts || n_faces == 0 ||
+        n_verts == 0)
         return MG_ERR_INVALID_ARGUMENT;
     Inputs in{verts, n_verts, faces, n_faces, gface, bary, q_local, log_scale, offset, n_gauss};
     hipLaunchKernelGGL(gaussian_backward_kernel, dim3(blocks_for(n_gauss, 256)), dim3(256), 0,

@@ -48,11 +48,12 @@ __global__ __launch_bounds__(kReduceThreads) void final_mean_kernel(const double
 __global__ __launch_bounds__(256) void point_mesh_backward_kernel(
     const float *__restrict__ verts, int64_t nv, const int32_t *__restrict__ faces, int64_t nf,
     const float *__restrict__ y, int64_t nq, const int32_t *__restrict__ face, const float *__restrict__ point,
-    const float *__restrict__ bary, float scale, float *__restrict__ g) {
+    const float *__restrict__ bary, float scale, const double *__restrict__ g_loss, float *__restrict__ g) {
     const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (q >= nq) return;
     const int32_t f = face[q];
     if (f < 0) return;
+    if (g_loss) scale *= static_cast<float>(*g_loss);
     const f3 r = load3(y, nq, q) - load3(point, nq, q);
     const float w1 = bary[q], w2 = bary[nq + q];
     const float w[3] = {1.0f - w1 - w2, w1, w2};
@@ -72,8 +73,14 @@ __global__ __launch_bounds__(256) void chamfer_backward_kernel(const float *__re
                                                                const float *__restrict__ b, int64_t nb,
                                                                const int32_t *__restrict__ nn_ab,
                                                                const int32_t *__restrict__ nn_ba, float s_ab,
-                                                               float s_ba, float *__restrict__ g) {
+                                                               float s_ba, const double *__restrict__ g_loss,
+                                                               float *__restrict__ g) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g_loss) {
+        const float gl = static_cast<float>(*g_loss);
+        s_ab *= gl;
+        s_ba *= gl;
+    }
     if (t < na) {
         const int32_t j = nn_ab[t];
         if (j < 0) return;
@@ -187,25 +194,25 @@ extern "C" mg_status mg_chamfer(const float *a, int32_t na, const void *bvh_a, s
 extern "C" mg_status mg_point_mesh_backward(const float *verts, int32_t n_verts, const int32_t *faces,
                                             int32_t n_faces, const float *queries, int32_t n_queries,
                                             const int32_t *face, const float *point, const float *bary,
-                                            float scale, float *g_verts, void *stream) {
+                                            float scale, const double *g_loss, float *g_verts, void *stream) {
     if (bad_count(n_verts) || bad_count(n_faces) || bad_count(n_queries)) return MG_ERR_INVALID_ARGUMENT;
     if (n_queries == 0) return MG_OK;
     if (!verts || !faces || !queries || !face || !point || !bary || !g_verts) return MG_ERR_INVALID_ARGUMENT;
     hipLaunchKernelGGL(point_mesh_backward_kernel, dim3(blocks_for(n_queries, 256)), dim3(256), 0,
                        as_stream(stream), verts, (int64_t)n_verts, faces, (int64_t)n_faces, queries,
-                       (int64_t)n_queries, face, point, bary, scale, g_verts);
+                       (int64_t)n_queries, face, point, bary, scale, g_loss, g_verts);
     return launch_status();
 }
 
 extern "C" mg_status mg_chamfer_backward(const float *a, int32_t na, const float *b, int32_t nb,
                                          const int32_t *nn_ab, const int32_t *nn_ba, float scale_ab,
-                                         float scale_ba, float *g_a, void *stream) {
+                                         float scale_ba, const double *g_loss, float *g_a, void *stream) {
     if (bad_count(na) || bad_count(nb)) return MG_ERR_INVALID_ARGUMENT;
     if (na == 0) return MG_OK;
     if (!a || !g_a || !nn_ab || (nb > 0 && (!b || !nn_ba))) return MG_ERR_INVALID_ARGUMENT;
     const int64_t total = static_cast<int64_t>(na) + nb;
     hipLaunchKernelGGL(chamfer_backward_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, as_stream(stream), a,
-                       (int64_t)na, b, (int64_t)nb, nn_ab, nn_ba, scale_ab, scale_ba, g_a);
+                       (int64_t)na, b, (int64_t)nb, nn_ab, nn_ba, scale_ab, scale_ba, g_loss, g_a);
     return launch_status();
 }
 

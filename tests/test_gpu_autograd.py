@@ -1,0 +1,226 @@
+"""The differentiable template projection on the GPU: autograd Functions and the
+device-side Adam refinement, against float64 finite differences and the oracle."""
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import need_gpu, dev, host, scale_of
+from grad_helpers import oracle_grad_at, normwise
+from synth import make_config
+from oracle import losses as olo
+from oracle import adam as oa
+from oracle import gaussians as og
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def device():
+    return need_gpu()
+
+
+def _setup(device, full=False, n_targets=None):
+    sc = make_config(4, small=not full)
+    Y = sc.extra["targets"]
+    if n_targets is not None:
+        Y = Y[:, :n_targets]
+    d = {"V": dev(sc.verts0, device), "F": dev(sc.faces, device), "Y": dev(Y, device),
+         "B": {k: dev(v, device) for k, v in sc.binding.items()}}
+    return sc, Y, d
+
+
+def _autograd_loss_grad(mg, d):
+    from paper_2606_00444_amd.autograd import template_projection_loss
+    V = d["V"].clone().requires_grad_(True)
+    bvh = mg.lbvh_build(d["V"], d["F"])
+    L = template_projection_loss(V, d["F"], d["B"], d["Y"], bvh)
+    L.backward()
+    return L.item(), host(V.grad)
+
+
+def test_autograd_gradient_vs_fp64_central_differences(device):
+    """dL/dV from the autograd Functions against FP64 central differences of the
+    oracle loss, on the 500-face subset, at coordinates whose +-h keeps every argmin."""
+    import paper_2606_00444_amd as mg
+    sc, Y, d = _setup(device)
+    L_dev, g_dev = _autograd_loss_grad(mg, d)
+    V, F, B = sc.verts0.astype(np.float64), sc.faces, sc.binding
+    L0, aux0 = olo.template_loss(V, F, B, Y)
+    assert L_dev == pytest.approx(L0, rel=1e-5)
+    base = (aux0["rec"]["face"], aux0["nn_ab"], aux0["nn_ba"])
+    h = 1e-6 * scale_of(V)
+    rng = np.random.default_rng(7)
+    coords = [(int(a), int(v)) for a, v in zip(rng.integers(0, 3, 150), rng.integers(0, V.shape[1], 150))]
+    fd, keep = [], []
+    for ax, vi in coords:
+        vals = []
+        same = True
+        for s in (+1, -1):
+            Vp = V.copy()
+            Vp[ax, vi] += s * h
+            Lp, aux = olo.template_loss(Vp, F, B, Y)
+            vals.append(Lp)
+            same &= all(np.array_equal(x, y) for x, y in zip((aux["rec"]["face"], aux["nn_ab"], aux["nn_ba"]), base))
+        if same:
+            fd.append((vals[0] - vals[1]) / (2 * h))
+            keep.append((ax, vi))
+    assert len(keep) >= 100
+    got = np.array([g_dev[ax, vi] for ax, vi in keep])
+    assert normwise(got, np.array(fd)) <= 1e-5
+
+
+def test_autograd_gradient_vs_oracle_at_device_argmins(device):
+    import paper_2606_00444_amd as mg
+    from paper_2606_00444_amd.refine import TemplateRefiner
+    sc, Y, d = _setup(device)
+    L_dev, g_dev = _autograd_loss_grad(mg, d)
+    # the same argmins from the refiner's buffers (same kernels, same inputs)
+    r = TemplateRefiner(d["V"], d["F"], d["B"], d["Y"])
+    row = r.loss_and_grad()
+    torch.cuda.synchronize()
+    am = (host(r.rec["face"]), host(r.ch["nn_ab"]), host(r.ch["nn_ba"]))
+    L_ref, g_ref = oracle_grad_at(sc.verts0, sc.faces, sc.binding, Y, am)
+    assert L_dev == pytest.approx(L_ref, rel=1e-5)
+    assert host(row).sum() == pytest.approx(L_dev, rel=1e-12)
+    assert normwise(g_dev, g_ref) <= 1e-5
+    assert normwise(host(r.gV), g_dev) <= 1e-6          # refiner == autograd up to atomic order
+
+
+def test_binding_function_all_outputs(device):
+    from paper_2606_00444_amd.autograd import MeshGaussianBinding
+    sc = make_config(2, small=True)
+    rng = np.random.default_rng(92)
+    G = sc.n_gauss
+    gm, gr, gc = (rng.normal(size=(k, G)).astype(np.float32) for k in (3, 9, 6))
+    off = rng.normal(0, 0.01, G).astype(np.float32)
+    V0 = sc.frames([3])[0]
+    b = {k: dev(v, device) for k, v in sc.binding.items()}
+    V = dev(V0, device).requires_grad_(True)
+    mean, rot, cov = MeshGaussianBinding.apply(V, dev(sc.faces, device), b["face"], b["bary"], b["q_local"],
+                                               b["log_scale"], dev(off, device), True)
+    ref = og.repose(V0, sc.faces, sc.binding, offset=off)
+    L = scale_of(V0)
+    assert np.abs(host(mean) - ref["mean"]).max() <= 1e-5 * max(1.0, L)
+    ((mean * dev(gm, device)).sum() + (rot * dev(gr, device)).sum() + (cov * dev(gc, device)).sum()).backward()
+    g_ref = olo.binding_vjp(V0, sc.faces, sc.binding, gm, gr.reshape(3, 3, G).transpose(2, 0, 1), gc, offset=off)
+    assert normwise(host(V.grad), g_ref) <= 1e-5
+    # only the mean used: the other two upstream gradients are absent (NULL on the device)
+    V.grad = None
+    mean, rot, cov = MeshGaussianBinding.apply(V, dev(sc.faces, device), b["face"], b["bary"], b["q_local"],
+                                               b["log_scale"], dev(off, device), True)
+    (mean * dev(gm, device)).sum().backward()
+    assert normwise(host(V.grad), olo.binding_vjp(V0, sc.faces, sc.binding, gm, offset=off)) <= 1e-5
+
+
+def test_chamfer_function_both_sides(device):
+    from paper_2606_00444_amd.autograd import ChamferLoss
+    rng = np.random.default_rng(93)
+    a = rng.normal(size=(3, 3000)).astype(np.float32)
+    b = rng.normal(size=(3, 2000)).astype(np.float32)
+    A = dev(a, device).requires_grad_(True)
+    Bt = dev(b, device).requires_grad_(True)
+    cd = ChamferLoss.apply(A, Bt)
+    (3.0 * cd).backward()                                   # upstream gradient read on the device
+    ref, nn_ab, nn_ba, _, _ = olo.chamfer(a, b)
+    assert cd.item() == pytest.approx(ref, rel=1e-5)
+    assert normwise(host(A.grad), 3.0 * olo.chamfer_grad_a(a, b, nn_ab, nn_ba)) <= 1e-5
+    assert normwise(host(Bt.grad), 3.0 * olo.chamfer_grad_a(b, a, nn_ba, nn_ab)) <= 1e-5
+
+
+def test_point_to_mesh_function_scaled_upstream(device):
+    import paper_2606_00444_amd as mg
+    from paper_2606_00444_amd.autograd import PointToMeshLoss
+    sc, Y, d = _setup(device)
+    V = d["V"].clone().requires_grad_(True)
+    bvh = mg.lbvh_build(d["V"], d["F"])
+    P = PointToMeshLoss.apply(V, d["F"], d["Y"], bvh)
+    (-0.5 * P).backward()
+    P_ref, rec = olo.point_to_mesh(sc.verts0, sc.faces, Y)
+    assert P.item() == pytest.approx(P_ref, rel=1e-5)
+    g_ref = -0.5 * olo.point_to_mesh_grad(sc.verts0, sc.faces, Y, rec)
+    assert normwise(host(V.grad), g_ref) <= 1e-5
+
+
+def _oracle_refine(sc, Y, steps, lr):
+    V = sc.verts0.astype(np.float64)
+    m = np.zeros_like(V)
+    v = np.zeros_like(V)
+    hist = []
+    for t in range(1, steps + 1):
+        L, g, _ = olo.template_loss_grad(V, sc.faces, sc.binding, Y)
+        hist.append(L)
+        V, m, v = oa.adam_step(V, g, m, v, t, lr)
+    return np.array(hist), V
+
+
+def test_refiner_200_adam_steps(device):
+    """200 Adam steps on the 500-face subset.  Per step the device gradient at the
+    device's V equals the oracle gradient there (at the device's argmins), normwise
+    within 1e-5 of the sum of the three loss terms' gradient norms (the terms
+    nearly cancel close to the optimum, float32 error does not); the loss
+    trajectory is compared with an FP64 oracle run side by side (argmin switches
+    let the two drift apart, so only the overall descent and the end point are
+    bounded loosely)."""
+    from paper_2606_00444_amd.refine import TemplateRefiner
+    sc, Y, d = _setup(device)
+    r = TemplateRefiner(d["V"], d["F"], d["B"], d["Y"])
+    checked = 0
+    for t in range(200):
+        if t in (0, 1, 50, 199):
+            Vt = host(r.V).astype(np.float64)
+            r.step()
+            torch.cuda.synchronize()
+            am = (host(r.rec["face"]), host(r.ch["nn_ab"]), host(r.ch["nn_ba"]))
+            L_ref, g_ref, scale = oracle_grad_at(Vt, sc.faces, sc.binding, Y, am, parts=True)
+            assert host(r.history[t]).sum() == pytest.approx(L_ref, rel=1e-5)
+            assert normwise(host(r.gV), g_ref, scale) <= 1e-5
+            checked += 1
+        else:
+            r.step()
+    torch.cuda.synchronize()
+    hist = host(r.losses()).sum(1)
+    assert checked == 4
+    ref_hist, _ = _oracle_refine(sc, Y, 200, r.lr)
+    print(f"loss: start {hist[0]:.6e} (oracle {ref_hist[0]:.6e}), end {hist[-1]:.6e} (oracle {ref_hist[-1]:.6e})")
+    assert hist[0] == pytest.approx(ref_hist[0], rel=1e-5)
+    assert hist[-1] < 0.5 * hist[0]
+    assert hist[-1] == pytest.approx(ref_hist[-1], rel=0.05)
+
+
+def test_refiner_graph_replay_matches_eager(device):
+    """A captured 200-step run replays to the eager run's trajectory (float32 atomics
+    reorder the gradient sums, so agreement is to rounding, not bitwise)."""
+    from paper_2606_00444_amd.refine import TemplateRefiner
+    sc, Y, d = _setup(device)
+    r = TemplateRefiner(d["V"], d["F"], d["B"], d["Y"])
+    r.run(200)
+    torch.cuda.synchronize()
+    eager_hist, eager_V = host(r.losses()).copy(), host(r.V).copy()
+    g = r.capture(200)
+    for _ in range(2):
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        hist = host(r.losses())
+        np.testing.assert_allclose(hist, eager_hist, rtol=1e-3)
+        assert np.abs(host(r.V) - eager_V).max() <= 1e-3 * scale_of(sc.verts0)
+
+
+def test_refiner_full_size_first_steps(device):
+    """Full-size template (40,000 faces, 100,000 Gaussians, 100,000 targets): the
+    refiner's gradient equals the autograd Functions' and the loss goes down."""
+    import paper_2606_00444_amd as mg
+    from paper_2606_00444_amd.refine import TemplateRefiner
+    sc, Y, d = _setup(device, full=True)
+    L_dev, g_dev = _autograd_loss_grad(mg, d)
+    r = TemplateRefiner(d["V"], d["F"], d["B"], d["Y"])
+    r.step()
+    torch.cuda.synchronize()
+    assert host(r.history[0]).sum() == pytest.approx(L_dev, rel=1e-12)
+    assert normwise(host(r.gV), g_dev) <= 1e-6
+    for _ in range(9):
+        r.step()
+    torch.cuda.synchronize()
+    hist = host(r.losses()).sum(1)
+    assert hist[-1] < hist[0]

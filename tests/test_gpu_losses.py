@@ -5,6 +5,7 @@ import pytest
 import torch
 
 from gpu_helpers import need_gpu, dev, host, scale_of
+from grad_helpers import oracle_grad_at, normwise
 from synth import make_config
 from oracle import losses as olo
 from oracle import closest as oc
@@ -17,10 +18,6 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module")
 def device():
     return need_gpu()
-
-
-def _normwise(a, b):
-    return np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b)
 
 
 def test_mean_deterministic(device):
@@ -70,40 +67,18 @@ def _gpu_template_grad(mg, device, sc, Y):
     return P + host(ch["means"]).sum(), host(gV), argmins
 
 
-def _oracle_grad_at(sc, Y, argmins):
-    """Oracle loss and analytic gradient, evaluated at the device's argmins after checking
-    that each of them ties the oracle's own minimum (gradients of a min are only defined
-    up to the choice among tied minimisers)."""
-    V, F, B = sc.verts0, sc.faces, sc.binding
-    face, nn_ab, nn_ba = argmins
-    L_ref, aux = olo.template_loss(V, F, B, Y)
-    Lsc = scale_of(V)
-    rec = oc.closest_on_faces(V, F, Y, face)
-    tol = 1e-5 * np.maximum(np.sqrt(aux["rec"]["dist2"]), 0.1 * Lsc)
-    assert (np.sqrt(rec["dist2"]) <= np.sqrt(aux["rec"]["dist2"]) + tol).all()
-    mu = aux["mu"]
-    d_ab = ((mu - Y[:, nn_ab]) ** 2).sum(0)
-    d_ba = ((mu[:, nn_ba] - Y) ** 2).sum(0)
-    _, _, _, r_ab, r_ba = olo.chamfer(mu, Y)
-    assert (np.sqrt(d_ab) <= np.sqrt(r_ab) + 1e-5 * np.maximum(np.sqrt(r_ab), 0.1 * Lsc)).all()
-    assert (np.sqrt(d_ba) <= np.sqrt(r_ba) + 1e-5 * np.maximum(np.sqrt(r_ba), 0.1 * Lsc)).all()
-    g = olo.point_to_mesh_grad(V, F, Y, rec)
-    g = g + olo.binding_vjp(V, F, B, olo.chamfer_grad_a(mu, Y, nn_ab, nn_ba))
-    return L_ref, g
-
-
 def test_template_gradient_fd_subset(device):
     import paper_2606_00444_amd as mg
     sc = make_config(4, small=True)
     Y = sc.extra["targets"]
     L_dev, g_dev, am = _gpu_template_grad(mg, device, sc, Y)
-    L_ref, g_ref = _oracle_grad_at(sc, Y, am)
+    L_ref, g_ref = oracle_grad_at(sc.verts0, sc.faces, sc.binding, Y, am)
     assert L_dev == pytest.approx(L_ref, rel=1e-5)
-    assert _normwise(g_dev, g_ref) <= 1e-5
+    assert normwise(g_dev, g_ref) <= 1e-5
     # where every argmin agrees, the oracle's own gradient is the same
     L0, g0, aux = olo.template_loss_grad(sc.verts0, sc.faces, sc.binding, Y)
     if all(np.array_equal(x, y) for x, y in zip(am, (aux["rec"]["face"], aux["nn_ab"], aux["nn_ba"]))):
-        assert _normwise(g_dev, g0) <= 1e-5
+        assert normwise(g_dev, g0) <= 1e-5
 
 
 def test_template_gradient_full_size_subsampled_targets(device):
@@ -111,9 +86,9 @@ def test_template_gradient_full_size_subsampled_targets(device):
     sc = make_config(4)
     Y = sc.extra["targets"][:, :4000]
     L_dev, g_dev, am = _gpu_template_grad(mg, device, sc, Y)
-    L_ref, g_ref = _oracle_grad_at(sc, Y, am)
+    L_ref, g_ref = oracle_grad_at(sc.verts0, sc.faces, sc.binding, Y, am)
     assert L_dev == pytest.approx(L_ref, rel=1e-5)
-    assert _normwise(g_dev, g_ref) <= 1e-5
+    assert normwise(g_dev, g_ref) <= 1e-5
 
 
 def test_binding_backward_all_outputs(device):
@@ -131,7 +106,7 @@ def test_binding_backward_all_outputs(device):
                                          b["q_local"], b["log_scale"], dev(off, device), dev(gm, device),
                                          dev(gr, device), dev(gc, device))
     ref = olo.binding_vjp(V, sc.faces, sc.binding, gm, gr.reshape(3, 3, G).transpose(2, 0, 1), gc, offset=off)
-    assert _normwise(host(g), ref) <= 1e-5
+    assert normwise(host(g), ref) <= 1e-5
 
 
 def test_adam_parity(device):
