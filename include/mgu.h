@@ -351,7 +351,10 @@ typedef struct mg_batch_scene {
     const float *log_scale;     /* [3][n_gauss] */
     const float *queries;       /* [3][n_queries] */
     int32_t n_queries;
-    int32_t reserved0;
+    int32_t batch;              /* this scene's queries per wave (1, 2, 4, 8, 16); 0: the plan's */
+    int32_t seed;               /* this scene's seed descent: 0 off, 1 on, -1: the plan's */
+    int32_t query_tile;         /* this scene's queries per work item, a multiple of 4 * its
+                                   batch; 0: the plan's */
     const void *bvh;            /* MG_PRIM_TRIANGLES BVH built over this scene's faces: only
                                    its topology is used, its boxes are untouched */
     size_t bvh_bytes;
@@ -367,6 +370,8 @@ typedef struct mg_batch_scene {
     float *normal;              /* out [n_frames][3][n_queries] or NULL */
 } mg_batch_scene;
 
+/* Plan-wide defaults; a scene's own batch / seed / query_tile fields override
+ * them (the autotuner picks the traversal per scene). */
 typedef struct mg_batch_options {
     int32_t batch;              /* queries per wave of the batch traversal: 1, 2, 4, 8, 16 (0: 4) */
     int32_t seed;               /* greedy seed descent: 0 off, otherwise on */

@@ -45,7 +45,7 @@ class QueryOptions(ctypes.Structure):
 class BatchScene(ctypes.Structure):
     _fields_ = [("frames", P), ("n_frames", I32), ("n_verts", I32), ("faces", P), ("n_faces", I32),
                 ("n_gauss", I32), ("gface", P), ("bary", P), ("q_local", P), ("log_scale", P),
-                ("queries", P), ("n_queries", I32), ("reserved0", I32), ("bvh", P), ("bvh_bytes", SZ),
+                ("queries", P), ("n_queries", I32), ("batch", I32), ("seed", I32), ("query_tile", I32), ("bvh", P), ("bvh_bytes", SZ),
                 ("nodes", P), ("roots", P), ("mean", P), ("quat", P), ("cov", P), ("face", P),
                 ("point", P), ("qbary", P), ("dist2", P), ("normal", P)]
 

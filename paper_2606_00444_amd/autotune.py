@@ -117,3 +117,47 @@ def options(res, order=None):
     if res.get("order") == "order":
         kw["order"] = order
     return kw
+
+
+BATCH_CANDIDATES = [("batch", b, s) for b in (1, 2, 4, 8, 16) for s in (False, True)]
+BATCH_TILES = [(g, q) for g in (1024, 2048, 4096) for q in (128, 256, 512, 1024)]
+
+
+def tune_batch(plan, reps=3, use_cache=True):
+    """Choose the batched launch's options and apply them to plan (a BatchPlan).
+
+    Per scene: queries per wave and seed descent, by timing the plain
+    closest-point traversal (the same device code) of the scene's queries on
+    its frame 0.  Plan-wide: the Gaussian and query tile sizes, by timing whole
+    runs of the plan.  Returns {"per_scene", "gauss_tile", "query_tile", "ms",
+    "timings"} and leaves the plan configured with the best choice.
+    """
+    per_scene = []
+    for sc in plan.scenes:
+        V = sc["frames"][0].contiguous()
+        bvh = api.lbvh_build(V, sc["faces"])
+        r = tune_closest(bvh, V, sc["queries"], normal=True, reps=reps, use_cache=use_cache,
+                         candidates=BATCH_CANDIDATES)
+        per_scene.append({"batch": r["batch"], "seed": r["seed"]})
+    sizes = ",".join(f"{s['faces'].shape[1]}x{s['frames'].shape[0]}x{s['gface'].shape[0]}x{s['queries'].shape[1]}"
+                     for s in plan.scenes)
+    picks = ",".join(f"{p['batch']}{int(p['seed'])}" for p in per_scene)
+    dev = torch.cuda.get_device_properties(plan.plan.device)
+    key = f"{getattr(dev, 'gcnArchName', dev.name)}|batchplan|{sizes}|{picks}"
+    cache = _load_cache() if use_cache else {}
+    if key in cache:
+        res = cache[key]
+    else:
+        timings = {}
+        for g, q in BATCH_TILES:
+            plan.configure(gauss_tile=g, query_tile=q, per_scene=per_scene)
+            timings[f"{g}/{q}"] = _graph_time(plan.run, reps)
+        best = min(timings, key=timings.get)
+        g, q = (int(x) for x in best.split("/"))
+        res = {"per_scene": per_scene, "gauss_tile": g, "query_tile": q, "ms": timings[best], "timings": timings}
+        if use_cache:
+            cache = _load_cache()
+            cache[key] = res
+            _store_cache(cache)
+    plan.configure(gauss_tile=res["gauss_tile"], query_tile=res["query_tile"], per_scene=res["per_scene"])
+    return res

@@ -18,9 +18,11 @@ class BatchPlan:
     scenes: list of dicts with device tensors
       frames [T][3][V] float32, faces [3][F] int32, gface [G] int32, bary [2][G],
       q_local [4][G], log_scale [3][G], queries [3][Q] float32,
-      and optionally bvh (a triangle LBVH over the faces; built from frame 0 if absent).
-    Options: batch (queries per wave), seed, gauss_tile, query_tile - the knobs
-    the autotuner chooses.  After run(), out[i] holds scene i's per-frame outputs.
+      and optionally bvh (a triangle LBVH over the faces; built from frame 0 if absent)
+      and this scene's traversal: batch (queries per wave), seed, query_tile.
+    Options: the plan-wide defaults of batch, seed and query_tile, and
+    gauss_tile.  autotune.tune_batch chooses all of them.  After run(), out[i]
+    holds scene i's per-frame outputs.
     """
 
     def __init__(self, scenes, *, batch=4, seed=True, gauss_tile=2048, query_tile=256, normals=True):
@@ -58,14 +60,29 @@ class BatchPlan:
         size = ctypes.c_size_t()
         _call("mg_batch_plan_size", ctypes.byref(arr), len(scenes), ctypes.byref(size))
         self.plan = torch.empty(size.value, dtype=torch.uint8, device=scenes[0]["frames"].device)
-        opt = _lib.BatchOptions()
-        opt.batch, opt.seed, opt.gauss_tile, opt.query_tile = int(batch), int(bool(seed)), int(gauss_tile), int(query_tile)
-        self.options = {"batch": batch, "seed": seed, "gauss_tile": gauss_tile, "query_tile": query_tile}
-        _call("mg_batch_plan_init", ctypes.byref(arr), len(scenes), ctypes.byref(opt), _ptr(self.plan),
-              self.plan.numel(), _stream())
+        self.configure(batch=batch, seed=seed, gauss_tile=gauss_tile, query_tile=query_tile)
         st = ctypes.c_void_p()
         _call("mg_batch_status_word", _ptr(self.plan), ctypes.byref(st))
         self._status_off = st.value - self.plan.data_ptr()
+
+    def configure(self, *, batch=4, seed=True, gauss_tile=2048, query_tile=256, per_scene=None):
+        """(Re)write the device plan with new plan-wide defaults and, optionally,
+        per-scene traversal overrides per_scene[i] = {batch, seed, query_tile}
+        (synchronises the stream; outputs and plan buffer are reused)."""
+        arr = self._arr
+        for i, sc in enumerate(self.scenes):
+            o = dict(sc)
+            if per_scene is not None:
+                o.update(per_scene[i])
+            arr[i].batch = int(o.get("batch") or 0)
+            arr[i].seed = -1 if o.get("seed") is None else int(bool(o["seed"]))
+            arr[i].query_tile = int(o.get("query_tile") or 0)
+        opt = _lib.BatchOptions()
+        opt.batch, opt.seed, opt.gauss_tile, opt.query_tile = int(batch), int(bool(seed)), int(gauss_tile), int(query_tile)
+        self.options = {"batch": batch, "seed": seed, "gauss_tile": gauss_tile, "query_tile": query_tile,
+                        "per_scene": per_scene}
+        _call("mg_batch_plan_init", ctypes.byref(arr), len(self.scenes), ctypes.byref(opt), _ptr(self.plan),
+              self.plan.numel(), _stream())
 
     def run(self):
         """Enqueue one run over every scene-frame on torch's current stream."""

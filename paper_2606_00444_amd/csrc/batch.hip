@@ -35,6 +35,7 @@ struct PlanScene {
     const float4 *topo;                     // the scene BVH's records (child references)
     uint32_t *top_scratch;                  // [n_frames][7][n_top] when n_top > kBatchTopLds, else null
     int32_t n_top_host;                     // n_top read at plan time
+    int32_t batch, seed, query_tile;        // this scene's traversal (plan defaults resolved)
     int32_t chunk_log2;
     int32_t sf_base;                        // index of (this scene, frame 0) among all scene-frames
     int64_t n_chunks, g_tiles, q_tiles;     // items per frame
@@ -218,10 +219,10 @@ __global__ __launch_bounds__(kBlock) void batch_persistent_kernel(PlanHeader *h)
             signal(&refit_done[sf], 1u);
         } else {
             wait_for(&refit_done[sf], 1u, &h->status);
-            const QueryArgs q = query_args(P, t, r, h->seed);
-            const int64_t q0 = k * h->query_tile;
-            const int64_t q1 = q0 + h->query_tile < q.nq ? q0 + h->query_tile : q.nq;
-            switch (h->batch) {
+            const QueryArgs q = query_args(P, t, r, P.seed);
+            const int64_t q0 = k * P.query_tile;
+            const int64_t q1 = q0 + P.query_tile < q.nq ? q0 + P.query_tile : q.nq;
+            switch (P.batch) {
                 case 1: query_tile<1>(q, q0, q1, smem); break;
                 case 2: query_tile<2>(q, q0, q1, smem); break;
                 case 8: query_tile<8>(q, q0, q1, smem); break;
@@ -306,6 +307,12 @@ extern "C" mg_status mg_batch_plan_init(const mg_batch_scene *scenes, int32_t n_
         if (s.bvh_bytes < static_cast<size_t>(L.total_bytes)) return MG_ERR_WORKSPACE_TOO_SMALL;
         PlanScene &P = h.scenes[i];
         P.s = s;
+        P.batch = s.batch == 0 ? batch : s.batch;
+        P.seed = s.seed < 0 ? (o.seed != 0) : (s.seed != 0);
+        P.query_tile = s.query_tile == 0 ? qtile : s.query_tile;
+        if (!(P.batch == 1 || P.batch == 2 || P.batch == 4 || P.batch == 8 || P.batch == 16) || s.seed < -1 ||
+            s.seed > 1 || P.query_tile <= 0 || P.query_tile % (4 * P.batch) != 0)
+            return MG_ERR_INVALID_ARGUMENT;
         const char *b = static_cast<const char *>(s.bvh);
         P.leaf_faces = reinterpret_cast<const int32_t *>(b + L.off_leaf_faces);
         P.prim = reinterpret_cast<const int32_t *>(b + L.off_prim);
@@ -328,7 +335,7 @@ extern "C" mg_status mg_batch_plan_init(const mg_batch_scene *scenes, int32_t n_
         P.sf_base = static_cast<int32_t>(sf);
         P.n_chunks = (s.n_faces + (int64_t(1) << c) - 1) >> c;
         P.g_tiles = (s.n_gauss + gtile - 1) / gtile;
-        P.q_tiles = (s.n_queries + qtile - 1) / qtile;
+        P.q_tiles = (s.n_queries + P.query_tile - 1) / P.query_tile;
         sf += s.n_frames;
     }
     h.total_sf = static_cast<int32_t>(sf);

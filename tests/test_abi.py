@@ -78,3 +78,29 @@ def test_argument_errors_before_any_hip_call(lib):
     assert lib.mg_adam_step(fake, fake, fake, fake, 10, 0, ctypes.c_float(1e-3), ctypes.c_float(0.9),
                             ctypes.c_float(0.999), ctypes.c_float(1e-8), None) == 1
     assert lib.mg_mean(fake, 10, fake, None, 0, None) == 2
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors have the C structs' sizes and field offsets (gcc on the header)."""
+    import subprocess
+    from paper_2606_00444_amd import _lib
+    structs = {"mg_lbvh_layout": _lib.LbvhLayout, "mg_query_options": _lib.QueryOptions,
+               "mg_batch_scene": _lib.BatchScene, "mg_batch_options": _lib.BatchOptions}
+    lines = ['#include <stdio.h>', '#include "mgu.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0; }"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        c, f, v = line.split()
+        got[(c, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

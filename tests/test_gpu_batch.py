@@ -38,10 +38,11 @@ def _plain_frame(mg, s, t, opts):
 
 
 def _compare(mg, scenes, plan, opts):
+    """opts: the traversal options of every scene (dict) or of each scene (list)."""
     for i, (s, sc, fr) in enumerate(scenes):
         o = plan.out[i]
         for t in range(fr.shape[0]):
-            bvh, g, q = _plain_frame(mg, s, t, opts)
+            bvh, g, q = _plain_frame(mg, s, t, opts[i] if isinstance(opts, list) else opts)
             # refit: boxes, child references and leaf triangles bitwise
             ref = decode_bvh(bvh)
             view = bvh.buf.clone()
@@ -77,6 +78,37 @@ def test_batched_equals_plain(device, batch, seed, gtile, qtile):
     torch.cuda.synchronize()
     assert plan.status() == 0
     _compare(mg, scenes, plan, {"batch": batch, "seed": seed})
+
+
+def test_batched_per_scene_options(device):
+    """Each scene's own traversal (queries per wave, seed, tile) overrides the plan's."""
+    import paper_2606_00444_amd as mg
+    from paper_2606_00444_amd.batch import BatchPlan
+    scenes = _scenes(device)
+    per = [{"batch": 1, "seed": False, "query_tile": 64}, {"batch": 16, "seed": True, "query_tile": 512}, {}]
+    plan = BatchPlan([s for s, _, _ in scenes], batch=2, seed=False, gauss_tile=1024, query_tile=128)
+    plan.configure(batch=2, seed=False, gauss_tile=1024, query_tile=128, per_scene=per)
+    plan.run()
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    _compare(mg, scenes, plan, [{"batch": 1, "seed": False}, {"batch": 16, "seed": True}, {"batch": 2, "seed": False}])
+
+
+def test_batched_autotuned(device, tmp_path, monkeypatch):
+    import paper_2606_00444_amd as mg
+    from paper_2606_00444_amd import autotune
+    from paper_2606_00444_amd.batch import BatchPlan
+    monkeypatch.setenv("MGU_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    scenes = _scenes(device, frames=2)
+    plan = BatchPlan([s for s, _, _ in scenes])
+    res = autotune.tune_batch(plan, reps=2)
+    assert len(res["per_scene"]) == 3 and len(res["timings"]) == len(autotune.BATCH_TILES)
+    again = autotune.tune_batch(plan, reps=2)                    # from the cache
+    assert again["per_scene"] == res["per_scene"] and again["query_tile"] == res["query_tile"]
+    plan.run()
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    _compare(mg, scenes, plan, [dict(p) for p in res["per_scene"]])
 
 
 def test_batched_uneven_full_size_scenes_sampled(device):
