@@ -153,10 +153,16 @@ mg_status mg_mesh_gaussian_update_backward(const float *verts, int32_t n_verts, 
  *                                ref (int bits): >= 0 internal node, < 0 leaf ~ref;
  *                                id: original primitive id.  A leaf's box is the
  *                                min/max of its vertices; refit rewrites all of it.
- *   node_aux    int32  [n-1]     refit schedule: index among the "top" nodes (whose
- *                                leaf range crosses a refit chunk boundary), or -1
- *   top_nodes   int32  [n]       the top nodes (header.n_top of them)
- *   top_scratch uint32 [7][n]    second-phase refit scratch when n_top is large
+ *   node_aux    int32  [n-1]     refit schedule: index among the "top" nodes (those
+ *                                with more than 2^chunk_log2 leaves), or -1
+ *   top_nodes   int32  [n]       node id of each top node (header.n_top of them)
+ *   top_child   int32  [2][n]    per top node and slot: the child's top index, or -1
+ *                                when the child roots a subtree
+ *   subtrees    int32  [3][n]    per subtree (header.n_sub): root reference, first
+ *                                and last leaf; the subtrees (at most 2^chunk_log2
+ *                                leaves, children of top nodes) cut the tree
+ *   top_box     float  [2][6][n] refit scratch: subtree-root boxes per top node slot
+ *   top_scratch uint32 [10][n]   second-phase refit scratch when n_top is large
  * ---------------------------------------------------------------------- */
 
 typedef struct mg_lbvh_header {
@@ -172,9 +178,10 @@ typedef struct mg_lbvh_header {
     float quant_scale[3];
     uint32_t bounds_enc[6];/* build scratch: order-preserving encodings of lo/hi */
     uint32_t tile_counter[4];
-    int32_t chunk_log2;    /* refit chunk: 2^chunk_log2 consecutive leaves per workgroup */
+    int32_t chunk_log2;    /* refit: subtrees of at most 2^chunk_log2 leaves */
     int32_t n_top;         /* number of top nodes */
-    int32_t reserved[10];
+    int32_t n_sub;         /* number of subtrees (n_top + 1 when n > 2^chunk_log2) */
+    int32_t reserved[9];
 } mg_lbvh_header;
 
 typedef struct mg_lbvh_layout {
@@ -188,6 +195,9 @@ typedef struct mg_lbvh_layout {
     int64_t off_nodes;
     int64_t off_node_aux;
     int64_t off_top_nodes;
+    int64_t off_top_child;
+    int64_t off_subtrees;
+    int64_t off_top_box;
     int64_t off_top_scratch;
 } mg_lbvh_layout;
 
@@ -208,7 +218,10 @@ mg_status mg_lbvh_build(const float *verts, int32_t n_verts, const int32_t *face
                         void *stream);
 
 /* Refit in place: recompute every box of a built BVH for new vertex positions
- * (same n_prims and prim_kind as the build; topology unchanged). */
+ * (same n_prims and prim_kind as the build; topology unchanged).  Two
+ * kernels: a workgroup per subtree, then one workgroup for the top nodes.
+ * Refits (and builds) of one BVH must not run concurrently: they share its
+ * scratch sections. */
 mg_status mg_lbvh_refit(const float *verts, int32_t n_verts, void *bvh, size_t bvh_bytes,
                         int32_t n_prims, int32_t prim_kind, void *stream);
 

@@ -24,21 +24,24 @@ namespace mgu {
 namespace {
 
 constexpr int kBlock = 256;                 // 4 waves
-constexpr int kBatchTopLds = 1024;          // top nodes per scene in the batched refit
+constexpr int kBatchTopLds = 768;           // top nodes per scene kept in LDS by the batched refit
+constexpr int kBatchMaxChunkLog2 = 10;      // subtrees of up to 1024 leaves (scenes up to 524,288 faces)
 constexpr int kMaxScenes = 64;
 constexpr int kSpin = 1 << 22;
 
 struct PlanScene {
     mg_batch_scene s;
     const int32_t *leaf_faces, *prim, *leaf_parent, *node_parent, *node_aux, *top_nodes;
-    const int32_t *n_top;
-    const float4 *topo;                     // the scene BVH's records (child references)
-    uint32_t *top_scratch;                  // [n_frames][7][n_top] when n_top > kBatchTopLds, else null
-    int32_t n_top_host;                     // n_top read at plan time
+    const int32_t *top_child, *subtrees;
+    const int32_t *n_top, *n_sub;           // the scene BVH's counts (device)
+    float *top_box;                         // [n_frames][2][6][n_top] deposited subtree-root boxes
+    uint32_t *top_scratch;                  // [n_frames][10][n_top] when n_top > kBatchTopLds, else null
+    int32_t n_top_host, n_sub_host;         // counts read at plan time
     int32_t batch, seed, query_tile;        // this scene's traversal (plan defaults resolved)
     int32_t chunk_log2;
     int32_t sf_base;                        // index of (this scene, frame 0) among all scene-frames
-    int64_t n_chunks, g_tiles, q_tiles;     // items per frame
+    int32_t pad;
+    int64_t n_chunks, g_tiles, q_tiles;     // items per frame (n_chunks: subtrees)
     int64_t first[4];                       // first item of this scene in each phase
 };
 
@@ -52,18 +55,38 @@ struct PlanHeader {
     PlanScene scenes[kMaxScenes];
 };
 
-// Number of top nodes of a built BVH (read from its device header).
-inline mg_status read_n_top(const mg_batch_scene &s, int32_t &T) {
+// Refit schedule of a built BVH (read from its device header): top nodes,
+// subtrees and the subtree size bound.
+struct Schedule {
+    int32_t n_top, n_sub, chunk_log2;
+};
+
+inline mg_status read_schedule(const mg_batch_scene &s, Schedule &S) {
     mg_lbvh_layout L;
     if (mg_lbvh_layout_query(s.n_faces, MG_PRIM_TRIANGLES, &L) != MG_OK) return MG_ERR_INVALID_ARGUMENT;
     const char *b = static_cast<const char *>(s.bvh);
-    const mg_lbvh_header *hdr = reinterpret_cast<const mg_lbvh_header *>(b + L.off_header);
-    if (hipMemcpy(&T, &hdr->n_top, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) return MG_ERR_HIP;
-    return (T >= 0 && T < s.n_faces + 1) ? MG_OK : MG_ERR_INVALID_ARGUMENT;
+    mg_lbvh_header hdr;
+    if (hipMemcpy(&hdr, b + L.off_header, sizeof(hdr), hipMemcpyDeviceToHost) != hipSuccess) return MG_ERR_HIP;
+    S.n_top = hdr.n_top;
+    S.n_sub = hdr.n_sub;
+    S.chunk_log2 = hdr.chunk_log2;
+    if (hdr.n_prims != s.n_faces || hdr.prim_kind != MG_PRIM_TRIANGLES || hdr.status != 0)
+        return MG_ERR_TOPOLOGY_MISMATCH;
+    if (S.n_top < 0 || S.n_top >= s.n_faces || S.n_sub < 1 || S.n_sub > s.n_faces)
+        return MG_ERR_INVALID_ARGUMENT;
+    // the batched kernel keeps a subtree's phase-1 state in its fixed LDS
+    if (S.chunk_log2 < 8 || S.chunk_log2 > kBatchMaxChunkLog2) return MG_ERR_INVALID_ARGUMENT;
+    return MG_OK;
 }
 
-// Plan layout: header, 2 x total_sf dependency counters, then second-phase
-// refit scratch for every scene whose top nodes exceed the LDS capacity.
+// Scratch words of one frame of a scene: deposited boxes, and second-phase
+// state when the top nodes exceed the LDS capacity.
+inline int64_t frame_scratch_words(int32_t T) {
+    return 12 * static_cast<int64_t>(T) + (T > kBatchTopLds ? 10 * static_cast<int64_t>(T) : 0);
+}
+
+// Plan layout: header, 2 x total_sf dependency counters, then per scene-frame
+// refit scratch.
 inline int64_t align256b(int64_t x) { return (x + 255) & ~int64_t(255); }
 
 inline int64_t plan_bytes_for(int64_t total_sf, int64_t scratch_words) {
@@ -120,13 +143,17 @@ __device__ RefitArgs refit_args(const PlanScene &P, int64_t t, PlanHeader *h) {
     a.leaf_parent = P.leaf_parent;
     a.node_parent = P.node_parent;
     a.nodes = reinterpret_cast<float4 *>(s.nodes + t * 24 * static_cast<int64_t>(s.n_faces > 1 ? s.n_faces - 1 : 0));
-    a.topo = P.topo;
     a.node_aux = P.node_aux;
     a.top_nodes = P.top_nodes;
-    a.top_scratch = nullptr;
+    a.top_child = P.top_child;
+    a.subtrees = P.subtrees;
+    a.tstride = P.n_top_host;
+    a.top_box = P.top_box + t * 12 * static_cast<int64_t>(P.n_top_host);
+    a.top_scratch = P.top_scratch ? P.top_scratch + t * 10 * static_cast<int64_t>(P.n_top_host) : nullptr;
     a.root = s.roots + 8 * t;
     a.status = &h->status;
     a.n_top = P.n_top;
+    a.n_sub = P.n_sub;
     a.n = s.n_faces;
     a.chunk_log2 = P.chunk_log2;
     return a;
@@ -164,8 +191,9 @@ __device__ void query_tile(const QueryArgs &q, int64_t q0, int64_t q1, unsigned 
     batch_loop<true, M>(q, q0 + static_cast<int64_t>(w) * M, static_cast<int64_t>(kBlock / 64) * M, q1, stacks[w]);
 }
 
-constexpr size_t kSmemBytes = 7 * 4 * kBatchTopLds > 4 * sizeof(WaveStack<16>) ? 7 * 4 * kBatchTopLds
-                                                                                 : 4 * sizeof(WaveStack<16>);
+constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
+constexpr size_t kSmemBytes = cmax(cmax(refit_top_lds(kBatchTopLds), refit_sub_lds(int64_t(1) << kBatchMaxChunkLog2)),
+                                   4 * sizeof(WaveStack<16>));
 
 __global__ __launch_bounds__(kBlock) void batch_persistent_kernel(PlanHeader *h) {
     __shared__ __align__(16) unsigned char smem[kSmemBytes];
@@ -191,8 +219,7 @@ __global__ __launch_bounds__(kBlock) void batch_persistent_kernel(PlanHeader *h)
         const int sf = P.sf_base + static_cast<int>(t);
         const RefitArgs r = refit_args(P, t, h);
         if (phase == 0) {
-            uint32_t *cnt = reinterpret_cast<uint32_t *>(smem);
-            refit_chunk<true>(r, k, cnt);
+            refit_subtree<true>(r, k, smem);
             signal(&done_chunks[sf], 1u);
         } else if (phase == 1) {
             const mg_batch_scene &s = P.s;
@@ -207,14 +234,12 @@ __global__ __launch_bounds__(kBlock) void batch_persistent_kernel(PlanHeader *h)
         } else if (phase == 2) {
             wait_for(&done_chunks[sf], static_cast<uint32_t>(P.n_chunks), &h->status);
             const int T = *P.n_top;
-            if (T > 0 && T <= kBatchTopLds) {
-                uint32_t *cnt = reinterpret_cast<uint32_t *>(smem);
-                refit_top_body<true>(r, T, cnt, cnt + kBatchTopLds, kBatchTopLds);
-            } else if (T > kBatchTopLds && P.top_scratch && T <= P.n_top_host) {
-                uint32_t *cnt = P.top_scratch + t * 7 * static_cast<int64_t>(P.n_top_host);
-                refit_top_body<true>(r, T, cnt, cnt + P.n_top_host, P.n_top_host);
-            } else if (T > 0) {
-                if (threadIdx.x == 0) atomicOr(&h->status, 2);
+            if (T != P.n_top_host) {
+                if (threadIdx.x == 0) atomicOr(&h->status, 2);   // the BVH was rebuilt after planning
+            } else if (T > 0 && T <= kBatchTopLds) {
+                refit_top<true>(r, T, reinterpret_cast<uint32_t *>(smem), kBatchTopLds);
+            } else if (T > kBatchTopLds) {
+                refit_top<true>(r, T, r.top_scratch, T);
             }
             signal(&refit_done[sf], 1u);
         } else {
@@ -244,15 +269,15 @@ int64_t total_frames(const mg_batch_scene *scenes, int32_t n) {
 
 using namespace mgu;
 
-// Scratch words for the second refit phase of every scene with more top nodes than fit in LDS.
+// Refit scratch words of every scene-frame.
 inline mg_status scratch_words(const mg_batch_scene *scenes, int32_t n_scenes, int64_t &words) {
     words = 0;
     for (int i = 0; i < n_scenes; ++i) {
         if (!scenes[i].bvh || scenes[i].n_faces < 1) return MG_ERR_INVALID_ARGUMENT;
-        int32_t T = 0;
-        const mg_status st = read_n_top(scenes[i], T);
+        Schedule S;
+        const mg_status st = read_schedule(scenes[i], S);
         if (st != MG_OK) return st;
-        if (T > kBatchTopLds) words += static_cast<int64_t>(scenes[i].n_frames) * 7 * T;
+        words += static_cast<int64_t>(scenes[i].n_frames) * frame_scratch_words(S.n_top);
     }
     return MG_OK;
 }
@@ -320,20 +345,26 @@ extern "C" mg_status mg_batch_plan_init(const mg_batch_scene *scenes, int32_t n_
         P.node_parent = reinterpret_cast<const int32_t *>(b + L.off_node_parent);
         P.node_aux = reinterpret_cast<const int32_t *>(b + L.off_node_aux);
         P.top_nodes = reinterpret_cast<const int32_t *>(b + L.off_top_nodes);
+        P.top_child = reinterpret_cast<const int32_t *>(b + L.off_top_child);
+        P.subtrees = reinterpret_cast<const int32_t *>(b + L.off_subtrees);
         P.n_top = &reinterpret_cast<const mg_lbvh_header *>(b + L.off_header)->n_top;
-        P.topo = reinterpret_cast<const float4 *>(b + L.off_nodes);
-        st = read_n_top(s, P.n_top_host);
+        P.n_sub = &reinterpret_cast<const mg_lbvh_header *>(b + L.off_header)->n_sub;
+        Schedule S;
+        st = read_schedule(s, S);
         if (st != MG_OK) return st;
+        P.n_top_host = S.n_top;
+        P.n_sub_host = S.n_sub;
+        P.chunk_log2 = S.chunk_log2;
+        // per-frame scratch: [n_frames][12][T] deposited boxes, then [n_frames][10][T] phase-2 state
+        P.top_box = reinterpret_cast<float *>(scratch);
+        scratch += static_cast<int64_t>(s.n_frames) * 12 * S.n_top;
         P.top_scratch = nullptr;
-        if (P.n_top_host > kBatchTopLds) {
+        if (S.n_top > kBatchTopLds) {
             P.top_scratch = scratch;
-            scratch += static_cast<int64_t>(s.n_frames) * 7 * P.n_top_host;
+            scratch += static_cast<int64_t>(s.n_frames) * 10 * S.n_top;
         }
-        int c = 8;
-        while ((int64_t(1) << c) * 256 < s.n_faces && c < 12) ++c;   // the build's chunk rule
-        P.chunk_log2 = c;
         P.sf_base = static_cast<int32_t>(sf);
-        P.n_chunks = (s.n_faces + (int64_t(1) << c) - 1) >> c;
+        P.n_chunks = S.n_sub;
         P.g_tiles = (s.n_gauss + gtile - 1) / gtile;
         P.q_tiles = (s.n_queries + P.query_tile - 1) / P.query_tile;
         sf += s.n_frames;

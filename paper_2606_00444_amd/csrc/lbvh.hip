@@ -15,13 +15,11 @@
 //            pass, tiles ranked with wave64 ballots (match masks over the 8
 //            digit bits), global digit offsets by decoupled look-back
 //   tree     Karras radix tree per internal node + leaf permutation of faces;
-//            marks the "top" nodes whose leaf range crosses a refit chunk
-//   refit    two phases.  Internal nodes of a Karras tree cover contiguous leaf
-//            ranges, so every node whose range lies inside one chunk of
-//            2^chunk_log2 leaves is refit by the workgroup owning that chunk,
-//            with arrival counters in LDS (workgroup scope, no cross-XCD
-//            traffic).  The few top nodes are then finished by one workgroup,
-//            again with LDS counters and LDS atomic min/max accumulators.
+//            lists the subtrees of at most C leaves that cut the tree and the
+//            "top" nodes above them, then links each top node to its parent
+//   refit    two kernels: a workgroup per subtree refits it with counters,
+//            boxes and parent links in LDS, then one workgroup finishes the
+//            top nodes in rounds (see refit.hpp)
 //
 // Node records are child-centric (96 B: both children's boxes, or a leaf
 // child's triangle itself) so a traversal step reads one record and a leaf
@@ -54,16 +52,20 @@ inline mg_lbvh_layout make_layout(int64_t n, int kind) {
     L.off_nodes = o;       o += align256(96 * m);
     L.off_node_aux = o;    o += align256(4 * m);
     L.off_top_nodes = o;   o += align256(4 * n);
-    L.off_top_scratch = o; o += align256(28 * n);
+    L.off_top_child = o;   o += align256(8 * n);
+    L.off_subtrees = o;    o += align256(12 * n);
+    L.off_top_box = o;     o += align256(48 * n);
+    L.off_top_scratch = o; o += align256(40 * n);
     L.total_bytes = o;
     return L;
 }
 
-// Refit chunk: the smallest power of two >= 256 leaves that gives at most
-// about 256 chunks (one workgroup each), capped at 4096 leaves.
+// Largest subtree C = 2^chunk_log2 leaves: the smallest power of two >= 256
+// with n <= 512 C (a few hundred subtrees, so the top tree stays small),
+// capped at 2048 (the phase-1 LDS state is 32 B per leaf).
 inline int chunk_log2_for(int64_t n) {
     int c = 8;
-    while ((int64_t(1) << c) * 256 < n && c < 12) ++c;
+    while ((int64_t(512) << c) < n && c < 11) ++c;
     return c;
 }
 
@@ -112,6 +114,7 @@ __global__ void build_init_kernel(mg_lbvh_header *hdr, uint32_t *hist, uint32_t 
         for (int k = 0; k < 4; ++k) hdr->tile_counter[k] = 0;
         hdr->chunk_log2 = chunk_log2;
         hdr->n_top = 0;
+        hdr->n_sub = 0;
     }
 }
 
@@ -380,6 +383,7 @@ __global__ __launch_bounds__(256) void hierarchy_kernel(const uint32_t *__restri
                                                         int32_t *__restrict__ node_parent,
                                                         int32_t *__restrict__ node_aux,
                                                         int32_t *__restrict__ top_nodes,
+                                                        int32_t *__restrict__ subtrees,
                                                         float *__restrict__ nodes,
                                                         mg_lbvh_header *hdr, int chunk_log2) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -392,6 +396,10 @@ __global__ __launch_bounds__(256) void hierarchy_kernel(const uint32_t *__restri
     }
     if (n == 1) {
         leaf_parent[0] = -1;
+        subtrees[0] = ~0;         // the one leaf is the one subtree
+        subtrees[1] = 0;
+        subtrees[2] = 0;
+        hdr->n_sub = 1;
         return;
     }
     if (i >= n - 1) return;
@@ -420,29 +428,67 @@ __global__ __launch_bounds__(256) void hierarchy_kernel(const uint32_t *__restri
     // rewrites the same values, so they are valid before any box exists
     nodes[24 * i + 3] = __int_as_float(static_cast<int32_t>(lo == gamma ? ~gamma : gamma));
     nodes[24 * i + 15] = __int_as_float(static_cast<int32_t>(hi == gamma + 1 ? ~(gamma + 1) : gamma + 1));
-    // top node: its leaf range crosses a chunk boundary (slot order is irrelevant)
-    if ((lo >> chunk_log2) != (hi >> chunk_log2)) {
+    // the cut: a node with more than C leaves is a top node, and each of its
+    // children with at most C leaves roots a subtree (list order is irrelevant)
+    const int64_t C = int64_t(1) << chunk_log2;
+    if (hi - lo + 1 > C) {
         const int32_t t = static_cast<int32_t>(atomicAdd(reinterpret_cast<uint32_t *>(&hdr->n_top), 1u));
         top_nodes[t] = static_cast<int32_t>(i);
         node_aux[i] = t;
+        const int64_t cf[2] = {lo, gamma + 1}, cl[2] = {gamma, hi};
+        for (int c = 0; c < 2; ++c) {
+            if (cl[c] - cf[c] + 1 > C) continue;
+            const int32_t k = static_cast<int32_t>(atomicAdd(reinterpret_cast<uint32_t *>(&hdr->n_sub), 1u));
+            const bool leaf = cl[c] == cf[c];
+            subtrees[k] = static_cast<int32_t>(leaf ? ~cf[c] : (c == 0 ? gamma : gamma + 1));
+            subtrees[n + k] = static_cast<int32_t>(cf[c]);
+            subtrees[2 * n + k] = static_cast<int32_t>(cl[c]);
+        }
     } else {
         node_aux[i] = -1;
+        if (i == 0) {             // the whole tree is one subtree
+            atomicAdd(reinterpret_cast<uint32_t *>(&hdr->n_sub), 1u);
+            subtrees[0] = 0;
+            subtrees[n] = 0;
+            subtrees[2 * n] = static_cast<int32_t>(n - 1);
+        }
     }
 }
 
-template <bool kTri>
-__global__ __launch_bounds__(256) void refit_local_kernel(RefitArgs a) {
-    extern __shared__ uint32_t s_cnt[];
-    refit_chunk<kTri>(a, blockIdx.x, s_cnt);
+// Per top node and slot: the child's top index, or -1 when the child roots a subtree.
+__global__ __launch_bounds__(256) void top_child_kernel(const int32_t *__restrict__ node_aux,
+                                                        const int32_t *__restrict__ top_nodes,
+                                                        const float *__restrict__ nodes, int64_t n,
+                                                        int32_t *__restrict__ top_child, mg_lbvh_header *hdr) {
+    const int T = hdr->n_top;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < T; t += gridDim.x * blockDim.x) {
+        const int32_t p = top_nodes[t];
+        if (p < 0 || p >= n - 1) { atomicOr(&hdr->status, 8); continue; }
+        for (int s = 0; s < 2; ++s) {
+            const int32_t ref = __float_as_int(nodes[24 * static_cast<int64_t>(p) + 12 * s + 3]);
+            top_child[s * n + t] = (ref >= 0 && ref < n - 1 && node_aux[ref] >= 0) ? node_aux[ref] : -1;
+        }
+    }
 }
 
+// Phase 1: workgroups take subtrees.
+template <bool kTri>
+__global__ __launch_bounds__(256) void refit_sub_kernel(RefitArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int32_t ns = *a.n_sub;
+    for (int64_t k = blockIdx.x; k < ns; k += gridDim.x) {
+        refit_subtree<kTri>(a, k, smem);
+        __syncthreads();          // LDS is reused by the next subtree
+    }
+}
+
+// Phase 2: one workgroup, one top node per thread while they fit in LDS.
 template <bool kTri>
 __global__ __launch_bounds__(1024) void refit_top_kernel(RefitArgs a) {
-    __shared__ uint32_t s_cnt[kTopLds];
-    __shared__ uint32_t s_box[6 * kTopLds];
+    extern __shared__ __align__(16) unsigned char smem[];
     const int T = *a.n_top;
-    if (T <= kTopLds) refit_top_body<kTri>(a, T, s_cnt, s_box, kTopLds);
-    else refit_top_body<kTri>(a, T, a.top_scratch, a.top_scratch + a.n, a.n);
+    if (T > 0 && T <= kTopLds) refit_top<kTri>(a, T, reinterpret_cast<uint32_t *>(smem), kTopLds);
+    else if (T > kTopLds) refit_top<kTri>(a, T, a.top_scratch, a.n);
 }
 
 mg_status check_kind(int32_t kind) {
@@ -458,28 +504,31 @@ mg_status launch_refit(const float *verts, int64_t nv, void *bvh, int64_t n, int
     a.leaf_parent = at<int32_t>(bvh, L.off_leaf_parent);
     a.node_parent = at<int32_t>(bvh, L.off_node_parent);
     a.nodes = at<float4>(bvh, L.off_nodes);
-    a.topo = a.nodes;
     a.node_aux = at<int32_t>(bvh, L.off_node_aux);
     a.top_nodes = at<int32_t>(bvh, L.off_top_nodes);
+    a.top_child = at<int32_t>(bvh, L.off_top_child);
+    a.subtrees = at<int32_t>(bvh, L.off_subtrees);
+    a.top_box = at<float>(bvh, L.off_top_box);
+    a.tstride = n;
     a.top_scratch = at<uint32_t>(bvh, L.off_top_scratch);
     mg_lbvh_header *hdr = at<mg_lbvh_header>(bvh, L.off_header);
     a.root = hdr->root_lo;
     a.status = &hdr->status;
     a.n_top = &hdr->n_top;
+    a.n_sub = &hdr->n_sub;
     a.n = n;
     a.chunk_log2 = chunk_log2_for(n);
     const int64_t C = int64_t(1) << a.chunk_log2;
-    const int chunks = static_cast<int>((n + C - 1) / C);
-    const size_t lds = static_cast<size_t>(C) * sizeof(uint32_t);
+    const int grid = static_cast<int>(std::min<int64_t>(2 * ((n + C - 1) / C), 65535));
     if (kind == MG_PRIM_TRIANGLES)
-        hipLaunchKernelGGL(refit_local_kernel<true>, dim3(chunks), dim3(256), lds, s, a);
+        hipLaunchKernelGGL(refit_sub_kernel<true>, dim3(grid), dim3(256), refit_sub_lds(C), s, a);
     else
-        hipLaunchKernelGGL(refit_local_kernel<false>, dim3(chunks), dim3(256), lds, s, a);
-    if (n > C) {   // otherwise the whole tree is one chunk and phase 1 reached the root
+        hipLaunchKernelGGL(refit_sub_kernel<false>, dim3(grid), dim3(256), refit_sub_lds(C), s, a);
+    if (n > C) {   // otherwise the one subtree is the whole tree and phase 1 wrote the root
         if (kind == MG_PRIM_TRIANGLES)
-            hipLaunchKernelGGL(refit_top_kernel<true>, dim3(1), dim3(1024), 0, s, a);
+            hipLaunchKernelGGL(refit_top_kernel<true>, dim3(1), dim3(1024), refit_top_lds(kTopLds), s, a);
         else
-            hipLaunchKernelGGL(refit_top_kernel<false>, dim3(1), dim3(1024), 0, s, a);
+            hipLaunchKernelGGL(refit_top_kernel<false>, dim3(1), dim3(1024), refit_top_lds(kTopLds), s, a);
     }
     return launch_status();
 }
@@ -548,7 +597,11 @@ extern "C" mg_status mg_lbvh_build(const float *verts, int32_t n_verts, const in
     hipLaunchKernelGGL(hierarchy_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, codes, prim, n, fz,
                        fz ? at<int32_t>(bvh, L.off_leaf_faces) : nullptr, at<int32_t>(bvh, L.off_leaf_parent),
                        at<int32_t>(bvh, L.off_node_parent), at<int32_t>(bvh, L.off_node_aux),
-                       at<int32_t>(bvh, L.off_top_nodes), at<float>(bvh, L.off_nodes), hdr, chunk_log2_for(n));
+                       at<int32_t>(bvh, L.off_top_nodes), at<int32_t>(bvh, L.off_subtrees),
+                       at<float>(bvh, L.off_nodes), hdr, chunk_log2_for(n));
+    hipLaunchKernelGGL(top_child_kernel, dim3(static_cast<unsigned>(std::min<int64_t>(blocks_for(n, 256), 64))),
+                       dim3(256), 0, s, at<int32_t>(bvh, L.off_node_aux), at<int32_t>(bvh, L.off_top_nodes),
+                       at<float>(bvh, L.off_nodes), n, at<int32_t>(bvh, L.off_top_child), hdr);
     if (launch_status() != MG_OK) return MG_ERR_HIP;
     return launch_refit(verts, n_verts, bvh, n, prim_kind, s);
 }

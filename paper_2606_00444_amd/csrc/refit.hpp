@@ -1,13 +1,31 @@
-// LBVH refit bodies shared by the plain refit/build kernels and the batched
+// LBVH refit bodies shared by the plain refit/build kernel and the batched
 // persistent kernel.
 //
-// Internal nodes of a Karras tree cover contiguous leaf ranges, so every node
-// whose range lies inside one chunk of 2^chunk_log2 leaves is refit by the
-// workgroup owning that chunk, with arrival counters in LDS (workgroup scope, no
-// cross-XCD traffic).  The few "top" nodes whose range crosses a chunk boundary
-// are then finished by one workgroup, again with LDS counters and LDS atomic
-// min/max accumulators.  Boxes are exact (min/max only), so any schedule gives
-// bitwise the same result.
+// The tree is cut into subtrees of at most C = 2^chunk_log2 leaves: a subtree
+// root is a child, with at most C leaves, of a node with more than C (or the
+// whole tree when it has at most C leaves).  Above the cut lie the "top"
+// nodes, one fewer than the subtrees.  Both sets are fixed by the topology and
+// listed once, when the tree is built.
+//
+// Phase 1 (one workgroup per subtree): a Karras node covers a contiguous leaf
+// range and its index is one end of that range, so the internal nodes of a
+// subtree over leaves [f, l] have indices in [f, l].  The workgroup keeps, per
+// local index, an arrival counter, a box accumulator (order-preserving uint
+// min/max) and the node's parent link in LDS; a leaf's thread writes the leaf's
+// record slot and climbs while it is the second arrival, so the climb reads
+// only LDS.  The subtree root's box is deposited in its top parent's slot of
+// the top-box table.
+//
+// Phase 2 (one workgroup, after phase 1 has finished): the top nodes are
+// finished in rounds.  Each round, every node whose top children are done
+// takes the union of its deposited subtree-root boxes and its top children's
+// boxes, writes its top children's record slots, and is done; the rounds end
+// when the root is.  Boxes, child indices and flags live in LDS (or in global
+// scratch when there are more top nodes than fit).
+//
+// Boxes are exact (min/max only), so any schedule gives bitwise the same
+// records.  Every index read from the buffer is range-checked; a corrupted
+// buffer sets the error word instead of faulting or hanging.
 #pragma once
 
 #include "mgu_internal.hpp"
@@ -20,54 +38,83 @@ struct RefitArgs {
     const int32_t *prim;
     const int32_t *leaf_parent; const int32_t *node_parent;
     float4 *nodes;                // [n-1][6] records written by this refit
-    const float4 *topo;           // records holding the child references (the BVH's own;
-                                  // the same as nodes except for per-frame copies)
-    const int32_t *node_aux; const int32_t *top_nodes;
-    uint32_t *top_scratch;        // [7][n]: counts, then 6 box planes (large n_top only)
+    const int32_t *node_aux;      // top index of a top node, else -1
+    const int32_t *top_nodes;     // [T] node id of each top node
+    const int32_t *top_child;     // [2][n] top index of each child, -1 when it roots a subtree
+    const int32_t *subtrees;      // [3][n_sub]: root reference, first leaf, last leaf
+    float *top_box;               // [2][6][tstride] deposited subtree-root boxes
+    int64_t tstride;
+    uint32_t *top_scratch;        // [10][tstride] phase-2 state when T exceeds the LDS capacity
     float *root;                  // root box: lo at [0..2], hi at [4..6]
     int32_t *status;              // error word
     const int32_t *n_top;         // number of top nodes (device)
+    const int32_t *n_sub;         // number of subtrees (device)
     int64_t n;
     int chunk_log2;
 };
 
-constexpr int kTopLds = 2048;     // top nodes handled with LDS accumulators
+constexpr int kTopLds = 1024;     // top nodes handled with LDS state in the plain refit
+
+// LDS bytes of phase 1 for subtrees of up to C leaves, and of phase 2 for Tl
+// top nodes (6 box planes, 2 child indices, done and ready flags).
+constexpr size_t refit_sub_lds(int64_t C) { return static_cast<size_t>(C) * 32; }
+constexpr size_t refit_top_lds(int64_t Tl) { return static_cast<size_t>(Tl) * 40; }
 
 __device__ __forceinline__ void write_root(float *root, f3 lo, f3 hi) {
     root[0] = lo.x; root[1] = lo.y; root[2] = lo.z;
     root[4] = hi.x; root[5] = hi.y; root[6] = hi.z;
 }
 
-// Box of the child stored in a record slot: a leaf triangle's vertices or a
-// box (internal children and points store lo/hi in the first two float4).
-template <bool kTri>
-__device__ __forceinline__ void slot_box(const float4 *slot, f3 &lo, f3 &hi) {
-    const float4 f0 = slot[0], f1 = slot[1];
-    const f3 a = f3{f0.x, f0.y, f0.z}, b = f3{f1.x, f1.y, f1.z};
-    if (kTri && __float_as_int(f0.w) < 0) {
-        const float4 f2 = slot[2];
-        const f3 c = f3{f2.x, f2.y, f2.z};
-        lo = fmin3(fmin3(a, b), c);
-        hi = fmax3(fmax3(a, b), c);
-    } else {
-        lo = a;
-        hi = b;
-    }
+__device__ __forceinline__ void lds_union(uint32_t *b, int64_t stride, int64_t j, f3 lo, f3 hi) {
+    atomicMin(&b[0 * stride + j], f2ord(lo.x));
+    atomicMin(&b[1 * stride + j], f2ord(lo.y));
+    atomicMin(&b[2 * stride + j], f2ord(lo.z));
+    atomicMax(&b[3 * stride + j], f2ord(hi.x));
+    atomicMax(&b[4 * stride + j], f2ord(hi.y));
+    atomicMax(&b[5 * stride + j], f2ord(hi.z));
 }
 
-// Phase 1: workgroup b owns leaves [b C, b C + C) and every internal node whose
-// range lies inside them.  Arrival counters live in LDS (index node - b C: a
-// local node is one end of its own range), so all synchronisation is at
-// workgroup scope.  A climb stops at the first top node; its child's data is
-// already in the top node's record for phase 2.
+__device__ __forceinline__ void lds_read(const uint32_t *b, int64_t stride, int64_t j, f3 &lo, f3 &hi) {
+    lo = f3{ord2f(b[0 * stride + j]), ord2f(b[1 * stride + j]), ord2f(b[2 * stride + j])};
+    hi = f3{ord2f(b[3 * stride + j]), ord2f(b[4 * stride + j]), ord2f(b[5 * stride + j])};
+}
+
+__device__ __forceinline__ void lds_empty(uint32_t *b, int64_t stride, int64_t j) {
+    const uint32_t e_lo = f2ord(INFINITY), e_hi = f2ord(-INFINITY);
+    b[0 * stride + j] = e_lo; b[1 * stride + j] = e_lo; b[2 * stride + j] = e_lo;
+    b[3 * stride + j] = e_hi; b[4 * stride + j] = e_hi; b[5 * stride + j] = e_hi;
+}
+
+// Deposit the box of a subtree root into slot `slot` of its top parent p.
+__device__ __forceinline__ void deposit(const RefitArgs &a, int32_t p, int slot, f3 lo, f3 hi) {
+    const int32_t t = a.node_aux[p];
+    if (t < 0 || t >= a.tstride) { atomicOr(a.status, 8); return; }
+    float *b = a.top_box + static_cast<int64_t>(slot) * 6 * a.tstride + t;
+    b[0] = lo.x; b[a.tstride] = lo.y; b[2 * a.tstride] = lo.z;
+    b[3 * a.tstride] = hi.x; b[4 * a.tstride] = hi.y; b[5 * a.tstride] = hi.z;
+}
+
+// Phase 1 for subtree k.  smem: refit_sub_lds(C) bytes.
 template <bool kTri>
-__device__ void refit_chunk(const RefitArgs &a, int64_t chunk, uint32_t *s_cnt) {
+__device__ void refit_subtree(const RefitArgs &a, int64_t k, unsigned char *smem) {
     const int64_t C = int64_t(1) << a.chunk_log2;
-    const int64_t base = chunk * C;
-    const int64_t end = base + C < a.n ? base + C : a.n;
-    for (int64_t k = threadIdx.x; k < C; k += blockDim.x) s_cnt[k] = 0;
+    const int32_t r = a.subtrees[k];
+    const int64_t f = a.subtrees[a.n + k], l = a.subtrees[2 * a.n + k];
+    uint32_t *s_box = reinterpret_cast<uint32_t *>(smem);          // [6][C]
+    uint32_t *s_cnt = s_box + 6 * C;                               // [C]
+    int32_t *s_par = reinterpret_cast<int32_t *>(s_cnt + C);       // [C]
+    const int64_t size = l - f + 1;
+    if (f < 0 || l >= a.n || size < 1 || size > C) {
+        if (threadIdx.x == 0) atomicOr(a.status, 4);
+        return;
+    }
+    for (int64_t j = threadIdx.x; j < size; j += blockDim.x) {
+        s_cnt[j] = 0;
+        lds_empty(s_box, C, j);
+        s_par[j] = f + j < a.n - 1 ? a.node_parent[f + j] : -1;
+    }
     __syncthreads();
-    for (int64_t i = base + threadIdx.x; i < end; i += blockDim.x) {
+    for (int64_t i = f + threadIdx.x; i <= l; i += blockDim.x) {
         const int32_t id = a.prim[i];
         f3 x, y, z;
         if (kTri) {
@@ -78,7 +125,7 @@ __device__ void refit_chunk(const RefitArgs &a, int64_t chunk, uint32_t *s_cnt) 
             x = y = z = load3(a.verts, a.nv, id);
         }
         f3 lo = fmin3(fmin3(x, y), z), hi = fmax3(fmax3(x, y), z);
-        int32_t tag = a.leaf_parent[i];
+        const int32_t tag = a.leaf_parent[i];
         if (tag < 0) {            // a single leaf is the root
             write_root(a.root, lo, hi);
             continue;
@@ -89,87 +136,112 @@ __device__ void refit_chunk(const RefitArgs &a, int64_t chunk, uint32_t *s_cnt) 
         rec[0] = make_float4(x.x, x.y, x.z, __int_as_float(~static_cast<int32_t>(i)));
         rec[1] = make_float4(y.x, y.y, y.z, __int_as_float(id));
         if (kTri) rec[2] = make_float4(z.x, z.y, z.z, 0.0f);
-        // a valid tree is at most 62 levels deep; the cap and range checks turn a
-        // corrupted buffer into an error word instead of a fault or a hang
+        if (r == ~static_cast<int32_t>(i)) {      // a one-leaf subtree
+            deposit(a, p, slot, lo, hi);
+            continue;
+        }
+        // a valid tree is at most 62 levels deep
         for (int level = 0; level < 64; ++level) {
-            if (p < base || p >= end || a.node_aux[p] >= 0) break;     // top node: phase 2
-            const uint32_t old = __hip_atomic_fetch_add(&s_cnt[p - base], 1u, __ATOMIC_ACQ_REL,
-                                                        __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (old == 0) break;
-            f3 slo, shi;
-            slot_box<kTri>(a.nodes + 6 * static_cast<int64_t>(p) + 3 * (1 - slot), slo, shi);
-            lo = fmin3(lo, slo);
-            hi = fmax3(hi, shi);
-            tag = a.node_parent[p];
-            if (tag < 0) {
+            const int64_t j = p - f;
+            if (j < 0 || j >= size) { atomicOr(a.status, 4); break; }
+            lds_union(s_box, C, j, lo, hi);
+            const uint32_t old = __hip_atomic_fetch_add(&s_cnt[j], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (old == 0) break;                  // the sibling finishes node p
+            lds_read(s_box, C, j, lo, hi);
+            const int32_t c = p;
+            const int32_t ptag = s_par[j];
+            if (ptag < 0) {
                 write_root(a.root, lo, hi);
                 break;
             }
-            const int32_t c = p;
-            p = tag >> 1;
-            slot = tag & 1;
+            p = ptag >> 1;
+            slot = ptag & 1;
             if (p >= a.n - 1) { atomicOr(a.status, 4); break; }
             rec = a.nodes + 6 * static_cast<int64_t>(p) + 3 * slot;
             rec[0] = make_float4(lo.x, lo.y, lo.z, __int_as_float(c));
             rec[1] = make_float4(hi.x, hi.y, hi.z, 0.0f);
+            if (c == r) {
+                deposit(a, p, slot, lo, hi);
+                break;
+            }
         }
     }
 }
 
-// Phase 2 body: cnt [T] and box planes bx[k * stride + t] either in LDS or in
-// the BVH's scratch section; one workgroup, so workgroup scope suffices.
+// Phase 2 over T top nodes with state at st (stride planes of uint32: 6 box
+// planes, 2 child planes, done, ready), in LDS or global scratch; one
+// workgroup.  Returns after the root's box is written.
 template <bool kTri>
-__device__ void refit_top_body(const RefitArgs &a, int T, uint32_t *cnt, uint32_t *bx, int64_t stride) {
-    constexpr uint32_t kReady = 0x80000000u;
+__device__ void refit_top(const RefitArgs &a, int T, uint32_t *st, int64_t stride) {
+    __shared__ int s_root, s_root_done;
+    uint32_t *bx = st;
+    int32_t *ch = reinterpret_cast<int32_t *>(st + 6 * stride);
+    uint32_t *done = st + 8 * stride;
+    uint32_t *rdy = st + 9 * stride;
+    if (threadIdx.x == 0) {
+        s_root = -1;
+        s_root_done = 0;
+    }
+    __syncthreads();
     for (int t = threadIdx.x; t < T; t += blockDim.x) {
-        const int32_t p = a.top_nodes[t];
         f3 lo = f3{INFINITY, INFINITY, INFINITY}, hi = f3{-INFINITY, -INFINITY, -INFINITY};
-        uint32_t count = 0;
-        for (int slot = 0; slot < 2; ++slot) {
-            const float4 *sl = a.nodes + 6 * static_cast<int64_t>(p) + 3 * slot;
-            const int32_t ref = __float_as_int(a.topo[6 * static_cast<int64_t>(p) + 3 * slot].w);
-            if (ref >= a.n - 1 || ~ref >= a.n) { atomicOr(a.status, 16); continue; }
-            if (ref >= 0 && a.node_aux[ref] >= 0) continue;       // a top child arrives later
-            f3 clo, chi;
-            slot_box<kTri>(sl, clo, chi);
-            lo = fmin3(lo, clo);
-            hi = fmax3(hi, chi);
-            ++count;
+        for (int s = 0; s < 2; ++s) {
+            const int32_t c = a.top_child[s * a.n + t];
+            ch[s * stride + t] = c;
+            if (c >= 0) continue;                 // a top child: merged in a later round
+            const float *b = a.top_box + static_cast<int64_t>(s) * 6 * a.tstride + t;
+            lo = fmin3(lo, f3{b[0], b[a.tstride], b[2 * a.tstride]});
+            hi = fmax3(hi, f3{b[3 * a.tstride], b[4 * a.tstride], b[5 * a.tstride]});
         }
         bx[0 * stride + t] = f2ord(lo.x); bx[1 * stride + t] = f2ord(lo.y); bx[2 * stride + t] = f2ord(lo.z);
         bx[3 * stride + t] = f2ord(hi.x); bx[4 * stride + t] = f2ord(hi.y); bx[5 * stride + t] = f2ord(hi.z);
-        cnt[t] = count == 2 ? (kReady | 2u) : count;
+        done[t] = 0;
+        if (a.top_nodes[t] == 0) s_root = t;
     }
     __syncthreads();
-    for (int t0 = threadIdx.x; t0 < T; t0 += blockDim.x) {
-        if ((__hip_atomic_load(&cnt[t0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) & kReady) == 0) continue;
-        int t = t0;
-        for (int level = 0; level < 64; ++level) {
-            const int32_t p = a.top_nodes[t];
-            const f3 lo = f3{ord2f(bx[0 * stride + t]), ord2f(bx[1 * stride + t]), ord2f(bx[2 * stride + t])};
-            const f3 hi = f3{ord2f(bx[3 * stride + t]), ord2f(bx[4 * stride + t]), ord2f(bx[5 * stride + t])};
-            const int32_t tag = a.node_parent[p];
-            if (tag < 0) {
-                write_root(a.root, lo, hi);
-                break;
-            }
-            const int32_t pp = tag >> 1, slot = tag & 1;
-            float4 *rec = a.nodes + 6 * static_cast<int64_t>(pp) + 3 * slot;
-            rec[0] = make_float4(lo.x, lo.y, lo.z, __int_as_float(p));
-            rec[1] = make_float4(hi.x, hi.y, hi.z, 0.0f);
-            const int32_t tt = a.node_aux[pp];
-            if (tt < 0 || tt >= T) { atomicOr(a.status, 8); break; }
-            __hip_atomic_fetch_min(&bx[0 * stride + tt], f2ord(lo.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_min(&bx[1 * stride + tt], f2ord(lo.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_min(&bx[2 * stride + tt], f2ord(lo.z), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_max(&bx[3 * stride + tt], f2ord(hi.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_max(&bx[4 * stride + tt], f2ord(hi.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_max(&bx[5 * stride + tt], f2ord(hi.z), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            const uint32_t old = __hip_atomic_fetch_add(&cnt[tt], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (old != 1u) break;                                 // the sibling is still on its way
-            t = tt;
-        }
+    if (s_root < 0) {
+        if (threadIdx.x == 0) atomicOr(a.status, 8);
+        return;
     }
+    // a valid top tree is at most 62 levels high: one node finishes per level
+    for (int round = 0; round < 64; ++round) {
+        for (int t = threadIdx.x; t < T; t += blockDim.x) {
+            uint32_t r = 0;
+            if (!done[t]) {
+                const int32_t c0 = ch[t], c1 = ch[stride + t];
+                r = (c0 < 0 || (c0 < T && done[c0])) && (c1 < 0 || (c1 < T && done[c1]));
+            }
+            rdy[t] = r;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < T; t += blockDim.x) {
+            if (!rdy[t]) continue;
+            f3 lo, hi;
+            lds_read(bx, stride, t, lo, hi);
+            const int32_t pn = a.top_nodes[t];
+            for (int s = 0; s < 2; ++s) {
+                const int32_t c = ch[s * stride + t];
+                if (c < 0) continue;
+                f3 clo, chi;
+                lds_read(bx, stride, c, clo, chi);
+                lo = fmin3(lo, clo);
+                hi = fmax3(hi, chi);
+                float4 *rec = a.nodes + 6 * static_cast<int64_t>(pn) + 3 * s;
+                rec[0] = make_float4(clo.x, clo.y, clo.z, __int_as_float(a.top_nodes[c]));
+                rec[1] = make_float4(chi.x, chi.y, chi.z, 0.0f);
+            }
+            bx[0 * stride + t] = f2ord(lo.x); bx[1 * stride + t] = f2ord(lo.y); bx[2 * stride + t] = f2ord(lo.z);
+            bx[3 * stride + t] = f2ord(hi.x); bx[4 * stride + t] = f2ord(hi.y); bx[5 * stride + t] = f2ord(hi.z);
+            done[t] = 1;
+            if (t == s_root) {
+                write_root(a.root, lo, hi);
+                s_root_done = 1;
+            }
+        }
+        __syncthreads();
+        if (s_root_done) return;
+    }
+    if (threadIdx.x == 0) atomicOr(a.status, 8);   // the root never became ready
 }
 
 }  // namespace mgu
