@@ -78,10 +78,11 @@ def source_hash(files):
     return h.hexdigest()[:16]
 
 
+_CSRC = "paper_2606_00444_amd/csrc/"
 KERNEL_SOURCES = {
-    "gaussian_update": ["paper_2606_00444_amd/csrc/gaussian.hip", "paper_2606_00444_amd/csrc/mgu_internal.hpp"],
-    "refit": ["paper_2606_00444_amd/csrc/lbvh.hip", "paper_2606_00444_amd/csrc/mgu_internal.hpp"],
-    "collide": ["paper_2606_00444_amd/csrc/query.hip", "paper_2606_00444_amd/csrc/mgu_internal.hpp"],
+    "gaussian_update": [_CSRC + f for f in ("gaussian.hip", "repose.hpp", "mgu_internal.hpp")],
+    "refit": [_CSRC + f for f in ("lbvh.hip", "refit.hpp", "mgu_internal.hpp")],
+    "collide": [_CSRC + f for f in ("query.hip", "traverse.hpp", "mgu_internal.hpp")],
 }
 
 
@@ -134,6 +135,11 @@ def cpu_baseline(sc, frames_np, targets_np, n_sample):
         "seconds": {k: round(v, 4) for k, v in timings.items()},
         "wall_s": round(time.perf_counter() - t_all, 2),
     }
+
+
+def sample_frames(T, k=6):
+    """k frames spread evenly over a sequence of T (both ends included)."""
+    return sorted({round(i * (T - 1) / (k - 1)) for i in range(k)}) if T > 1 else [0]
 
 
 def graph_ms(fn, reps, torch):
@@ -399,6 +405,22 @@ def cpu_baseline_refine(sc, Y):
             "wall_s": round(sec, 2)}
 
 
+def copy_calibration(mb, reps):
+    """A plain copy of known size (the vertex-buffer copy kernel): reads and writes mb MB per launch.
+    Its FETCH_SIZE / WRITE_SIZE counters calibrate the counters of the other kernels."""
+    import torch
+    import paper_2606_00444_amd as mg
+    dev = torch.device("cuda:0")
+    n = (mb * 1000 * 1000) // 12                     # vertices of 12 B
+    frames = torch.rand(2, 3, n, device=dev)
+    live = torch.empty(3, n, device=dev)
+    for r in range(reps):
+        mg.vertex_buffer_update(frames, r % 2, live)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read_per_launch": 12 * n, "bytes_written_per_launch": 12 * n,
+                                           "reps": reps}}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -409,7 +431,14 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=None,
                     help="queries the oracle baseline runs per query set (default: c1/c2/c5 8000, c3 all)")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of a HIP graph")
+    ap.add_argument("--phase", choices=["copy", "update", "refit", "collide", "rebuild", "target_queries"],
+                    help="profiling aid (c1/c2/c5): run only this phase --reps times, eagerly, and exit")
+    ap.add_argument("--reps", type=int, default=60)
+    ap.add_argument("--copy-calibration", type=int, metavar="MB", default=0,
+                    help="profiling aid: copy MB megabytes with the vertex-buffer copy kernel --reps times and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration(args.copy_calibration, args.reps)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
@@ -429,7 +458,8 @@ def main():
     t0 = time.perf_counter()
     sc = make_config(cfg)
     T = sc.n_frames
-    n_used = min(T, max(args.steps, args.warmup))
+    # frames (and varying-topology targets) the run touches; a single-phase profiling run needs one
+    n_used = 1 if args.phase else min(T, max(args.steps, args.warmup))
     frame_ids = list(range(n_used))
     frames_np = sc.frames(range(T))
     targets_np = make_targets(cfg, frame_ids)
@@ -515,6 +545,27 @@ def main():
         phase_rebuild(j)
         phase_target_queries(j)
 
+    if args.phase:
+        # profiling aid: one phase alone, eagerly, so per-dispatch counters see only it
+        frames_c = sample_frames(T)
+
+        def collide_at(r):             # one collision launch per sampled frame, cyclically
+            phase_copy(frames_c[r % len(frames_c)])
+            phase_refit()
+            phase_collide()
+
+        phases = {"copy": lambda r: phase_copy(r % T), "update": lambda r: phase_update(),
+                  "refit": lambda r: phase_refit(), "collide": collide_at,
+                  "rebuild": lambda r: phase_rebuild(r % n_used), "target_queries": lambda r: phase_target_queries(0)}
+        phase_copy(0)
+        phase_rebuild(0)
+        for r in range(args.reps):
+            phases[args.phase](r)
+        torch.cuda.synchronize()
+        print(json.dumps({"phase": args.phase, "reps": args.reps, "workload": args.workload,
+                          "autotuned": {k: {"kernel": v["kernel"], "batch": v["batch"], "seed": v["seed"],
+                                            "order": v["order"]} for k, v in tune.items()}}))
+        return
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
@@ -563,9 +614,16 @@ def main():
         "vertex_copy": timed(lambda r: phase_copy(r % T), reps),
         "gaussian_update": timed(lambda r: phase_update(), reps),
         "refit": timed(lambda r: phase_refit(), reps),
-        "collide": timed(lambda r: phase_collide(), reps),
         "rebuild": timed(lambda r: phase_rebuild(r % n_used), reps),
     }
+    # the collision query's cost follows the deformation: average it over frames
+    # spread across the sequence (the same frames a --phase collide run cycles through)
+    per_frame = []
+    for f in sample_frames(T):
+        phase_copy(f)
+        phase_refit()
+        per_frame.append(timed(lambda r: phase_collide(), max(10, reps // 6)))
+    ph["collide"] = float(np.mean(per_frame))
     # the target BVHs share one buffer: time their queries on one freshly built target
     phase_rebuild(0)
     ph["target_queries"] = timed(lambda r: phase_target_queries(0), reps)
@@ -588,10 +646,17 @@ def main():
     refit_path_ms = ph["vertex_copy"] + ph["gaussian_update"] + ph["refit"] + ph["collide"]
     rebuild_path_ms = ph["rebuild"] + ph["target_queries"]
     # traversal statistics of one collision launch (outside the timed region)
+    # traversal statistics over the same sampled frames (counters accumulate across launches)
     cnt = torch.zeros(4, dtype=torch.int64, device=dev)
-    phase_collide(cnt)
+    frames_c = sample_frames(T)
+    for f in frames_c:
+        phase_copy(f)
+        phase_refit()
+        phase_collide(cnt)
     torch.cuda.synchronize()
     n_exp, n_lbox, n_lex, n_q = (int(x) for x in cnt.cpu())
+    n_exp, n_lbox, n_lex = (x / len(frames_c) for x in (n_exp, n_lbox, n_lex))   # per launch
+    n_q //= len(frames_c)
     trav = {"node_expansions_per_query": round(n_exp / n_q, 1), "leaf_bound_tests_per_query": round(n_lbox / n_q, 1),
             "exact_leaf_tests_per_query": round(n_lex / n_q, 1)}
     # algorithmic float32 operations per unit: expansion = two child box

@@ -162,7 +162,7 @@ mg_status mg_mesh_gaussian_update_backward(const float *verts, int32_t n_verts, 
  *                                and last leaf; the subtrees (at most 2^chunk_log2
  *                                leaves, children of top nodes) cut the tree
  *   top_box     float  [2][6][n] refit scratch: subtree-root boxes per top node slot
- *   top_scratch uint32 [10][n]   second-phase refit scratch when n_top is large
+ *   top_scratch uint32 [11][n]   second-phase refit scratch when n_top is large
  * ---------------------------------------------------------------------- */
 
 typedef struct mg_lbvh_header {

@@ -55,7 +55,7 @@ inline mg_lbvh_layout make_layout(int64_t n, int kind) {
     L.off_top_child = o;   o += align256(8 * n);
     L.off_subtrees = o;    o += align256(12 * n);
     L.off_top_box = o;     o += align256(48 * n);
-    L.off_top_scratch = o; o += align256(40 * n);
+    L.off_top_scratch = o; o += align256(44 * n);
     L.total_bytes = o;
     return L;
 }
@@ -477,7 +477,7 @@ __global__ __launch_bounds__(256) void refit_sub_kernel(RefitArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int32_t ns = *a.n_sub;
     for (int64_t k = blockIdx.x; k < ns; k += gridDim.x) {
-        refit_subtree<kTri>(a, k, smem);
+        refit_subtree<kTri, 256>(a, k, smem);
         __syncthreads();          // LDS is reused by the next subtree
     }
 }
@@ -487,8 +487,8 @@ template <bool kTri>
 __global__ __launch_bounds__(1024) void refit_top_kernel(RefitArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int T = *a.n_top;
-    if (T > 0 && T <= kTopLds) refit_top<kTri>(a, T, reinterpret_cast<uint32_t *>(smem), kTopLds);
-    else if (T > kTopLds) refit_top<kTri>(a, T, a.top_scratch, a.n);
+    if (T > 0 && T <= kTopLds) refit_top<kTri, 1024>(a, T, reinterpret_cast<uint32_t *>(smem), kTopLds);
+    else if (T > kTopLds) refit_top<kTri, 1024>(a, T, a.top_scratch, a.n);
 }
 
 mg_status check_kind(int32_t kind) {

@@ -44,7 +44,7 @@ struct RefitArgs {
     const int32_t *subtrees;      // [3][n_sub]: root reference, first leaf, last leaf
     float *top_box;               // [2][6][tstride] deposited subtree-root boxes
     int64_t tstride;
-    uint32_t *top_scratch;        // [10][tstride] phase-2 state when T exceeds the LDS capacity
+    uint32_t *top_scratch;        // [11][tstride] phase-2 state when T exceeds the LDS capacity
     float *root;                  // root box: lo at [0..2], hi at [4..6]
     int32_t *status;              // error word
     const int32_t *n_top;         // number of top nodes (device)
@@ -56,9 +56,9 @@ struct RefitArgs {
 constexpr int kTopLds = 1024;     // top nodes handled with LDS state in the plain refit
 
 // LDS bytes of phase 1 for subtrees of up to C leaves, and of phase 2 for Tl
-// top nodes (6 box planes, 2 child indices, done and ready flags).
+// top nodes (6 box planes, 2 child indices, node id, done and ready flags).
 constexpr size_t refit_sub_lds(int64_t C) { return static_cast<size_t>(C) * 32; }
-constexpr size_t refit_top_lds(int64_t Tl) { return static_cast<size_t>(Tl) * 40; }
+constexpr size_t refit_top_lds(int64_t Tl) { return static_cast<size_t>(Tl) * 44; }
 
 __device__ __forceinline__ void write_root(float *root, f3 lo, f3 hi) {
     root[0] = lo.x; root[1] = lo.y; root[2] = lo.z;
@@ -94,8 +94,11 @@ __device__ __forceinline__ void deposit(const RefitArgs &a, int32_t p, int slot,
     b[3 * a.tstride] = hi.x; b[4 * a.tstride] = hi.y; b[5 * a.tstride] = hi.z;
 }
 
-// Phase 1 for subtree k.  smem: refit_sub_lds(C) bytes.
-template <bool kTri>
+// Phase 1 for subtree k by a workgroup of kThreads threads (a compile-time
+// stride: blockDim would be reloaded from the dispatch packet, and that load's
+// wait would also wait for the record stores in flight).  smem:
+// refit_sub_lds(C) bytes.
+template <bool kTri, int kThreads>
 __device__ void refit_subtree(const RefitArgs &a, int64_t k, unsigned char *smem) {
     const int64_t C = int64_t(1) << a.chunk_log2;
     const int32_t r = a.subtrees[k];
@@ -108,13 +111,13 @@ __device__ void refit_subtree(const RefitArgs &a, int64_t k, unsigned char *smem
         if (threadIdx.x == 0) atomicOr(a.status, 4);
         return;
     }
-    for (int64_t j = threadIdx.x; j < size; j += blockDim.x) {
+    for (int64_t j = threadIdx.x; j < size; j += kThreads) {
         s_cnt[j] = 0;
         lds_empty(s_box, C, j);
         s_par[j] = f + j < a.n - 1 ? a.node_parent[f + j] : -1;
     }
     __syncthreads();
-    for (int64_t i = f + threadIdx.x; i <= l; i += blockDim.x) {
+    for (int64_t i = f + threadIdx.x; i <= l; i += kThreads) {
         const int32_t id = a.prim[i];
         f3 x, y, z;
         if (kTri) {
@@ -169,21 +172,22 @@ __device__ void refit_subtree(const RefitArgs &a, int64_t k, unsigned char *smem
 }
 
 // Phase 2 over T top nodes with state at st (stride planes of uint32: 6 box
-// planes, 2 child planes, done, ready), in LDS or global scratch; one
-// workgroup.  Returns after the root's box is written.
-template <bool kTri>
+// planes, 2 child planes, node id, done, ready), in LDS or global scratch;
+// one workgroup.  Returns after the root's box is written.
+template <bool kTri, int kThreads>
 __device__ void refit_top(const RefitArgs &a, int T, uint32_t *st, int64_t stride) {
     __shared__ int s_root, s_root_done;
     uint32_t *bx = st;
     int32_t *ch = reinterpret_cast<int32_t *>(st + 6 * stride);
-    uint32_t *done = st + 8 * stride;
-    uint32_t *rdy = st + 9 * stride;
+    int32_t *node = reinterpret_cast<int32_t *>(st + 8 * stride);
+    uint32_t *done = st + 9 * stride;
+    uint32_t *rdy = st + 10 * stride;
     if (threadIdx.x == 0) {
         s_root = -1;
         s_root_done = 0;
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < T; t += blockDim.x) {
+    for (int t = threadIdx.x; t < T; t += kThreads) {
         f3 lo = f3{INFINITY, INFINITY, INFINITY}, hi = f3{-INFINITY, -INFINITY, -INFINITY};
         for (int s = 0; s < 2; ++s) {
             const int32_t c = a.top_child[s * a.n + t];
@@ -196,7 +200,9 @@ __device__ void refit_top(const RefitArgs &a, int T, uint32_t *st, int64_t strid
         bx[0 * stride + t] = f2ord(lo.x); bx[1 * stride + t] = f2ord(lo.y); bx[2 * stride + t] = f2ord(lo.z);
         bx[3 * stride + t] = f2ord(hi.x); bx[4 * stride + t] = f2ord(hi.y); bx[5 * stride + t] = f2ord(hi.z);
         done[t] = 0;
-        if (a.top_nodes[t] == 0) s_root = t;
+        const int32_t pn = a.top_nodes[t];
+        node[t] = pn;
+        if (pn == 0) s_root = t;
     }
     __syncthreads();
     if (s_root < 0) {
@@ -205,7 +211,7 @@ __device__ void refit_top(const RefitArgs &a, int T, uint32_t *st, int64_t strid
     }
     // a valid top tree is at most 62 levels high: one node finishes per level
     for (int round = 0; round < 64; ++round) {
-        for (int t = threadIdx.x; t < T; t += blockDim.x) {
+        for (int t = threadIdx.x; t < T; t += kThreads) {
             uint32_t r = 0;
             if (!done[t]) {
                 const int32_t c0 = ch[t], c1 = ch[stride + t];
@@ -214,11 +220,12 @@ __device__ void refit_top(const RefitArgs &a, int T, uint32_t *st, int64_t strid
             rdy[t] = r;
         }
         __syncthreads();
-        for (int t = threadIdx.x; t < T; t += blockDim.x) {
+        for (int t = threadIdx.x; t < T; t += kThreads) {
             if (!rdy[t]) continue;
             f3 lo, hi;
             lds_read(bx, stride, t, lo, hi);
-            const int32_t pn = a.top_nodes[t];
+            const int32_t pn = node[t];
+            if (pn < 0 || pn >= a.n - 1) { atomicOr(a.status, 8); continue; }
             for (int s = 0; s < 2; ++s) {
                 const int32_t c = ch[s * stride + t];
                 if (c < 0) continue;
@@ -227,7 +234,7 @@ __device__ void refit_top(const RefitArgs &a, int T, uint32_t *st, int64_t strid
                 lo = fmin3(lo, clo);
                 hi = fmax3(hi, chi);
                 float4 *rec = a.nodes + 6 * static_cast<int64_t>(pn) + 3 * s;
-                rec[0] = make_float4(clo.x, clo.y, clo.z, __int_as_float(a.top_nodes[c]));
+                rec[0] = make_float4(clo.x, clo.y, clo.z, __int_as_float(node[c]));
                 rec[1] = make_float4(chi.x, chi.y, chi.z, 0.0f);
             }
             bx[0 * stride + t] = f2ord(lo.x); bx[1 * stride + t] = f2ord(lo.y); bx[2 * stride + t] = f2ord(lo.z);
