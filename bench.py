@@ -431,6 +431,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=None,
                     help="queries the oracle baseline runs per query set (default: c1/c2/c5 8000, c3 all)")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of a HIP graph")
+    ap.add_argument("--streams", type=int, choices=(1, 2), default=2,
+                    help="c1/c2/c5: run the rebuild comparison path on a second stream (2) or serially (1)")
     ap.add_argument("--phase", choices=["copy", "update", "refit", "collide", "rebuild", "target_queries"],
                     help="profiling aid (c1/c2/c5): run only this phase --reps times, eagerly, and exit")
     ap.add_argument("--reps", type=int, default=60)
@@ -534,16 +536,34 @@ def main():
         mg.closest_point_query(tbvh[j], tgt_v[j], particles, normal=True, out=col_t, **o_ct)
         mg.closest_point_query(tbvh[j], tgt_v[j], V0, out=proj, **o_pr)
 
+    # The refit path (template) and the rebuild comparison path (varying target) share
+    # no data: with --streams 2 the rebuild path runs on a second HIP stream (default
+    # priority), forked from and joined back into the launch stream every step, so each
+    # path's kernels can use compute units the other leaves idle.
+    side = torch.cuda.Stream() if args.streams == 2 else None
+
     def step(i):
         # simulation runs at the reconstruction rate: step i at f_sim = f_recon -> frame i (mod T)
         k = mg.frame_index(i % T, 30, 1, 30, T)
         j = k % n_used
+        if side is None:
+            phase_copy(k)
+            phase_update()
+            phase_refit()
+            phase_collide()
+            phase_rebuild(j)
+            phase_target_queries(j)
+            return
+        main = torch.cuda.current_stream()
+        side.wait_stream(main)
+        with torch.cuda.stream(side):
+            phase_rebuild(j)
+            phase_target_queries(j)
         phase_copy(k)
         phase_update()
         phase_refit()
         phase_collide()
-        phase_rebuild(j)
-        phase_target_queries(j)
+        main.wait_stream(side)
 
     if args.phase:
         # profiling aid: one phase alone, eagerly, so per-dispatch counters see only it
@@ -684,7 +704,8 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "frames": T, "vertices": NV, "faces": NF,
                    "gaussians": G, "particles": Q, "template_vertices_projected": NV,
-                   "target_faces_mean": round(tf_mean), "timing": "eager" if args.eager else "hip-graph"},
+                   "target_faces_mean": round(tf_mean), "timing": "eager" if args.eager else "hip-graph",
+                   "streams": args.streams},
         "refit_path": {"ms_per_frame": round(refit_path_ms, 5), "frames_per_s": round(1000.0 / refit_path_ms, 1)},
         "rebuild_path": {"ms_per_frame": round(rebuild_path_ms, 5), "frames_per_s": round(1000.0 / rebuild_path_ms, 1)},
         "queries_per_s": round(q_per_frame * fps, 1),
