@@ -173,9 +173,15 @@ __device__ void refit_subtree(const RefitArgs &a, int64_t k, unsigned char *smem
 
 // Phase 2 over T top nodes with state at st (stride planes of uint32: 6 box
 // planes, 2 child planes, node id, done, ready), in LDS or global scratch;
-// one workgroup.  Returns after the root's box is written.
+// one workgroup of kThreads.  Returns after the root's box is written.
+//
+// While every thread owns at most kOwn nodes (T <= kOwn kThreads), a thread
+// keeps its nodes' child indices, ids, boxes and flags in registers, so a
+// round costs one LDS read of the children's flags and one of their boxes;
+// larger T keep everything in the planes.
 template <bool kTri, int kThreads>
 __device__ void refit_top(const RefitArgs &a, int T, uint32_t *st, int64_t stride) {
+    constexpr int kOwn = 4;
     __shared__ int s_root, s_root_done;
     uint32_t *bx = st;
     int32_t *ch = reinterpret_cast<int32_t *>(st + 6 * stride);
@@ -209,44 +215,90 @@ __device__ void refit_top(const RefitArgs &a, int T, uint32_t *st, int64_t strid
         if (threadIdx.x == 0) atomicOr(a.status, 8);
         return;
     }
-    // a valid top tree is at most 62 levels high: one node finishes per level
-    for (int round = 0; round < 64; ++round) {
-        for (int t = threadIdx.x; t < T; t += kThreads) {
-            uint32_t r = 0;
-            if (!done[t]) {
-                const int32_t c0 = ch[t], c1 = ch[stride + t];
-                r = (c0 < 0 || (c0 < T && done[c0])) && (c1 < 0 || (c1 < T && done[c1]));
-            }
-            rdy[t] = r;
+    const int root = s_root;
+    // finish node t (its top children are done): union, records of its top children
+    auto finish = [&](int t, int32_t pn, int32_t c0, int32_t c1, f3 lo, f3 hi) {
+        const int32_t cs[2] = {c0, c1};
+        for (int s = 0; s < 2; ++s) {
+            const int32_t c = cs[s];
+            if (c < 0) continue;
+            f3 clo, chi;
+            lds_read(bx, stride, c, clo, chi);
+            lo = fmin3(lo, clo);
+            hi = fmax3(hi, chi);
+            float4 *rec = a.nodes + 6 * static_cast<int64_t>(pn) + 3 * s;
+            rec[0] = make_float4(clo.x, clo.y, clo.z, __int_as_float(node[c]));
+            rec[1] = make_float4(chi.x, chi.y, chi.z, 0.0f);
         }
-        __syncthreads();
-        for (int t = threadIdx.x; t < T; t += kThreads) {
-            if (!rdy[t]) continue;
-            f3 lo, hi;
-            lds_read(bx, stride, t, lo, hi);
-            const int32_t pn = node[t];
-            if (pn < 0 || pn >= a.n - 1) { atomicOr(a.status, 8); continue; }
-            for (int s = 0; s < 2; ++s) {
-                const int32_t c = ch[s * stride + t];
-                if (c < 0) continue;
-                f3 clo, chi;
-                lds_read(bx, stride, c, clo, chi);
-                lo = fmin3(lo, clo);
-                hi = fmax3(hi, chi);
-                float4 *rec = a.nodes + 6 * static_cast<int64_t>(pn) + 3 * s;
-                rec[0] = make_float4(clo.x, clo.y, clo.z, __int_as_float(node[c]));
-                rec[1] = make_float4(chi.x, chi.y, chi.z, 0.0f);
-            }
-            bx[0 * stride + t] = f2ord(lo.x); bx[1 * stride + t] = f2ord(lo.y); bx[2 * stride + t] = f2ord(lo.z);
-            bx[3 * stride + t] = f2ord(hi.x); bx[4 * stride + t] = f2ord(hi.y); bx[5 * stride + t] = f2ord(hi.z);
-            done[t] = 1;
-            if (t == s_root) {
-                write_root(a.root, lo, hi);
-                s_root_done = 1;
+        bx[0 * stride + t] = f2ord(lo.x); bx[1 * stride + t] = f2ord(lo.y); bx[2 * stride + t] = f2ord(lo.z);
+        bx[3 * stride + t] = f2ord(hi.x); bx[4 * stride + t] = f2ord(hi.y); bx[5 * stride + t] = f2ord(hi.z);
+        if (t == root) {
+            write_root(a.root, lo, hi);
+            s_root_done = 1;
+        }
+    };
+    if (T <= kOwn * kThreads) {
+        int32_t my_c0[kOwn], my_c1[kOwn], my_pn[kOwn];
+        bool my_done[kOwn];
+        f3 my_lo[kOwn], my_hi[kOwn];
+#pragma unroll
+        for (int u = 0; u < kOwn; ++u) {
+            const int t = threadIdx.x + u * kThreads;
+            my_done[u] = t >= T;
+            my_c0[u] = my_c1[u] = -1;
+            my_pn[u] = -1;
+            if (t < T) {
+                my_c0[u] = ch[t];
+                my_c1[u] = ch[stride + t];
+                my_pn[u] = node[t];
+                lds_read(bx, stride, t, my_lo[u], my_hi[u]);
+                if (my_c0[u] >= T || my_c1[u] >= T || my_pn[u] < 0 || my_pn[u] >= a.n - 1) {
+                    atomicOr(a.status, 8);
+                    my_done[u] = true;
+                }
             }
         }
-        __syncthreads();
-        if (s_root_done) return;
+        // a valid top tree is at most 62 levels high: one level finishes per round
+        for (int round = 0; round < 64; ++round) {
+            bool go[kOwn];
+#pragma unroll
+            for (int u = 0; u < kOwn; ++u)
+                go[u] = !my_done[u] && (my_c0[u] < 0 || done[my_c0[u]]) && (my_c1[u] < 0 || done[my_c1[u]]);
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kOwn; ++u) {
+                if (!go[u]) continue;
+                const int t = threadIdx.x + u * kThreads;
+                finish(t, my_pn[u], my_c0[u], my_c1[u], my_lo[u], my_hi[u]);
+                my_done[u] = true;
+                done[t] = 1;
+            }
+            __syncthreads();
+            if (s_root_done) return;
+        }
+    } else {
+        for (int round = 0; round < 64; ++round) {
+            for (int t = threadIdx.x; t < T; t += kThreads) {
+                uint32_t r = 0;
+                if (!done[t]) {
+                    const int32_t c0 = ch[t], c1 = ch[stride + t];
+                    r = (c0 < 0 || (c0 < T && done[c0])) && (c1 < 0 || (c1 < T && done[c1]));
+                }
+                rdy[t] = r;
+            }
+            __syncthreads();
+            for (int t = threadIdx.x; t < T; t += kThreads) {
+                if (!rdy[t]) continue;
+                const int32_t pn = node[t];
+                if (pn < 0 || pn >= a.n - 1) { atomicOr(a.status, 8); done[t] = 1; continue; }
+                f3 lo, hi;
+                lds_read(bx, stride, t, lo, hi);
+                finish(t, pn, ch[t], ch[stride + t], lo, hi);
+                done[t] = 1;
+            }
+            __syncthreads();
+            if (s_root_done) return;
+        }
     }
     if (threadIdx.x == 0) atomicOr(a.status, 8);   // the root never became ready
 }
