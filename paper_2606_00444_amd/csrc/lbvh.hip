@@ -471,15 +471,28 @@ __global__ __launch_bounds__(256) void top_child_kernel(const int32_t *__restric
     }
 }
 
-// Phase 1: workgroups take subtrees.
-template <bool kTri>
-__global__ __launch_bounds__(256) void refit_sub_kernel(RefitArgs a) {
+// Phase 1: workgroups of kThreads take subtrees.
+template <bool kTri, int kThreads>
+__global__ __launch_bounds__(kThreads) void refit_sub_kernel(RefitArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int32_t ns = *a.n_sub;
     for (int64_t k = blockIdx.x; k < ns; k += gridDim.x) {
-        refit_subtree<kTri, 256>(a, k, smem);
+        refit_subtree<kTri, kThreads>(a, k, smem);
         __syncthreads();          // LDS is reused by the next subtree
     }
+}
+
+// Phase 1 with one workgroup thread per two leaves of the largest subtree
+// (at least 256 threads), so the climbs of a subtree mostly run side by side.
+template <bool kTri>
+void launch_refit_sub(const RefitArgs &a, int64_t C, int grid, hipStream_t s) {
+    const size_t lds = refit_sub_lds(C);
+    if (C >= 2048)
+        hipLaunchKernelGGL((refit_sub_kernel<kTri, 1024>), dim3(grid), dim3(1024), lds, s, a);
+    else if (C >= 1024)
+        hipLaunchKernelGGL((refit_sub_kernel<kTri, 512>), dim3(grid), dim3(512), lds, s, a);
+    else
+        hipLaunchKernelGGL((refit_sub_kernel<kTri, 256>), dim3(grid), dim3(256), lds, s, a);
 }
 
 // Phase 2: one workgroup, one top node per thread while they fit in LDS.
@@ -521,9 +534,9 @@ mg_status launch_refit(const float *verts, int64_t nv, void *bvh, int64_t n, int
     const int64_t C = int64_t(1) << a.chunk_log2;
     const int grid = static_cast<int>(std::min<int64_t>(2 * ((n + C - 1) / C), 65535));
     if (kind == MG_PRIM_TRIANGLES)
-        hipLaunchKernelGGL(refit_sub_kernel<true>, dim3(grid), dim3(256), refit_sub_lds(C), s, a);
+        launch_refit_sub<true>(a, C, grid, s);
     else
-        hipLaunchKernelGGL(refit_sub_kernel<false>, dim3(grid), dim3(256), refit_sub_lds(C), s, a);
+        launch_refit_sub<false>(a, C, grid, s);
     if (n > C) {   // otherwise the one subtree is the whole tree and phase 1 wrote the root
         if (kind == MG_PRIM_TRIANGLES)
             hipLaunchKernelGGL(refit_top_kernel<true>, dim3(1), dim3(1024), refit_top_lds(kTopLds), s, a);
