@@ -12,7 +12,8 @@ Inputs are synthetic, seeded and device-resident before timing.  Warm-up steps
 run eagerly; the K timed steps are captured once into a HIP graph and replayed
 (so host launch overhead is not measured), bracketed by synchronisations.
 
-Workload c3 times the batched form instead (one step = one persistent launch
+Workload track times temporal correspondence tracking (one step = one frame),
+c3 times the batched form instead (one step = one persistent launch
 over all scenes x frames, against the plain per-frame path on the same GPU),
 and c4 the differentiable form (one step = one Adam step of the template
 projection loss, forward + backward + update).
@@ -47,10 +48,12 @@ WORKLOADS = {
               "100,000 target samples; one Adam step of P + Chamfer"),
     "c5": (5, "UV-sphere 250,002 V / 500,000 F, 1,000,000 Gaussians, 1,000,000 queries, 100 frames, "
               "1,000,000-face split rebuild targets"),
+    "track": (2, "temporal correspondence tracking (Eq. 1): the 20,002-vertex template carried through "
+                 "200 marching-tetrahedra targets of ~46-53k faces, re-anchored every 50 frames"),
 }
 METRIC = "frames/s and closest-point queries/s, refit vs rebuild; achieved HBM GB/s"
 # (timed steps, warm-up steps) per workload: each default run times about a second of GPU work
-DEFAULT_STEPS = {"c1": (60, 10), "c2": (200, 10), "c3": (10, 2), "c4": (200, 10), "c5": (20, 3)}
+DEFAULT_STEPS = {"c1": (60, 10), "c2": (200, 10), "c3": (10, 2), "c4": (200, 10), "c5": (20, 3), "track": (199, 0)}
 
 
 def _target_job(args):
@@ -174,6 +177,108 @@ def timed_region(run, steps, torch):
 
 def omp_threads():
     return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def run_track(args):
+    """Temporal correspondence tracking: one step = one frame (rebuild, query, re-anchor every 50)."""
+    from synth import make_config
+    t0 = time.perf_counter()
+    sc = make_config(2)
+    T = min(sc.n_frames, args.steps + 1)
+    targets_np = make_targets(2, list(range(T)))
+    setup_s = time.perf_counter() - t0
+
+    import torch
+    import paper_2606_00444_amd as mg
+    from paper_2606_00444_amd.tracking import Tracker
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    mg.check_device()
+    D = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    targets = [(D(v), D(f)) for v, f in targets_np]
+    V0 = D(sc.verts0)
+    NV = sc.n_verts
+    out = torch.empty(T, 3, NV, device=dev)
+    mg.vertex_buffer_update(V0.reshape(1, 3, NV), 0, out[0])
+    tr = Tracker(V0, max(f.shape[1] for _, f in targets_np), every=50, w_track=0.8)
+    K = T - 1
+
+    def run_all():
+        for t in range(1, T):
+            tr.step(out[t - 1], targets[t][0], targets[t][1], t, out[t])
+
+    run_all()                                               # eager warm-up pass over every frame
+    torch.cuda.synchronize()
+    if args.eager:
+        run = run_all
+    else:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            run_all()
+        g.replay()
+        torch.cuda.synchronize()
+        run = g.replay
+    ms_per_step, wall = timed_region(run, K, torch)
+
+    # per-phase durations on frame 1: the rebuild of its BVH and the query of the tracked points
+    tv, tf = targets[1]
+    bvh = mg.LBVH(tf.shape[1], mg.MG_PRIM_TRIANGLES, dev, buf=tr.buf, ws=tr.ws)
+    mg.lbvh_build(tv, tf, bvh=bvh)
+    from paper_2606_00444_amd.api import _query_out
+    rec = _query_out(NV, dev, True, False, False, False)
+    ph = {"rebuild": graph_ms(lambda _: mg.lbvh_build(tv, tf, bvh=bvh), 50, torch),
+          "query": graph_ms(lambda _: mg.closest_point_query(bvh, tv, out[0], out=rec), 50, torch)}
+    cnt = torch.zeros(4, dtype=torch.int64, device=dev)
+    mg.closest_point_query(bvh, tv, out[0], out=rec, counters=cnt)
+    torch.cuda.synchronize()
+    n_exp, n_lbox, n_lex, n_q = (int(x) for x in cnt.cpu())
+    ops = 34.0 * n_exp + 29.0 * n_lbox + 80.0 * n_lex
+    if ph["query"] >= ph["rebuild"]:
+        achieved = ops / (ph["query"] * 1e-3) / 1e12
+        roofline = {"bound": "alu", "kernel": "traverse_batch_kernel (tracked points onto the frame's mesh)",
+                    "achieved": round(achieved, 4), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5), "traffic": None,
+                    "alg_ops_per_launch": int(ops), "avg_launch_ms": round(ph["query"], 5)}
+    else:
+        tf_mean = float(np.mean([f.shape[1] for _, f in targets_np]))
+        alg = 200.0 * tf.shape[1] + 12.0 * tv.shape[1]
+        achieved = alg / (ph["rebuild"] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": "rebuild (all build kernels)", "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": None, "alg_bytes_per_launch": int(alg), "avg_launch_ms": round(ph["rebuild"], 5),
+                    "target_faces_mean": round(tf_mean)}
+    out_json = {
+        "metric": METRIC, "value": round(1000.0 / ms_per_step, 2), "unit": "frames/s", "n_gpus": 1,
+        "steps": K, "warmup": 1, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"track: {WORKLOADS['track'][1]}", "frames": T, "template_vertices": NV,
+                   "every": 50, "w_track": 0.8, "timing": "eager" if args.eager else "hip-graph"},
+        "kernels_ms": {k: round(v, 5) for k, v in ph.items()},
+        "queries_per_s": round(NV * 1000.0 / ms_per_step, 1),
+        "traversal": {"node_expansions_per_query": round(n_exp / n_q, 1),
+                      "exact_leaf_tests_per_query": round(n_lex / n_q, 1)},
+        "roofline": roofline,
+        "wall_s": round(wall, 4), "setup_s": round(setup_s, 2),
+    }
+    if not args.no_cpu_baseline:
+        out_json["cpu_baseline"] = cpu_baseline_track(sc, targets_np, args.cpu_sample or 4000)
+    print(json.dumps(out_json))
+
+
+def cpu_baseline_track(sc, targets_np, n_sample):
+    """The float64 oracle's tracking step for frame 1 on a sample of template points, scaled to frames/s."""
+    from oracle import tracking as otr
+    rng = np.random.default_rng(0)
+    idx = rng.choice(sc.n_verts, min(n_sample, sc.n_verts), replace=False)
+    tv, tf = targets_np[1]
+    t = time.perf_counter()
+    otr.track_step(sc.verts0[:, idx].astype(np.float64), tv.astype(np.float64), tf)
+    sec = (time.perf_counter() - t) * sc.n_verts / idx.size
+    th = omp_threads()
+    return {"value": 1.0 / sec, "unit": "frames/s", "cores": th, "kind": "oracle",
+            "sample": (f"frame 1: brute-force plain-C closest points of {idx.size} random template vertices "
+                       f"(OpenMP, {th} threads), scaled to all {sc.n_verts}"),
+            "wall_s": round(time.perf_counter() - t, 2)}
 
 
 def run_batched(args):
@@ -454,6 +559,8 @@ def main():
         return run_batched(args)
     if args.workload == "c4":
         return run_refine(args)
+    if args.workload == "track":
+        return run_track(args)
     cfg, desc = WORKLOADS[args.workload]
 
     from synth import make_config

@@ -85,6 +85,11 @@ mg_status mg_vertex_buffer_update(const float *frames, int32_t n_frames, int32_t
  * captured HIP graph); used to clear gradient accumulators. */
 mg_status mg_fill(float *x, int64_t n, float value, void *stream);
 
+/* out[n] = wa a[n] + wb b[n] on the device (out may alias a or b).  The
+ * re-anchoring of temporal correspondence tracking (Sec. 3.3, Strategy 1:
+ * every 50 frames, 80% tracked motion blended with 20% template projection). */
+mg_status mg_blend(const float *a, const float *b, float wa, float wb, float *out, int64_t n, void *stream);
+
 /* ------------------------------------------------------------------------
  * Face-bound Gaussian re-pose (render side of the dual representation,
  * Sec. 3.2).  The paper states no binding formula; the library computes, per

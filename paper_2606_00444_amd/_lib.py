@@ -63,6 +63,7 @@ PROTOTYPES = {
     "mg_frame_index": (I32, [I64, I64, I64, I64, I32, P]),
     "mg_vertex_buffer_update": (I32, [P, I32, I32, I32, P, P]),
     "mg_fill": (I32, [P, I64, F32, P]),
+    "mg_blend": (I32, [P, P, F32, F32, P, I64, P]),
     "mg_mesh_gaussian_update": (I32, [P, I32, P, I32, P, P, P, P, P, I32, U32, P, P, P, P, P]),
     "mg_mesh_gaussian_update_backward": (I32, [P, I32, P, I32, P, P, P, P, P, I32, P, P, P, P, P]),
     "mg_lbvh_layout_query": (I32, [I32, I32, P]),

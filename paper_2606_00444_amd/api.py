@@ -15,7 +15,7 @@ from . import _lib
 from ._lib import MG_PRIM_POINTS, MG_PRIM_TRIANGLES, MG_QUERY_AUTO, MG_QUERY_BATCH, MG_QUERY_LANE, LbvhLayout, QueryOptions
 
 __all__ = [
-    "frame_index", "vertex_buffer_update", "fill", "mesh_gaussian_update", "mesh_gaussian_update_backward",
+    "frame_index", "vertex_buffer_update", "fill", "blend", "mesh_gaussian_update", "mesh_gaussian_update_backward",
     "LBVH", "query_order", "lbvh_bytes", "lbvh_workspace_bytes", "lbvh_build", "lbvh_refit", "closest_point_query", "closest_point_bruteforce",
     "nearest_point_query", "mean", "chamfer", "point_mesh_backward", "chamfer_backward", "adam_step",
     "validate_indices", "validate_finite", "version", "check_device",
@@ -96,6 +96,17 @@ def fill(x, value=0.0):
     """x[:] = value on the device (float32, contiguous); graph-capturable."""
     _call("mg_fill", _ptr(_f32(x)), x.numel(), float(value), _stream())
     return x
+
+
+def blend(a, b, wa, wb, out=None):
+    """out = wa * a + wb * b on the device (float32, same shape; out may be a or b)."""
+    if a.shape != b.shape:
+        raise ValueError("blend: a and b must have the same shape")
+    out = torch.empty_like(a) if out is None else out
+    if out.shape != a.shape:
+        raise ValueError("blend: out must have the shape of a")
+    _call("mg_blend", _ptr(_f32(a)), _ptr(_f32(b)), float(wa), float(wb), _ptr(_f32(out)), a.numel(), _stream())
+    return out
 
 
 def mesh_gaussian_update(verts, faces, gface, bary, q_local, log_scale, offset=None, *, out=None,

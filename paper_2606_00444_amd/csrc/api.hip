@@ -29,6 +29,14 @@ __global__ __launch_bounds__(256) void fill_kernel(float *__restrict__ x, int64_
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = value;
 }
 
+// out = wa a + wb b, element by element (out may be a or b).
+__global__ __launch_bounds__(256) void blend_kernel(const float *a, const float *b, float wa, float wb, float *out,
+                                                    int64_t n) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = wa * a[i] + wb * b[i];
+}
+
 }  // namespace
 }  // namespace mgu
 
@@ -98,5 +106,14 @@ extern "C" mg_status mg_fill(float *x, int64_t n, float value, void *stream) {
     if (n == 0) return MG_OK;
     const int grid = static_cast<int>(std::min<int64_t>(blocks_for(n, 256), 2048));
     hipLaunchKernelGGL(fill_kernel, dim3(grid), dim3(256), 0, as_stream(stream), x, n, value);
+    return launch_status();
+}
+
+extern "C" mg_status mg_blend(const float *a, const float *b, float wa, float wb, float *out, int64_t n,
+                              void *stream) {
+    if (n < 0 || (n > 0 && (!a || !b || !out))) return MG_ERR_INVALID_ARGUMENT;
+    if (n == 0) return MG_OK;
+    const int grid = static_cast<int>(std::min<int64_t>(blocks_for(n, 256), 2048));
+    hipLaunchKernelGGL(blend_kernel, dim3(grid), dim3(256), 0, as_stream(stream), a, b, wa, wb, out, n);
     return launch_status();
 }
