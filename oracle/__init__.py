@@ -29,8 +29,10 @@ Dynamic Mesh-Gaussian Reconstructions", arXiv 2606.00444):
              means, both directions, no factor 1/2), and their gradients with
              respect to the template vertices, through the binding.
 * adam       Adam (Kingma & Ba 2015) with torch.optim.Adam's update order.
+* knn        k-NN weighted surface projection (the NearestSurface variant of Sec. 3.3;
+             k and weights unstated: k nearest faces, inverse-distance weights).
 * tracking   temporal correspondence tracking (Sec. 3.3, Eq. 1): closest points
              carried frame to frame, re-anchored to the template projection.
 """
 
-from . import frame, gaussians, morton, lbvh, closest, losses, adam, tracking  # noqa: F401
+from . import frame, gaussians, morton, lbvh, closest, losses, adam, tracking, knn  # noqa: F401
