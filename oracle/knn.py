@@ -8,7 +8,8 @@ without stating k or the weights.  Reading: the k faces nearest to the point
 id), each with its closest point c_i at distance d_i, combined as
 sum w_i c_i / sum w_i with inverse-distance weights w_i = 1 / (d_i + eps).
 k = 1 is the single closest point.  Parity with the paper is unpinned (k and
-the weights are ours); the definition itself is pinned by the tests.
+the weights are ours); a face at distance exactly 0 gives its own point.  The
+definition itself is pinned by the tests.
 """
 
 import numpy as np
@@ -44,12 +45,20 @@ def weighted_point(verts, faces, queries, face_k, eps):
     face_k = np.asarray(face_k, dtype=np.int64)
     num = np.zeros((3, face_k.shape[1]))
     den = np.zeros(face_k.shape[1])
+    hit = np.zeros(face_k.shape[1], bool)
+    on = np.zeros((3, face_k.shape[1]))
     for j in range(face_k.shape[0]):
         r = closest_on_faces(verts, faces, queries, face_k[j])
-        w = 1.0 / (np.sqrt(r["dist2"]) + eps)
-        num += w * r["point"]
-        den += w
-    return num / den
+        first = (r["dist2"] == 0) & ~hit
+        on[:, first] = r["point"][:, first]
+        hit |= first
+        with np.errstate(divide="ignore"):
+            w = 1.0 / (np.sqrt(r["dist2"]) + eps)
+        num += np.where(np.isfinite(w), w, 0.0) * r["point"]
+        den += np.where(np.isfinite(w), w, 0.0)
+    out = num / np.where(den > 0, den, 1.0)
+    out[:, hit] = on[:, hit]
+    return out
 
 
 def knn_surface(verts, faces, queries, k=4, eps=0.0):

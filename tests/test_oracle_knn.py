@@ -53,8 +53,10 @@ def test_point_on_the_surface_is_kept():
     v, f = icosphere(2)
     V, F = v.T.astype(np.float64), f.T
     P = V[:, ::7]                                          # mesh vertices: distance 0
-    r = ok.knn_surface(V, F, P, k=4, eps=1e-12)
-    np.testing.assert_allclose(r["point"], P, rtol=0, atol=1e-9)
+    r = ok.knn_surface(V, F, P, k=4, eps=0.0)
+    np.testing.assert_array_equal(r["point"], P)           # the exact-hit rule
+    r = ok.knn_surface(V, F, P + 1e-9, k=4, eps=1e-12)     # just off the surface
+    np.testing.assert_allclose(r["point"], P, rtol=0, atol=1e-6)
 
 
 def test_face_order_permutation_invariance():
