@@ -200,7 +200,8 @@ def run_track(args):
     NV = sc.n_verts
     out = torch.empty(T, 3, NV, device=dev)
     mg.vertex_buffer_update(V0.reshape(1, 3, NV), 0, out[0])
-    tr = Tracker(V0, max(f.shape[1] for _, f in targets_np), every=50, w_track=0.8)
+    L = float(np.ptp(sc.verts0, axis=1).max())
+    tr = Tracker(V0, max(f.shape[1] for _, f in targets_np), every=50, w_track=0.8, k=args.knn, eps=1e-6 * L)
     K = T - 1
 
     def run_all():
@@ -226,16 +227,26 @@ def run_track(args):
     mg.lbvh_build(tv, tf, bvh=bvh)
     from paper_2606_00444_amd.api import _query_out
     rec = _query_out(NV, dev, True, False, False, False)
+    if args.knn > 1:
+        kq = {"face": torch.empty(args.knn, NV, dtype=torch.int32, device=dev),
+              "dist2": torch.empty(args.knn, NV, device=dev), "point": rec["point"]}
+        project = lambda _: mg.knn_surface_query(bvh, tv, out[0], k=args.knn, eps=1e-6 * L, out=kq)
+    else:
+        project = lambda _: mg.closest_point_query(bvh, tv, out[0], out=rec)
     ph = {"rebuild": graph_ms(lambda _: mg.lbvh_build(tv, tf, bvh=bvh), 50, torch),
-          "query": graph_ms(lambda _: mg.closest_point_query(bvh, tv, out[0], out=rec), 50, torch)}
+          "query": graph_ms(project, 50, torch)}
     cnt = torch.zeros(4, dtype=torch.int64, device=dev)
-    mg.closest_point_query(bvh, tv, out[0], out=rec, counters=cnt)
+    if args.knn > 1:
+        mg.knn_surface_query(bvh, tv, out[0], k=args.knn, eps=1e-6 * L, out=kq, counters=cnt)
+    else:
+        mg.closest_point_query(bvh, tv, out[0], out=rec, counters=cnt)
     torch.cuda.synchronize()
     n_exp, n_lbox, n_lex, n_q = (int(x) for x in cnt.cpu())
     ops = 34.0 * n_exp + 29.0 * n_lbox + 80.0 * n_lex
     if ph["query"] >= ph["rebuild"]:
         achieved = ops / (ph["query"] * 1e-3) / 1e12
-        roofline = {"bound": "alu", "kernel": "traverse_batch_kernel (tracked points onto the frame's mesh)",
+        kname = "knn_lane_kernel" if args.knn > 1 else "traverse_batch_kernel"
+        roofline = {"bound": "alu", "kernel": f"{kname} (tracked points onto the frame's mesh)",
                     "achieved": round(achieved, 4), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5), "traffic": None,
                     "alg_ops_per_launch": int(ops), "avg_launch_ms": round(ph["query"], 5)}
@@ -252,7 +263,8 @@ def run_track(args):
         "steps": K, "warmup": 1, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"track: {WORKLOADS['track'][1]}", "frames": T, "template_vertices": NV,
-                   "every": 50, "w_track": 0.8, "timing": "eager" if args.eager else "hip-graph"},
+                   "every": 50, "w_track": 0.8, "nearest_surface": "closest point" if args.knn <= 1 else
+                   f"k-NN weighted, k = {args.knn}, w = 1/(d + 1e-6 L)", "timing": "eager" if args.eager else "hip-graph"},
         "kernels_ms": {k: round(v, 5) for k, v in ph.items()},
         "queries_per_s": round(NV * 1000.0 / ms_per_step, 1),
         "traversal": {"node_expansions_per_query": round(n_exp / n_q, 1),
@@ -541,6 +553,7 @@ def main():
     ap.add_argument("--phase", choices=["copy", "update", "refit", "collide", "rebuild", "target_queries"],
                     help="profiling aid (c1/c2/c5): run only this phase --reps times, eagerly, and exit")
     ap.add_argument("--reps", type=int, default=60)
+    ap.add_argument("--knn", type=int, default=1, help="track: NearestSurface with the k nearest faces (1-8)")
     ap.add_argument("--copy-calibration", type=int, metavar="MB", default=0,
                     help="profiling aid: copy MB megabytes with the vertex-buffer copy kernel --reps times and exit")
     args = ap.parse_args()

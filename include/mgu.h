@@ -288,6 +288,24 @@ mg_status mg_closest_point_bruteforce(const float *verts, int32_t n_verts, const
                                       float max_dist2, int32_t *face, float *point, float *bary,
                                       float *dist2, float *normal, void *stream);
 
+/* k-NN weighted surface projection (the weighted nearest-neighbour variant of
+ * NearestSurface in Sec. 3.3; the paper states neither k nor the weights).
+ * For every query, the k faces of a MG_PRIM_TRIANGLES BVH nearest
+ * to it (1 <= k <= 8; ties of the squared distance to the lowest original face
+ * id; faces farther than max_dist2 are ignored), and their closest points c_i
+ * at distances d_i combined as point = sum w_i c_i / sum w_i with
+ * w_i = 1 / (d_i + eps) (eps >= 0; a face at distance exactly 0 gives its point).
+ * Outputs (device): face_k [k][n_queries] (-1 where fewer than k faces exist or
+ * lie within max_dist2), dist2_k [k][n_queries] or NULL (+inf for -1 entries),
+ * point [3][n_queries] or NULL (the query itself when no face qualifies).
+ * counters: NULL or a device uint64 [4] accumulating node expansions, leaf
+ * bound tests, exact leaf tests and queries (as mg_query_options.counters).
+ * One query per lane; k = 1 gives the single closest point (unweighted). */
+mg_status mg_knn_surface_query(const void *bvh, size_t bvh_bytes, int32_t n_prims, const float *verts,
+                               int32_t n_verts, const float *queries, int32_t n_queries, int32_t k,
+                               float eps, float max_dist2, int32_t *face_k, float *dist2_k, float *point,
+                               uint64_t *counters, void *stream);
+
 /* Nearest point of a MG_PRIM_POINTS BVH built over points [3][n_prims]:
  * index[q] (lowest index on exact ties, -1 if none within max_dist2) and
  * dist2[q] (+inf if none); dist2 may be NULL.  opts as for mg_closest_point_query. */

@@ -73,6 +73,7 @@ PROTOTYPES = {
     "mg_closest_point_query": (I32, [P, SZ, I32, P, I32, P, I32, F32, P, P, P, P, P, P, P]),
     "mg_closest_point_bruteforce": (I32, [P, I32, P, I32, P, I32, F32, P, P, P, P, P, P]),
     "mg_nearest_point_query": (I32, [P, SZ, I32, P, P, I32, F32, P, P, P, P]),
+    "mg_knn_surface_query": (I32, [P, SZ, I32, P, I32, P, I32, I32, F32, F32, P, P, P, P, P]),
     "mg_reduce_workspace_size": (I32, [I64, P]),
     "mg_mean": (I32, [P, I64, P, P, SZ, P]),
     "mg_chamfer": (I32, [P, I32, P, SZ, P, I32, P, SZ, P, P, P, P, P, P, SZ, P, P]),

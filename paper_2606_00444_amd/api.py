@@ -17,7 +17,7 @@ from ._lib import MG_PRIM_POINTS, MG_PRIM_TRIANGLES, MG_QUERY_AUTO, MG_QUERY_BAT
 __all__ = [
     "frame_index", "vertex_buffer_update", "fill", "blend", "mesh_gaussian_update", "mesh_gaussian_update_backward",
     "LBVH", "query_order", "lbvh_bytes", "lbvh_workspace_bytes", "lbvh_build", "lbvh_refit", "closest_point_query", "closest_point_bruteforce",
-    "nearest_point_query", "mean", "chamfer", "point_mesh_backward", "chamfer_backward", "adam_step",
+    "nearest_point_query", "knn_surface_query", "mean", "chamfer", "point_mesh_backward", "chamfer_backward", "adam_step",
     "validate_indices", "validate_finite", "version", "check_device",
 ]
 
@@ -266,6 +266,21 @@ def closest_point_bruteforce(verts, faces, queries, max_dist2=math.inf, *, norma
     _call("mg_closest_point_bruteforce", _ptr(verts), verts.shape[1], _ptr(_i32(faces)), faces.shape[1],
           _ptr(queries), nq, float(max_dist2), _ptr(o["face"]), _ptr(o["point"]), _ptr(o["bary"]),
           _ptr(o["dist2"]), _ptr(o["normal"]), _stream())
+    return o
+
+
+def knn_surface_query(bvh, verts, queries, k=4, eps=0.0, max_dist2=math.inf, *, out=None, counters=None):
+    """k-NN weighted surface projection: dict face [k][Q] int32, dist2 [k][Q], point [3][Q]."""
+    if bvh.kind != MG_PRIM_TRIANGLES:
+        raise ValueError("knn_surface_query needs a triangle BVH")
+    nq = _f32(queries, 3, "queries").shape[1]
+    o = dict(out or {})
+    for key, shape, dt in (("face", (k, nq), torch.int32), ("dist2", (k, nq), torch.float32), ("point", (3, nq), torch.float32)):
+        if o.get(key) is None:
+            o[key] = torch.empty(shape, dtype=dt, device=queries.device)
+    _call("mg_knn_surface_query", _ptr(bvh.buf), bvh.nbytes, bvh.n, _ptr(verts), verts.shape[1], _ptr(queries), nq,
+          int(k), float(eps), float(max_dist2), _ptr(_i32(o["face"])), _ptr(_f32(o["dist2"])), _ptr(_f32(o["point"])),
+          _ptr(counters), _stream())
     return o
 
 

@@ -109,6 +109,130 @@ __global__ __launch_bounds__(64 * kBatchWaves) void traverse_batch_kernel(QueryA
                         stacks[w]);
 }
 
+// ----------------------------------------------------------------- k nearest
+// One query per lane, depth-first like the lane kernel, keeping the K best
+// (d^2, original id, leaf) in registers sorted by (d^2, id); a child is pruned
+// against the k-th best (k <= K at run time).  At the end the k closest points
+// are combined with inverse-distance weights 1 / (d + eps) (the weighted
+// nearest-neighbour NearestSurface of Sec. 3.3); a face at distance 0 gives its
+// own point.
+template <int K>
+__global__ __launch_bounds__(kLaneBlock) void knn_lane_kernel(QueryArgs a, int k, float eps, int32_t *face_k,
+                                                              float *dist2_k) {
+    unsigned long long n_exp = 0, n_lbox = 0, n_lex = 0;
+    __shared__ int32_t s_stack[kLdsStack][kLaneBlock];
+    int32_t deep[kMaxStack - kLdsStack];
+    const int lane = threadIdx.x;
+    const int64_t q = static_cast<int64_t>(blockIdx.x) * kLaneBlock + lane;
+    if (q >= a.nq) return;
+    const f3 p = load3(a.queries, a.nq, q);
+    float bd[K];
+    int32_t bid[K], bleaf[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        bd[j] = a.maxd2;
+        bid[j] = INT_MAX;
+        bleaf[j] = -1;
+    }
+    // the k-th best (registers are not indexed at run time)
+    auto kth = [&]() {
+        float b = bd[0];
+#pragma unroll
+        for (int j = 1; j < K; ++j)
+            if (j == k - 1) b = bd[j];
+        return b;
+    };
+    auto consider = [&](float d2, int32_t id, int32_t leaf) {
+        ++n_lex;
+        const bool in = d2 < bd[K - 1] || (d2 == bd[K - 1] && id < bid[K - 1]);
+        if (!in) return;
+        bd[K - 1] = d2;
+        bid[K - 1] = id;
+        bleaf[K - 1] = leaf;
+#pragma unroll
+        for (int j = K - 1; j > 0; --j) {
+            const bool up = bd[j] < bd[j - 1] || (bd[j] == bd[j - 1] && bid[j] < bid[j - 1]);
+            if (up) {
+                const float td = bd[j]; bd[j] = bd[j - 1]; bd[j - 1] = td;
+                const int32_t ti = bid[j]; bid[j] = bid[j - 1]; bid[j - 1] = ti;
+                const int32_t tl = bleaf[j]; bleaf[j] = bleaf[j - 1]; bleaf[j - 1] = tl;
+            }
+        }
+    };
+
+    if (a.n == 1) {
+        consider(single_leaf_dist2<true>(a, p), a.prim[0], 0);
+    } else if (a.n > 1) {
+        const f3 rlo = f3{a.root[0], a.root[1], a.root[2]};
+        const f3 rhi = f3{a.root[4], a.root[5], a.root[6]};
+        int sp = 0;
+        int32_t node = box_dist2(p, rlo, rhi) <= kth() * kPruneSlack ? 0 : -1;
+        for (int64_t step = 0; node >= 0 && node < a.n - 1 && step < a.n + 64; ++step) {
+            const float4 *rec = a.nodes + 6 * static_cast<int64_t>(node);
+            const float4 l0 = rec[0], l1 = rec[1], l2 = rec[2], r0 = rec[3], r1 = rec[4], r2 = rec[5];
+            const int32_t lref = __float_as_int(l0.w), rref = __float_as_int(r0.w);
+            if (lref >= a.n - 1 || rref >= a.n - 1 || ~lref >= a.n || ~rref >= a.n) break;
+            ++n_exp;
+            n_lbox += (lref < 0) + (rref < 0);
+            if (lref < 0 && leaf_box_dist2<true>(p, l0, l1, l2) <= kth() * kPruneSlack)
+                consider(leaf_dist2<true>(p, l0, l1, l2), __float_as_int(l1.w), ~lref);
+            if (rref < 0 && leaf_box_dist2<true>(p, r0, r1, r2) <= kth() * kPruneSlack)
+                consider(leaf_dist2<true>(p, r0, r1, r2), __float_as_int(r1.w), ~rref);
+            const float bound = kth() * kPruneSlack;
+            const float dl = lref >= 0 ? box_dist2(p, xyz(l0), xyz(l1)) : INFINITY;
+            const float dr = rref >= 0 ? box_dist2(p, xyz(r0), xyz(r1)) : INFINITY;
+            const bool gl = lref >= 0 && dl <= bound, gr = rref >= 0 && dr <= bound;
+            if (gl && gr) {
+                const bool left_first = dl <= dr;
+                const int32_t far = left_first ? rref : lref;
+                node = left_first ? lref : rref;
+                if (sp < kLdsStack) s_stack[sp][lane] = far;
+                else if (sp < kMaxStack) deep[sp - kLdsStack] = far;
+                sp = sp < kMaxStack ? sp + 1 : sp;
+            } else if (gl) {
+                node = lref;
+            } else if (gr) {
+                node = rref;
+            } else if (sp > 0) {
+                --sp;
+                node = sp < kLdsStack ? s_stack[sp][lane] : deep[sp - kLdsStack];
+            } else {
+                node = -1;
+            }
+        }
+    }
+    f3 num = f3{0.0f, 0.0f, 0.0f};
+    float den = 0.0f;
+    bool hit = false;                       // a face at distance 0: its point, unweighted
+    f3 on = p;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (j >= k) break;
+        const int32_t leaf = bleaf[j];
+        const bool ok = leaf >= 0 && leaf < a.n;
+        face_k[j * a.nq + q] = ok ? bid[j] : -1;
+        if (dist2_k) dist2_k[j * a.nq + q] = ok ? bd[j] : INFINITY;
+        if (!ok) continue;
+        const f3 A = load3(a.verts, a.nv, a.leaf_faces[leaf]);
+        const f3 B = load3(a.verts, a.nv, a.leaf_faces[a.n + leaf]);
+        const f3 C = load3(a.verts, a.nv, a.leaf_faces[2 * a.n + leaf]);
+        float w1, w2;
+        const float d2 = tri_closest(p, A, B, C, w1, w2);
+        const float w0 = 1.0f - w1 - w2;
+        const f3 c = f3{w0 * A.x + w1 * B.x + w2 * C.x, w0 * A.y + w1 * B.y + w2 * C.y,
+                        w0 * A.z + w1 * B.z + w2 * C.z};
+        if ((d2 == 0.0f || k == 1) && !hit) {   // k = 1: the closest point itself, unweighted
+            hit = true;
+            on = c;
+        }
+        const float w = 1.0f / (sqrtf(d2) + eps);
+        num = num + w * c;
+        den += w;
+    }
+    if (a.point) store3(a.point, a.nq, q, hit ? on : (den > 0.0f ? (1.0f / den) * num : p));
+    if (a.counters) add_counters(a, n_exp, n_lbox, n_lex, 1);
+}
+
 // Every face for every query, in original face order (strict < keeps the
 // lowest id on exact ties).
 __global__ __launch_bounds__(256) void bruteforce_kernel(const float *__restrict__ verts, int64_t nv,
@@ -263,5 +387,35 @@ extern "C" mg_status mg_closest_point_bruteforce(const float *verts, int32_t n_v
     hipLaunchKernelGGL(bruteforce_kernel, dim3(blocks_for(n_queries, 256)), dim3(256), 0, as_stream(stream),
                        verts, (int64_t)n_verts, faces, (int64_t)n_faces, queries, (int64_t)n_queries, max_dist2,
                        face, point, bary, dist2, normal);
+    return launch_status();
+}
+
+extern "C" mg_status mg_knn_surface_query(const void *bvh, size_t bvh_bytes, int32_t n_prims, const float *verts,
+                                          int32_t n_verts, const float *queries, int32_t n_queries, int32_t k,
+                                          float eps, float max_dist2, int32_t *face_k, float *dist2_k,
+                                          float *point, uint64_t *counters, void *stream) {
+    if (bad_count(n_prims) || bad_count(n_verts) || bad_count(n_queries) || !bvh || k < 1 || k > 8 ||
+        !(eps >= 0.0f) || !(max_dist2 >= 0.0f))
+        return MG_ERR_INVALID_ARGUMENT;
+    mg_lbvh_layout L;
+    mg_lbvh_layout_query(n_prims, MG_PRIM_TRIANGLES, &L);
+    if (bvh_bytes < static_cast<size_t>(L.total_bytes)) return MG_ERR_WORKSPACE_TOO_SMALL;
+    if (n_queries == 0) return MG_OK;
+    if (!queries || !face_k || (n_prims > 0 && (!verts || n_verts == 0))) return MG_ERR_INVALID_ARGUMENT;
+    QueryArgs a{};
+    a.nodes = cat<float4>(bvh, L.off_nodes);
+    a.root = cat<mg_lbvh_header>(bvh, L.off_header)->root_lo;
+    a.leaf_faces = cat<int32_t>(bvh, L.off_leaf_faces);
+    a.prim = cat<int32_t>(bvh, L.off_prim);
+    a.verts = verts; a.nv = n_verts; a.n = n_prims;
+    a.queries = queries; a.nq = n_queries; a.maxd2 = max_dist2;
+    a.point = point;
+    a.counters = reinterpret_cast<unsigned long long *>(counters);
+    const dim3 g(static_cast<unsigned>(blocks_for(n_queries, kLaneBlock))), b(kLaneBlock);
+    hipStream_t s = as_stream(stream);
+    if (k <= 1) hipLaunchKernelGGL(knn_lane_kernel<1>, g, b, 0, s, a, k, eps, face_k, dist2_k);
+    else if (k <= 2) hipLaunchKernelGGL(knn_lane_kernel<2>, g, b, 0, s, a, k, eps, face_k, dist2_k);
+    else if (k <= 4) hipLaunchKernelGGL(knn_lane_kernel<4>, g, b, 0, s, a, k, eps, face_k, dist2_k);
+    else hipLaunchKernelGGL(knn_lane_kernel<8>, g, b, 0, s, a, k, eps, face_k, dist2_k);
     return launch_status();
 }

@@ -8,7 +8,8 @@ closest-point query with the tracked points as queries).  To limit drift, every
 the tracked motion blended with 1 - w_track of the direct template projection
 (Eq. 2, the template's own vertices projected onto that mesh); the paper uses
 every = 50 and w_track = 0.8.  The track starts from the template vertices;
-NearestSurface is the single closest point; the blend is used as it is.
+NearestSurface is the single closest point (k = 1) or, with k > 1, the k-NN
+weighted projection (mg_knn_surface_query); the blend is used as it is.
 Every step runs in the library's kernels (build, query, blend).
 """
 
@@ -24,31 +25,42 @@ class Tracker:
     BVH buffer and workspace serve every frame).  query: traversal options.
     """
 
-    def __init__(self, template_verts, max_faces, *, every=50, w_track=0.8, query=None):
+    def __init__(self, template_verts, max_faces, *, every=50, w_track=0.8, query=None, k=1, eps=0.0):
         dev = template_verts.device
         self.template = template_verts
         self.every, self.w_track = int(every), float(w_track)
+        self.k, self.eps = int(k), float(eps)
         self.query = dict(query or {})
         self.buf = torch.empty(api.lbvh_bytes(max_faces), dtype=torch.uint8, device=dev)
         self.ws = torch.empty(max(api.lbvh_workspace_bytes(max_faces), 1), dtype=torch.uint8, device=dev)
         n = template_verts.shape[1]
         self.rec = api._query_out(n, dev, True, False, False, False)
         self.anchor = api._query_out(n, dev, True, False, False, False)
+        if self.k > 1:
+            self.knn = {"face": torch.empty(self.k, n, dtype=torch.int32, device=dev),
+                        "dist2": torch.empty(self.k, n, device=dev)}
+            self.knn_anchor = dict(self.knn, point=self.anchor["point"])
+
+    def _project(self, bvh, verts, points, out_rec, knn_out):
+        if self.k > 1:
+            api.knn_surface_query(bvh, verts, points, k=self.k, eps=self.eps, out=knn_out)
+        else:
+            api.closest_point_query(bvh, verts, points, point=True, bary=False, dist2=False, out=out_rec,
+                                    **self.query)
 
     def step(self, points, verts, faces, t, out):
         """Tracked points of frame t (>= 1) on mesh (verts, faces) into out [3][N], from points [3][N]."""
         bvh = api.LBVH(faces.shape[1], api.MG_PRIM_TRIANGLES, verts.device, buf=self.buf, ws=self.ws)
         api.lbvh_build(verts, faces, bvh=bvh)
         self.rec["point"] = out
-        api.closest_point_query(bvh, verts, points, point=True, bary=False, dist2=False, out=self.rec, **self.query)
+        self._project(bvh, verts, points, self.rec, dict(self.knn, point=out) if self.k > 1 else None)
         if self.every and t % self.every == 0:
-            api.closest_point_query(bvh, verts, self.template, point=True, bary=False, dist2=False,
-                                    out=self.anchor, **self.query)
+            self._project(bvh, verts, self.template, self.anchor, self.knn_anchor if self.k > 1 else None)
             api.blend(out, self.anchor["point"], self.w_track, 1.0 - self.w_track, out=out)
         return out
 
 
-def track_correspondences(template_verts, targets, *, every=50, w_track=0.8, query=None, out=None):
+def track_correspondences(template_verts, targets, *, every=50, w_track=0.8, query=None, k=1, eps=0.0, out=None):
     """Tracked template vertices of every frame: [T][3][N] (frame 0 = the template).
 
     targets: list of (verts [3][V_t] float32, faces [3][F_t] int32) device tensors.
@@ -57,7 +69,8 @@ def track_correspondences(template_verts, targets, *, every=50, w_track=0.8, que
     n = template_verts.shape[1]
     out = torch.empty(T, 3, n, device=template_verts.device) if out is None else out
     api.vertex_buffer_update(template_verts.reshape(1, 3, n), 0, out[0])
-    tr = Tracker(template_verts, max(f.shape[1] for _, f in targets), every=every, w_track=w_track, query=query)
+    tr = Tracker(template_verts, max(f.shape[1] for _, f in targets), every=every, w_track=w_track, query=query,
+                 k=k, eps=eps)
     for t in range(1, T):
         tv, tf = targets[t]
         tr.step(out[t - 1], tv, tf, t, out[t])

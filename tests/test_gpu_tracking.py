@@ -113,3 +113,26 @@ def test_blend(device):
     np.testing.assert_allclose(out, 0.8 * a.astype(np.float64) + 0.2 * b, rtol=1e-6, atol=1e-6)
     mg.blend(A, B, 0.8, 0.2, out=A)                       # in place
     np.testing.assert_array_equal(host(A), out)
+
+
+def test_tracking_with_knn_projection(device):
+    """Strategy 1 with the k-NN weighted NearestSurface (k = 4): 12 frames of the small
+    sequence with re-anchoring every 5; each frame against the oracle's step from the
+    device's previous frame (ties of the k-th face may choose another face: 99.5% of
+    points match, the rest are bounded by the mesh scale)."""
+    from paper_2606_00444_amd.tracking import track_correspondences
+    sc = make_config(2, small=True)
+    T, k = 12, 4
+    L = scale_of(sc.verts0)
+    eps = 1e-6 * L
+    targets_np = [sc.target(t) for t in range(T)]
+    targets = [(dev(v, device), dev(f, device)) for v, f in targets_np]
+    tr = host(track_correspondences(dev(sc.verts0, device), targets, every=5, k=k, eps=eps))
+    for t in range(1, T):
+        tv, tf = targets_np[t]
+        want = otr.track_step(tr[t - 1].astype(np.float64), tv.astype(np.float64), tf, k, eps)
+        if t % 5 == 0:
+            want = 0.8 * want + 0.2 * otr.track_step(sc.verts0.astype(np.float64), tv.astype(np.float64), tf, k, eps)
+        near = (np.abs(tr[t] - want) <= 1e-5 * np.maximum(np.abs(want), 0.1 * L)).all(axis=0)
+        assert near.mean() >= 0.995, (t, near.mean())
+        assert np.abs(tr[t] - want).max() <= 0.05 * L

@@ -66,3 +66,17 @@ def test_blend_of_distinct_tracks():
     tr = otr.track(P, targets, every=2, w_track=0.8)
     np.testing.assert_allclose(tr[2][0], [0.8 * 0.5 + 0.2 * 0.3], rtol=0, atol=1e-14)
     np.testing.assert_allclose(tr[2][1:], [[0.5], [0.0]], rtol=0, atol=1e-14)
+
+
+def test_knn_variant_reduces_to_closest_and_keeps_static_points():
+    v, f = icosphere(1)
+    V, F = v.T.astype(np.float64), f.T
+    targets = [(V, F)] * 4
+    # vertices are exact hits: with any k the track stays put
+    np.testing.assert_array_equal(otr.track(V, targets, every=2, k=4), np.stack([V] * 4))
+    # k = 1 is the closest-point track
+    P = 0.9 * V
+    tv, tf = _square(z=0.1)
+    a = otr.track(P[:, :10], [(tv, tf)] * 3, every=2, k=1)
+    b = otr.track(P[:, :10], [(tv, tf)] * 3, every=2)
+    np.testing.assert_array_equal(a, b)
