@@ -31,8 +31,10 @@ Dynamic Mesh-Gaussian Reconstructions", arXiv 2606.00444):
 * adam       Adam (Kingma & Ba 2015) with torch.optim.Adam's update order.
 * knn        k-NN weighted surface projection (the NearestSurface variant of Sec. 3.3;
              k and weights unstated: k nearest faces, inverse-distance weights).
+* sdf        index signed-distance grid (the SDF of Sec. 3.4): nearest template faces
+             stored per node, signed distances recomputed per frame, trilinear sampling.
 * tracking   temporal correspondence tracking (Sec. 3.3, Eq. 1): closest points
              carried frame to frame, re-anchored to the template projection.
 """
 
-from . import frame, gaussians, morton, lbvh, closest, losses, adam, tracking, knn  # noqa: F401
+from . import frame, gaussians, morton, lbvh, closest, losses, adam, tracking, knn, sdf  # noqa: F401
