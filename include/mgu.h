@@ -315,6 +315,37 @@ mg_status mg_nearest_point_query(const void *bvh, size_t bvh_bytes, int32_t n_pr
                                  const mg_query_options *opts, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Index signed-distance grid: the SDF the paper builds from the template
+ * faces beside the BVH (Sec. 3.4, Initialization: structures that store only
+ * indices and serve every frame).  An nx x ny x nz grid (each >= 2, at most
+ * 2^31 - 1 nodes) with node (i, j, k) at lo + h (i, j, k), node index
+ * i + nx (j + ny k).  At initialisation every node stores the ids of its k
+ * nearest template faces (mg_knn_surface_query on the node positions); per
+ * frame mg_sdf_update recomputes each node's signed distance from those faces'
+ * current vertices: the minimum point-to-triangle distance over them (ties to
+ * the lowest slot), positive where the winning face's normal points (and on
+ * its plane), negative behind it.  Exact while a node's nearest face stays
+ * among its k; an upper bound of the unsigned distance otherwise.
+ * ---------------------------------------------------------------------- */
+
+/* points [3][nx ny nz] (device) <- the node positions. */
+mg_status mg_grid_points(float lo_x, float lo_y, float lo_z, float h, int32_t nx, int32_t ny, int32_t nz,
+                         float *points, void *stream);
+
+/* sdf [nx ny nz] (device) <- signed distances of the nodes to their faces
+ * face_k [k][nx ny nz] (1 <= k <= 64; ids outside [0, n_faces) are ignored;
+ * a node with no valid face gets +inf); face [nx ny nz] (device, or NULL) <-
+ * the winning face id (-1 if none).  verts [3][n_verts], faces [3][n_faces]. */
+mg_status mg_sdf_update(const float *verts, int32_t n_verts, const int32_t *faces, int32_t n_faces,
+                        const int32_t *face_k, int32_t k, float lo_x, float lo_y, float lo_z, float h,
+                        int32_t nx, int32_t ny, int32_t nz, float *sdf, int32_t *face, void *stream);
+
+/* out [n_queries] (device) <- trilinear interpolation of the node values sdf at
+ * queries [3][n_queries]; +inf for a query outside the grid's box. */
+mg_status mg_sdf_sample(const float *sdf, float lo_x, float lo_y, float lo_z, float h, int32_t nx, int32_t ny,
+                        int32_t nz, const float *queries, int32_t n_queries, float *out, void *stream);
+
+/* ------------------------------------------------------------------------
  * Losses for differentiable template projection.  Chamfer distance is used
  * by the paper as a metric (Sec. 4.2) without a formula; the library's is
  * CD(A,B) = mean_a min_b |a-b|^2 + mean_b min_a |a-b|^2.

@@ -270,13 +270,14 @@ def closest_point_bruteforce(verts, faces, queries, max_dist2=math.inf, *, norma
 
 
 def knn_surface_query(bvh, verts, queries, k=4, eps=0.0, max_dist2=math.inf, *, out=None, counters=None):
-    """k-NN weighted surface projection: dict face [k][Q] int32, dist2 [k][Q], point [3][Q]."""
+    """k-NN weighted surface projection: dict face [k][Q] int32, dist2 [k][Q], point [3][Q]
+    (out={"point": None} skips the weighted point)."""
     if bvh.kind != MG_PRIM_TRIANGLES:
         raise ValueError("knn_surface_query needs a triangle BVH")
     nq = _f32(queries, 3, "queries").shape[1]
     o = dict(out or {})
     for key, shape, dt in (("face", (k, nq), torch.int32), ("dist2", (k, nq), torch.float32), ("point", (3, nq), torch.float32)):
-        if o.get(key) is None:
+        if key not in o or (o[key] is None and key != "point"):
             o[key] = torch.empty(shape, dtype=dt, device=queries.device)
     _call("mg_knn_surface_query", _ptr(bvh.buf), bvh.nbytes, bvh.n, _ptr(verts), verts.shape[1], _ptr(queries), nq,
           int(k), float(eps), float(max_dist2), _ptr(_i32(o["face"])), _ptr(_f32(o["dist2"])), _ptr(_f32(o["point"])),
