@@ -33,8 +33,10 @@ Dynamic Mesh-Gaussian Reconstructions", arXiv 2606.00444):
              k and weights unstated: k nearest faces, inverse-distance weights).
 * sdf        index signed-distance grid (the SDF of Sec. 3.4): nearest template faces
              stored per node, signed distances recomputed per frame, trilinear sampling.
+* contact    sphere-mesh contact step from on-demand face normals (collision response
+             for the falling-sphere simulation of Sec. 4.1; the engine is out of scope).
 * tracking   temporal correspondence tracking (Sec. 3.3, Eq. 1): closest points
              carried frame to frame, re-anchored to the template projection.
 """
 
-from . import frame, gaussians, morton, lbvh, closest, losses, adam, tracking, knn, sdf  # noqa: F401
+from . import frame, gaussians, morton, lbvh, closest, losses, adam, tracking, knn, sdf, contact  # noqa: F401
