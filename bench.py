@@ -48,6 +48,9 @@ WORKLOADS = {
               "100,000 target samples; one Adam step of P + Chamfer"),
     "c5": (5, "UV-sphere 250,002 V / 500,000 F, 1,000,000 Gaussians, 1,000,000 queries, 100 frames, "
               "1,000,000-face split rebuild targets"),
+    "contact": (2, "sphere-mesh contact: 50,000 spheres (radius 1% of the template) falling at 240 steps/s onto "
+                   "the deforming 40,000-face template; per step vertex copy, refit, integration, closest "
+                   "points with normals, contact response"),
     "sdf": (2, "index signed-distance grid: the 40,000-face template's 64^3 grid (4 nearest template faces "
                "per node) updated per frame, the 50,000 particles sampled through it; 200 frames"),
     "track": (2, "temporal correspondence tracking (Eq. 1): the 20,002-vertex template carried through "
@@ -55,7 +58,7 @@ WORKLOADS = {
 }
 METRIC = "frames/s and closest-point queries/s, refit vs rebuild; achieved HBM GB/s"
 # (timed steps, warm-up steps) per workload: each default run times about a second of GPU work
-DEFAULT_STEPS = {"c1": (60, 10), "c2": (200, 10), "c3": (10, 2), "c4": (200, 10), "c5": (20, 3), "track": (199, 0), "sdf": (200, 10)}
+DEFAULT_STEPS = {"c1": (60, 10), "c2": (200, 10), "c3": (10, 2), "c4": (200, 10), "c5": (20, 3), "track": (199, 0), "sdf": (200, 10), "contact": (200, 10)}
 
 
 def _target_job(args):
@@ -179,6 +182,96 @@ def timed_region(run, steps, torch):
 
 def omp_threads():
     return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def run_contact(args):
+    """Spheres falling onto the deforming template: one step = one frame of the contact simulation."""
+    from synth import make_config
+    t0 = time.perf_counter()
+    sc = make_config(2)
+    T = sc.n_frames
+    frames_np = sc.frames(range(T))
+    setup_s = time.perf_counter() - t0
+
+    import torch
+    import paper_2606_00444_amd as mg
+    from paper_2606_00444_amd.contact import Spheres
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    mg.check_device()
+    D = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    frames, F, V0 = D(frames_np), D(sc.faces), D(sc.verts0)
+    NV, NF = sc.n_verts, sc.n_faces
+    P = 50_000
+    L = float(np.ptp(sc.verts0, axis=1).max())
+    lo, hi = sc.verts0.min(1), sc.verts0.max(1)
+    rng = np.random.default_rng(60644499)
+    x0 = np.stack([rng.uniform(lo[0], hi[0], P), rng.uniform(lo[1], hi[1], P),
+                   rng.uniform(hi[2], hi[2] + 0.5 * L, P)]).astype(np.float32)
+    dt, r, e = 1.0 / 240.0, 0.01 * L, 0.3
+    live = torch.empty(3, NV, device=dev)
+    bvh = mg.lbvh_build(V0, F)
+    S = Spheres(D(x0), torch.zeros(3, P, device=dev), r, restitution=e)
+
+    def step(i):
+        mg.vertex_buffer_update(frames, i % T, live)
+        mg.lbvh_refit(bvh, live)
+        S.step(bvh, live, dt)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    if args.eager:
+        run = lambda: [step(i) for i in range(args.steps)]
+    else:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for i in range(args.warmup, args.warmup + args.steps):
+                step(i)
+        run = g.replay
+    ms_per_step, wall = timed_region(run, args.steps, torch)
+    contacts = int(S.contact.sum().item())
+    # per-phase durations in the final state
+    xs = S.x.clone()
+    vs = S.v.clone()
+    rec = S.rec
+    ph = {"refit": graph_ms(lambda _: mg.lbvh_refit(bvh, live), 50, torch),
+          "closest": graph_ms(lambda _: mg.closest_point_query(bvh, live, xs, normal=True, out=rec), 20, torch)}
+    S.x.copy_(xs)
+    S.v.copy_(vs)
+    cnt = torch.zeros(4, dtype=torch.int64, device=dev)
+    mg.closest_point_query(bvh, live, xs, normal=True, out=rec, counters=cnt)
+    torch.cuda.synchronize()
+    n_exp, n_lbox, n_lex, n_q = (int(x) for x in cnt.cpu())
+    ops = 34.0 * n_exp + 29.0 * n_lbox + 80.0 * n_lex
+    achieved = ops / (ph["closest"] * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": round(1000.0 / ms_per_step, 2), "unit": "frames/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"contact: {WORKLOADS['contact'][1]}", "spheres": P, "radius": r, "dt": dt,
+                   "restitution": e, "faces": NF, "timing": "eager" if args.eager else "hip-graph"},
+        "contacts_last_step": contacts,
+        "kernels_ms": {k: round(v, 5) for k, v in ph.items()},
+        "queries_per_s": round(P * 1000.0 / ms_per_step, 1),
+        "roofline": {"bound": "alu", "kernel": "traverse_batch_kernel (sphere centres onto the template)",
+                     "achieved": round(achieved, 4), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5), "traffic": None,
+                     "alg_ops_per_launch": int(ops), "avg_launch_ms": round(ph["closest"], 5)},
+        "wall_s": round(wall, 4), "setup_s": round(setup_s, 2),
+    }
+    if not args.no_cpu_baseline:
+        from oracle import contact as oco
+        idx = rng.choice(P, 4000, replace=False)
+        tt = time.perf_counter()
+        oco.step(x0[:, idx].astype(np.float64), np.zeros((3, idx.size)), frames_np[0], sc.faces, dt,
+                 np.array([0.0, 0.0, -9.8]), r, e)
+        sec = (time.perf_counter() - tt) * P / idx.size
+        th = omp_threads()
+        out["cpu_baseline"] = {"value": 1.0 / sec, "unit": "frames/s", "cores": th, "kind": "oracle",
+                               "sample": f"one step of {idx.size} random spheres (brute-force plain-C closest "
+                                         f"points, OpenMP {th} threads), scaled to all {P}"}
+    print(json.dumps(out))
 
 
 def run_sdf(args):
@@ -674,6 +767,8 @@ def main():
         return run_track(args)
     if args.workload == "sdf":
         return run_sdf(args)
+    if args.workload == "contact":
+        return run_contact(args)
     cfg, desc = WORKLOADS[args.workload]
 
     from synth import make_config

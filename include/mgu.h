@@ -346,6 +346,29 @@ mg_status mg_sdf_sample(const float *sdf, float lo_x, float lo_y, float lo_z, fl
                         int32_t nz, const float *queries, int32_t n_queries, float *out, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Sphere-mesh contact step from on-demand face normals: collision response
+ * for spheres dropped on the mesh (the falling-sphere simulation of Sec. 4.1;
+ * face normals computed on demand, Sec. 3.4 step 3).  A step of spheres of
+ * radius r: mg_particles_integrate, then mg_closest_point_query at the new
+ * positions (point, face and normal outputs), then mg_contact_response.
+ * Positions x and velocities v are [3][n] float32 device arrays.
+ * ---------------------------------------------------------------------- */
+
+/* v <- v + g dt, then x <- x + v dt (semi-implicit Euler); dt >= 0. */
+mg_status mg_particles_integrate(float *x, float *v, int32_t n, float gx, float gy, float gz, float dt,
+                                 void *stream);
+
+/* With c = point, n = normal (unit, zero for a degenerate face), face (-1 for
+ * none) from mg_closest_point_query at x: side = (x - c) . n; a sphere is in
+ * contact when face >= 0, n != 0 and (side < 0 or |x - c| < radius).  Then
+ * nh = (x - c)/|x - c| if side >= 0 and |x - c| > 0, else n; x <- c + radius nh;
+ * if v . nh < 0, v <- v - (1 + restitution)(v . nh) nh.  restitution in
+ * [0, 1], radius >= 0; contact [n] (device int32, or NULL) <- 1 / 0. */
+mg_status mg_contact_response(float *x, float *v, int32_t n, const float *point, const float *normal,
+                              const int32_t *face, float radius, float restitution, int32_t *contact,
+                              void *stream);
+
+/* ------------------------------------------------------------------------
  * Losses for differentiable template projection.  Chamfer distance is used
  * by the paper as a metric (Sec. 4.2) without a formula; the library's is
  * CD(A,B) = mean_a min_b |a-b|^2 + mean_b min_a |a-b|^2.

@@ -73,6 +73,8 @@ PROTOTYPES = {
     "mg_closest_point_query": (I32, [P, SZ, I32, P, I32, P, I32, F32, P, P, P, P, P, P, P]),
     "mg_closest_point_bruteforce": (I32, [P, I32, P, I32, P, I32, F32, P, P, P, P, P, P]),
     "mg_nearest_point_query": (I32, [P, SZ, I32, P, P, I32, F32, P, P, P, P]),
+    "mg_particles_integrate": (I32, [P, P, I32, F32, F32, F32, F32, P]),
+    "mg_contact_response": (I32, [P, P, I32, P, P, P, F32, F32, P, P]),
     "mg_grid_points": (I32, [F32, F32, F32, F32, I32, I32, I32, P, P]),
     "mg_sdf_update": (I32, [P, I32, P, I32, P, I32, F32, F32, F32, F32, I32, I32, I32, P, P, P]),
     "mg_sdf_sample": (I32, [P, F32, F32, F32, F32, I32, I32, I32, P, I32, P, P]),
