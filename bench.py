@@ -901,7 +901,7 @@ def main():
             phases[args.phase](r)
         torch.cuda.synchronize()
         print(json.dumps({"phase": args.phase, "reps": args.reps, "workload": args.workload,
-                          "autotuned": {k: {"kernel": v["kernel"], "batch": v["batch"], "seed": v["seed"],
+                          "autotuned": {k: {"kernel": v["kernel"], "batch": v["batch"], "seed": v["seed"], "dynamic": v.get("dynamic", False),
                                             "order": v["order"]} for k, v in tune.items()}}))
         return
     for i in range(args.warmup):
@@ -1033,7 +1033,7 @@ def main():
         "queries_per_s": round(q_per_frame * fps, 1),
         "collide_queries_per_s": round(Q / (ph["collide"] * 1e-3), 1),
         "traversal": trav,
-        "autotuned": {k: {"kernel": v["kernel"], "batch": v["batch"], "seed": v["seed"], "order": v["order"],
+        "autotuned": {k: {"kernel": v["kernel"], "batch": v["batch"], "seed": v["seed"], "dynamic": v.get("dynamic", False), "order": v["order"],
                           "ms": round(v["ms"], 4)}
                       for k, v in tune.items()},
         "kernels": kernels,

@@ -168,12 +168,16 @@ mg_status mg_mesh_gaussian_update_backward(const float *verts, int32_t n_verts, 
  *                                leaves, children of top nodes) cut the tree
  *   top_box     float  [2][6][n] refit scratch: subtree-root boxes per top node slot
  *   top_scratch uint32 [11][n]   second-phase refit scratch when n_top is large
+ *   inv_prim    int32  [n]       original primitive id -> leaf (inverse of prim)
  * ---------------------------------------------------------------------- */
 
 typedef struct mg_lbvh_header {
     int32_t n_prims;
     int32_t prim_kind;
-    int32_t status;        /* device-side error word (0 = fine) */
+    int32_t status;        /* device-side error word, 0 = fine; bits: 4 inconsistent
+                              tree, 8 bad refit schedule, 16 a query found an id
+                              without a leaf or a bounded wait ran out (its
+                              results may be wrong) */
     int32_t reserved0;
     float root_lo[3];      /* root box (the only box not stored in a node record) */
     float pad0;
@@ -204,6 +208,7 @@ typedef struct mg_lbvh_layout {
     int64_t off_subtrees;
     int64_t off_top_box;
     int64_t off_top_scratch;
+    int64_t off_inv_prim;
 } mg_lbvh_layout;
 
 /* Host-only: section offsets and total size of a BVH over n_prims primitives
@@ -244,8 +249,12 @@ mg_status mg_lbvh_refit(const float *verts, int32_t n_verts, void *bvh, size_t b
  * section of a MG_PRIM_POINTS BVH built over the queries, i.e. Morton order -
  * and every result is still written at the query's own index.  counters
  * (device uint64 [4], or NULL): += node expansions, leaf bound tests, exact
- * leaf tests, queries.  Results do not depend on these choices except among
- * exact ties, which all pick the lowest original id. */
+ * leaf tests, queries.  queue (device uint32 [1], or NULL; BATCH only): the
+ * waves stay resident and take query batches one at a time from this counter,
+ * which the call zeroes on its stream before the traversal (no initial value
+ * needed); calls that may overlap in time must use different words.  Without a
+ * queue, batches are dealt to the waves statically.  Results do not depend on
+ * these choices except among exact ties, which all pick the lowest original id. */
 #define MG_QUERY_AUTO  0
 #define MG_QUERY_LANE  1
 #define MG_QUERY_BATCH 2
@@ -257,7 +266,8 @@ typedef struct mg_query_options {
     int32_t reserved0;
     const int32_t *order;
     uint64_t *counters;
-    int64_t reserved[2];
+    uint32_t *queue;
+    int64_t reserved;
 } mg_query_options;
 
 /* ------------------------------------------------------------------------

@@ -35,12 +35,12 @@ class LbvhLayout(ctypes.Structure):
     _fields_ = [(n, I64) for n in ("total_bytes", "off_header", "off_codes", "off_prim", "off_leaf_faces",
                                    "off_leaf_parent", "off_node_parent", "off_nodes", "off_node_aux",
                                    "off_top_nodes", "off_top_child", "off_subtrees",
-                                   "off_top_box", "off_top_scratch")]
+                                   "off_top_box", "off_top_scratch", "off_inv_prim")]
 
 
 class QueryOptions(ctypes.Structure):
     _fields_ = [("kernel", I32), ("batch", I32), ("seed", I32), ("reserved0", I32), ("order", P),
-                ("counters", P), ("reserved", I64 * 2)]
+                ("counters", P), ("queue", P), ("reserved", I64)]
 
 
 class BatchScene(ctypes.Structure):

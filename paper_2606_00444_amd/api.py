@@ -206,15 +206,23 @@ def lbvh_refit(bvh, verts):
     return bvh
 
 
-def _opts(kernel, batch, seed=False, order=None, counters=None):
-    """ctypes options for the traversal ("auto" | "lane" | "batch"); None when automatic."""
-    if kernel in (None, "auto") and not batch and not seed and order is None and counters is None:
+def _opts(kernel, batch, seed=False, order=None, counters=None, queue=None):
+    """ctypes options for the traversal ("auto" | "lane" | "batch"); None when automatic.
+
+    queue: a device int32 [1] work counter for the batch kernel's dynamic
+    batch assignment (zeroed by the call itself), or None for static."""
+    auto = kernel in (None, "auto") and not batch and not seed and order is None and counters is None
+    if auto and queue is None:
         return None
     k = {"auto": MG_QUERY_AUTO, None: MG_QUERY_AUTO, "lane": MG_QUERY_LANE, "batch": MG_QUERY_BATCH}[kernel]
     o = QueryOptions()
     o.kernel = k
     o.batch = int(batch or 0)
-    o.seed = int(bool(seed))
+    o.seed = 1 if auto else int(bool(seed))           # the automatic choice has the seed on
+    if queue is not None:
+        if queue.dtype != torch.int32 or queue.numel() < 1:
+            raise TypeError("queue must be int32 [1]")
+        o.queue = _ptr(queue)
     if order is not None:
         if order.dtype != torch.int32:
             raise TypeError("order must be int32")
@@ -232,6 +240,13 @@ def query_order(queries):
     return bvh.section("prim", torch.int32, bvh.n).clone()
 
 
+def _queue(dynamic, device):
+    """A work counter for one traversal call with dynamic batch assignment (its
+    own word, so calls on different streams never share one; the call zeroes
+    it on its stream), or None."""
+    return torch.empty(1, dtype=torch.int32, device=device) if dynamic else None
+
+
 def _query_out(nq, device, point, bary, dist2, normal):
     return {
         "face": torch.empty(nq, dtype=torch.int32, device=device),
@@ -243,19 +258,23 @@ def _query_out(nq, device, point, bary, dist2, normal):
 
 
 def closest_point_query(bvh, verts, queries, max_dist2=math.inf, *, point=True, bary=True, dist2=True,
-                        normal=False, out=None, kernel=None, batch=0, seed=False, order=None,
+                        normal=False, out=None, kernel=None, batch=0, seed=False, dynamic=False, order=None,
                         counters=None):
     """Closest point on the mesh of a triangle LBVH for every query [3][Q].
 
-    kernel: None/"auto", "lane" or "batch" (batch = queries per wave) - see mg_query_options.
+    kernel: None/"auto", "lane" or "batch" (batch = queries per wave), dynamic:
+    batches taken from a work counter instead of dealt statically - see
+    mg_query_options.  out: a dict of output tensors to fill (face, and point, bary, dist2, normal
+    or None each).
     """
     if bvh.kind != MG_PRIM_TRIANGLES:
         raise ValueError("closest_point_query needs a triangle BVH")
     nq = _f32(queries, 3, "queries").shape[1]
-    o = out or _query_out(nq, queries.device, point, bary, dist2, normal)
+    o = out if out is not None else _query_out(nq, queries.device, point, bary, dist2, normal)
     _call("mg_closest_point_query", _ptr(bvh.buf), bvh.nbytes, bvh.n, _ptr(verts), verts.shape[1],
-          _ptr(queries), nq, float(max_dist2), _ptr(o["face"]), _ptr(o["point"]), _ptr(o["bary"]),
-          _ptr(o["dist2"]), _ptr(o["normal"]), _opts(kernel, batch, seed, order, counters), _stream())
+          _ptr(queries), nq, float(max_dist2), _ptr(o["face"]), _ptr(o.get("point")), _ptr(o.get("bary")),
+          _ptr(o.get("dist2")), _ptr(o.get("normal")),
+          _opts(kernel, batch, seed, order, counters, _queue(dynamic, queries.device)), _stream())
     return o
 
 
@@ -286,7 +305,7 @@ def knn_surface_query(bvh, verts, queries, k=4, eps=0.0, max_dist2=math.inf, *, 
 
 
 def nearest_point_query(bvh, points, queries, max_dist2=math.inf, *, kernel=None, batch=0, seed=False,
-                        order=None, counters=None):
+                        dynamic=False, order=None, counters=None):
     """(index [Q] int32, dist2 [Q]) of the nearest point of a point LBVH."""
     if bvh.kind != MG_PRIM_POINTS:
         raise ValueError("nearest_point_query needs a point BVH")
@@ -294,7 +313,8 @@ def nearest_point_query(bvh, points, queries, max_dist2=math.inf, *, kernel=None
     idx = torch.empty(nq, dtype=torch.int32, device=queries.device)
     d2 = torch.empty(nq, device=queries.device)
     _call("mg_nearest_point_query", _ptr(bvh.buf), bvh.nbytes, bvh.n, _ptr(points), _ptr(queries), nq,
-          float(max_dist2), _ptr(idx), _ptr(d2), _opts(kernel, batch, seed, order, counters), _stream())
+          float(max_dist2), _ptr(idx), _ptr(d2),
+          _opts(kernel, batch, seed, order, counters, _queue(dynamic, queries.device)), _stream())
     return idx, d2
 
 

@@ -2,7 +2,8 @@
 
 For a given BVH and query set it times every candidate traversal (one query per
 lane, or one wave per batch of 1-16 queries with or without the greedy seed
-descent; in the given query order or a supplied one such as Morton order), each
+descent, with batches dealt statically or taken from a work counter; in the
+given query order or a supplied one such as Morton order), each
 as a HIP graph of back-to-back launches bracketed by HIP events
 on the launch stream, and keeps the fastest.  Choices are cached per device,
 primitive kind, primitive count, query count and ordering in a JSON file
@@ -17,7 +18,8 @@ import torch
 
 from . import api
 
-CANDIDATES = [("lane", 0, False)] + [("batch", b, s) for b in (1, 2, 4, 8, 16) for s in (False, True)]
+CANDIDATES = ([("lane", 0, False, False)] + [("batch", b, s, False) for b in (1, 2, 4, 8, 16) for s in (False, True)]
+              + [("batch", b, True, True) for b in (2, 4, 8, 16)])
 
 
 def _cache_path():
@@ -75,12 +77,13 @@ def _tune(key, run, orders, candidates, reps, use_cache):
         return cache[key]
     timings = {}
     for oname, order in orders.items():
-        for kernel, batch, seed in candidates or CANDIDATES:
-            timings[f"{kernel}/{batch}/{int(seed)}/{oname}"] = _graph_time(
-                lambda: run(kernel=kernel, batch=batch, seed=seed, order=order), reps)
+        for kernel, batch, seed, dyn in candidates or CANDIDATES:
+            timings[f"{kernel}/{batch}/{int(seed)}/{int(dyn)}/{oname}"] = _graph_time(
+                lambda: run(kernel=kernel, batch=batch, seed=seed, dynamic=dyn, order=order), reps)
     best = min(timings, key=timings.get)
-    k, b, s, o = best.split("/")
-    res = {"kernel": k, "batch": int(b), "seed": bool(int(s)), "order": o, "ms": timings[best], "timings": timings}
+    k, b, s, d, o = best.split("/")
+    res = {"kernel": k, "batch": int(b), "seed": bool(int(s)), "dynamic": bool(int(d)), "order": o,
+           "ms": timings[best], "timings": timings}
     if use_cache:
         cache = _load_cache()
         cache[key] = res
@@ -113,13 +116,13 @@ def tune_nearest(bvh, points, queries, *, order=None, reps=5, use_cache=True, ca
 
 def options(res, order=None):
     """Keyword arguments of a tuning result for the query calls (order: the candidate order tensor)."""
-    kw = {"kernel": res["kernel"], "batch": res["batch"], "seed": res["seed"]}
+    kw = {"kernel": res["kernel"], "batch": res["batch"], "seed": res["seed"], "dynamic": res.get("dynamic", False)}
     if res.get("order") == "order":
         kw["order"] = order
     return kw
 
 
-BATCH_CANDIDATES = [("batch", b, s) for b in (1, 2, 4, 8, 16) for s in (False, True)]
+BATCH_CANDIDATES = [("batch", b, s, False) for b in (1, 2, 4, 8, 16) for s in (False, True)]
 BATCH_TILES = [(g, q) for g in (1024, 2048, 4096) for q in (128, 256, 512, 1024)]
 
 

@@ -31,7 +31,7 @@ constexpr int kSpin = 1 << 22;
 
 struct PlanScene {
     mg_batch_scene s;
-    const int32_t *leaf_faces, *prim, *leaf_parent, *node_parent, *node_aux, *top_nodes;
+    const int32_t *leaf_faces, *prim, *inv_prim, *leaf_parent, *node_parent, *node_aux, *top_nodes;
     const int32_t *top_child, *subtrees;
     const int32_t *n_top, *n_sub;           // the scene BVH's counts (device)
     float *top_box;                         // [n_frames][2][6][n_top] deposited subtree-root boxes
@@ -167,6 +167,8 @@ __device__ QueryArgs query_args(const PlanScene &P, int64_t t, const RefitArgs &
     a.root = r.root;
     a.leaf_faces = P.leaf_faces;
     a.prim = P.prim;
+    a.inv_prim = P.inv_prim;
+    a.status = r.status;
     a.verts = r.verts;
     a.nv = s.n_verts;
     a.n = s.n_faces;
@@ -181,19 +183,20 @@ __device__ QueryArgs query_args(const PlanScene &P, int64_t t, const RefitArgs &
     a.seed = seed;
     a.order = nullptr;
     a.counters = nullptr;
+    a.queue = nullptr;
     return a;
 }
 
+static_assert(kBlock == 64 * kBatchWaves, "a query tile is run by the workgroup's kBatchWaves waves");
+
 template <int M>
 __device__ void query_tile(const QueryArgs &q, int64_t q0, int64_t q1, unsigned char *smem) {
-    WaveStack<M> *stacks = reinterpret_cast<WaveStack<M> *>(smem);
-    const int w = threadIdx.x / 64;
-    batch_loop<true, M>(q, q0 + static_cast<int64_t>(w) * M, static_cast<int64_t>(kBlock / 64) * M, q1, stacks[w]);
+    batch_loop<true, M>(q, q0, static_cast<int64_t>(kBatchWaves) * M, q1, *reinterpret_cast<BatchLds<M> *>(smem));
 }
 
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 constexpr size_t kSmemBytes = cmax(cmax(refit_top_lds(kBatchTopLds), refit_sub_lds(int64_t(1) << kBatchMaxChunkLog2)),
-                                   4 * sizeof(WaveStack<16>));
+                                   sizeof(BatchLds<16>));
 
 __global__ __launch_bounds__(kBlock) void batch_persistent_kernel(PlanHeader *h) {
     __shared__ __align__(16) unsigned char smem[kSmemBytes];
@@ -341,6 +344,7 @@ extern "C" mg_status mg_batch_plan_init(const mg_batch_scene *scenes, int32_t n_
         const char *b = static_cast<const char *>(s.bvh);
         P.leaf_faces = reinterpret_cast<const int32_t *>(b + L.off_leaf_faces);
         P.prim = reinterpret_cast<const int32_t *>(b + L.off_prim);
+        P.inv_prim = reinterpret_cast<const int32_t *>(b + L.off_inv_prim);
         P.leaf_parent = reinterpret_cast<const int32_t *>(b + L.off_leaf_parent);
         P.node_parent = reinterpret_cast<const int32_t *>(b + L.off_node_parent);
         P.node_aux = reinterpret_cast<const int32_t *>(b + L.off_node_aux);

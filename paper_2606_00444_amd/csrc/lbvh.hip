@@ -56,6 +56,7 @@ inline mg_lbvh_layout make_layout(int64_t n, int kind) {
     L.off_subtrees = o;    o += align256(12 * n);
     L.off_top_box = o;     o += align256(48 * n);
     L.off_top_scratch = o; o += align256(44 * n);
+    L.off_inv_prim = o;    o += align256(4 * n);
     L.total_bytes = o;
     return L;
 }
@@ -376,7 +377,8 @@ __device__ __forceinline__ int kdelta(const uint32_t *__restrict__ codes, int64_
 // Internal node i (i < n - 1) and leaf i (i < n): Karras's range and split
 // search; children's parent tags; leaf face permutation; counter reset.
 __global__ __launch_bounds__(256) void hierarchy_kernel(const uint32_t *__restrict__ codes,
-                                                        const int32_t *__restrict__ prim, int64_t n,
+                                                        const int32_t *__restrict__ prim,
+                                                        int32_t *__restrict__ inv_prim, int64_t n,
                                                         const int32_t *__restrict__ faces,
                                                         int32_t *__restrict__ leaf_faces,
                                                         int32_t *__restrict__ leaf_parent,
@@ -388,6 +390,11 @@ __global__ __launch_bounds__(256) void hierarchy_kernel(const uint32_t *__restri
                                                         mg_lbvh_header *hdr, int chunk_log2) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    {
+        const int32_t p = prim[i];
+        if (p >= 0 && p < n) inv_prim[p] = static_cast<int32_t>(i);
+        else atomicOr(&hdr->status, 4);
+    }
     if (faces) {
         const int32_t p = prim[i];
         leaf_faces[i] = faces[p];
@@ -607,7 +614,8 @@ extern "C" mg_status mg_lbvh_build(const float *verts, int32_t n_verts, const in
                            lookback + static_cast<int64_t>(p) * 256 * W.tiles, &hdr->tile_counter[p],
                            &hdr->status);
     }
-    hipLaunchKernelGGL(hierarchy_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, codes, prim, n, fz,
+    hipLaunchKernelGGL(hierarchy_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, codes, prim,
+                       at<int32_t>(bvh, L.off_inv_prim), n, fz,
                        fz ? at<int32_t>(bvh, L.off_leaf_faces) : nullptr, at<int32_t>(bvh, L.off_leaf_parent),
                        at<int32_t>(bvh, L.off_node_parent), at<int32_t>(bvh, L.off_node_aux),
                        at<int32_t>(bvh, L.off_top_nodes), at<int32_t>(bvh, L.off_subtrees),

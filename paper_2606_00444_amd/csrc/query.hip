@@ -102,11 +102,10 @@ __global__ __launch_bounds__(kLaneBlock) void traverse_lane_kernel(QueryArgs a) 
 
 template <bool kTri, int M>
 __global__ __launch_bounds__(64 * kBatchWaves) void traverse_batch_kernel(QueryArgs a) {
-    __shared__ WaveStack<M> stacks[kBatchWaves];
-    const int w = threadIdx.x / 64;
-    const int64_t waves_total = static_cast<int64_t>(gridDim.x) * kBatchWaves;
-    batch_loop<kTri, M>(a, (static_cast<int64_t>(blockIdx.x) * kBatchWaves + w) * M, waves_total * M, a.nq,
-                        stacks[w]);
+    __shared__ BatchLds<M> lds;
+    const int64_t per_block = static_cast<int64_t>(kBatchWaves) * M;
+    batch_loop<kTri, M>(a, static_cast<int64_t>(blockIdx.x) * per_block, static_cast<int64_t>(gridDim.x) * per_block,
+                        a.nq, lds);
 }
 
 // ----------------------------------------------------------------- k nearest
@@ -292,29 +291,50 @@ inline void resolve(const mg_query_options *o, int64_t nq, int &kernel, int &bat
     if (batch <= 0) batch = 4;
 }
 
+__global__ void zero_word_kernel(uint32_t *w) { *w = 0u; }
+
+// Without a queue: one workgroup per kBatchWaves batches (at most 4096
+// workgroups, striding beyond).  With a queue: as many workgroups as can be
+// resident at once, each wave taking batches until none is left.
+template <bool kTri, int M>
+mg_status launch_batch(const QueryArgs &a, hipStream_t s) {
+    const int64_t per_block = static_cast<int64_t>(M) * kBatchWaves;
+    int64_t grid = std::min<int64_t>((a.nq + per_block - 1) / per_block, 256 * 16);
+    if (a.queue) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, traverse_batch_kernel<kTri, M>, 64 * kBatchWaves,
+                                                         0) != hipSuccess)
+            return MG_ERR_HIP;
+        grid = std::max<int64_t>(1, std::min<int64_t>(grid, static_cast<int64_t>(cus) * std::max(per_cu, 1)));
+        hipLaunchKernelGGL(zero_word_kernel, dim3(1), dim3(1), 0, s, a.queue);
+    }
+    hipLaunchKernelGGL((traverse_batch_kernel<kTri, M>), dim3(static_cast<unsigned>(grid)), dim3(64 * kBatchWaves), 0,
+                       s, a);
+    return launch_status();
+}
+
 template <bool kTri>
 mg_status launch_traverse(QueryArgs a, const mg_query_options *opts, hipStream_t s) {
     int kernel, batch;
     resolve(opts, a.nq, kernel, batch, a.seed);
     a.order = opts ? opts->order : nullptr;
     a.counters = opts ? reinterpret_cast<unsigned long long *>(opts->counters) : nullptr;
+    a.queue = opts ? opts->queue : nullptr;
     if (kernel == MG_QUERY_LANE) {
         hipLaunchKernelGGL(traverse_lane_kernel<kTri>, dim3(blocks_for(a.nq, kLaneBlock)), dim3(kLaneBlock), 0, s, a);
         return launch_status();
     }
-    const int64_t per_block = static_cast<int64_t>(batch) * kBatchWaves;
-    const int grid = static_cast<int>(std::min<int64_t>((a.nq + per_block - 1) / per_block, 256 * 16));
-    const dim3 g(grid), b(64 * kBatchWaves);
     switch (batch) {
-        case 1: hipLaunchKernelGGL((traverse_batch_kernel<kTri, 1>), g, b, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((traverse_batch_kernel<kTri, 2>), g, b, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((traverse_batch_kernel<kTri, 4>), g, b, 0, s, a); break;
-        case 8: hipLaunchKernelGGL((traverse_batch_kernel<kTri, 8>), g, b, 0, s, a); break;
-        case 16: hipLaunchKernelGGL((traverse_batch_kernel<kTri, 16>), g, b, 0, s, a); break;
-        case 32: hipLaunchKernelGGL((traverse_batch_kernel<kTri, 32>), g, b, 0, s, a); break;
+        case 1: return launch_batch<kTri, 1>(a, s);
+        case 2: return launch_batch<kTri, 2>(a, s);
+        case 4: return launch_batch<kTri, 4>(a, s);
+        case 8: return launch_batch<kTri, 8>(a, s);
+        case 16: return launch_batch<kTri, 16>(a, s);
+        case 32: return launch_batch<kTri, 32>(a, s);
         default: return MG_ERR_INVALID_ARGUMENT;
     }
-    return launch_status();
 }
 
 inline bool bad_options(const mg_query_options *o) {
@@ -342,11 +362,13 @@ extern "C" mg_status mg_closest_point_query(const void *bvh, size_t bvh_bytes, i
     if (bvh_bytes < static_cast<size_t>(L.total_bytes)) return MG_ERR_WORKSPACE_TOO_SMALL;
     if (n_queries == 0) return MG_OK;
     if (!queries || !face || (n_prims > 0 && (!verts || n_verts == 0))) return MG_ERR_INVALID_ARGUMENT;
-    QueryArgs a;
+    QueryArgs a{};
     a.nodes = cat<float4>(bvh, L.off_nodes);
     a.root = cat<mg_lbvh_header>(bvh, L.off_header)->root_lo;
     a.leaf_faces = cat<int32_t>(bvh, L.off_leaf_faces);
     a.prim = cat<int32_t>(bvh, L.off_prim);
+    a.inv_prim = cat<int32_t>(bvh, L.off_inv_prim);
+    a.status = &const_cast<mg_lbvh_header *>(cat<mg_lbvh_header>(bvh, L.off_header))->status;
     a.verts = verts; a.nv = n_verts; a.n = n_prims;
     a.queries = queries; a.nq = n_queries; a.maxd2 = max_dist2;
     a.face = face; a.point = point; a.bary = bary; a.dist2 = dist2; a.normal = normal;
@@ -364,11 +386,13 @@ extern "C" mg_status mg_nearest_point_query(const void *bvh, size_t bvh_bytes, i
     if (bvh_bytes < static_cast<size_t>(L.total_bytes)) return MG_ERR_WORKSPACE_TOO_SMALL;
     if (n_queries == 0) return MG_OK;
     if (!queries || !index || (n_prims > 0 && !points)) return MG_ERR_INVALID_ARGUMENT;
-    QueryArgs a;
+    QueryArgs a{};
     a.nodes = cat<float4>(bvh, L.off_nodes);
     a.root = cat<mg_lbvh_header>(bvh, L.off_header)->root_lo;
     a.leaf_faces = nullptr;
     a.prim = cat<int32_t>(bvh, L.off_prim);
+    a.inv_prim = cat<int32_t>(bvh, L.off_inv_prim);
+    a.status = &const_cast<mg_lbvh_header *>(cat<mg_lbvh_header>(bvh, L.off_header))->status;
     a.verts = points; a.nv = n_prims; a.n = n_prims;
     a.queries = queries; a.nq = n_queries; a.maxd2 = max_dist2;
     a.face = index; a.point = nullptr; a.bary = nullptr; a.dist2 = dist2; a.normal = nullptr;
@@ -407,6 +431,8 @@ extern "C" mg_status mg_knn_surface_query(const void *bvh, size_t bvh_bytes, int
     a.root = cat<mg_lbvh_header>(bvh, L.off_header)->root_lo;
     a.leaf_faces = cat<int32_t>(bvh, L.off_leaf_faces);
     a.prim = cat<int32_t>(bvh, L.off_prim);
+    a.inv_prim = cat<int32_t>(bvh, L.off_inv_prim);
+    a.status = &const_cast<mg_lbvh_header *>(cat<mg_lbvh_header>(bvh, L.off_header))->status;
     a.verts = verts; a.nv = n_verts; a.n = n_prims;
     a.queries = queries; a.nq = n_queries; a.maxd2 = max_dist2;
     a.point = point;

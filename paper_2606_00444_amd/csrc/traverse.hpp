@@ -19,7 +19,7 @@ constexpr int kLdsStack = 32;
 constexpr int kMaxStack = 64;
 constexpr float kPruneSlack = 1.0f + 1.0f / 1048576.0f;
 
-constexpr int kBatchWaves = 2;          // waves per workgroup of the batch kernel
+constexpr int kBatchWaves = 4;          // waves per workgroup of the batch kernel
 constexpr int kBatchCap = 512;          // stack entries before the pop width shrinks
 constexpr int kBatchAlloc = kBatchCap + 64;
 
@@ -38,6 +38,9 @@ struct QueryArgs {
     int seed;                           // batch kernel: greedy descent first
     const int32_t *order;               // processing order (permutation) or nullptr
     unsigned long long *counters;       // [4] statistics or nullptr
+    const int32_t *inv_prim;            // [n] leaf of each original id (id -> position in leaf order)
+    int32_t *status;                    // error word of the BVH header
+    uint32_t *queue;                    // batch kernel: dynamic batch counter (zeroed before launch) or nullptr
 };
 
 // Query processed in position i (order[i], or i); -1 if the order entry is out of range.
@@ -116,6 +119,17 @@ __device__ void write_result(const QueryArgs &a, int64_t q, f3 p, int32_t leaf, 
     }
 }
 
+// Final record of query q from the winning original id (-1 / INT_MAX: none).
+template <bool kTri>
+__device__ void write_result_id(const QueryArgs &a, int64_t q, f3 p, int32_t id, float d2) {
+    int32_t leaf = -1;
+    if (id >= 0 && id < a.n) {
+        leaf = a.inv_prim[id];
+        if (leaf < 0 || leaf >= a.n) { atomicOr(a.status, 16); leaf = -1; }
+    }
+    write_result<kTri>(a, q, p, leaf, id, d2);
+}
+
 // Test of the single leaf of a one-primitive BVH (no records exist).
 template <bool kTri>
 __device__ __forceinline__ float single_leaf_dist2(const QueryArgs &a, f3 p) {
@@ -129,27 +143,249 @@ __device__ __forceinline__ float single_leaf_dist2(const QueryArgs &a, f3 p) {
 }
 
 // --------------------------------------------------------------- batch kernel
-// Per-wave LDS of the batch traversal.
+// The waves of a workgroup each process batches of M queries with an LDS work
+// stack shared by the batch's queries; each round pops up to 64 entries (one
+// per lane).  A wave whose stack is deep hands its top 64 entries to an idle
+// wave of the same workgroup through a one-chunk mailbox, so a batch holding
+// an expensive query (one nearly equidistant from many faces) is finished by
+// several waves.  The per-query bests (d^2 bits, original id) stay with the
+// owning wave and are lowered by LDS atomics from whichever wave tests a face;
+// the owner writes its results once every chunk it gave away is done.
+
+constexpr int kDonateMin = 128;          // a wave keeps at least 64 entries after giving 64
+constexpr int kIdleSpinLimit = 1 << 22;  // bounded waits: error word instead of a hang
+
 template <int M>
 struct WaveStack {
     int32_t node[kBatchAlloc];
     float dist[kBatchAlloc];
     uint8_t slot[kBatchAlloc];
-    unsigned long long best[M];
-    int32_t leaf[M];
+    unsigned long long best[M];         // per query of the batch: (d^2 bits, original id)
     float q[3][M];
 };
 
-// One wave processes the query batches [qb, qb + M) for qb = start, start +
-// stride, ... below q_end (positions in the processing order).
+struct WaveMail {
+    int32_t node[64];
+    float dist[64];
+    uint8_t slot[64];
+    int32_t count;                      // entries in the chunk
+    int32_t owner;                      // wave whose batch the entries belong to
+    int32_t state;                      // 0 empty, 1 full, 2 being taken, 3 being filled
+    int32_t idle;                       // waves waiting for work
+    int32_t done;                       // waves that have finished all their batches
+    int32_t outstanding[kBatchWaves];   // chunks of each wave's batch held elsewhere
+};
+
+template <int M>
+struct BatchLds {
+    WaveStack<M> st[kBatchWaves];
+    WaveMail mail;
+};
+
+struct BatchStats {
+    unsigned long long exp = 0, lbox = 0, lex = 0, nq = 0;
+};
+
+__device__ __forceinline__ int lds_load(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_store(int32_t *p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ int lds_add(int32_t *p, int v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ bool lds_cas(int32_t *p, int expect, int v) {
+    return __hip_atomic_compare_exchange_strong(p, &expect, v, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                                __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Rounds over wave `self`'s stack (sp entries) until it is empty.  Entries
+// belong to the batch of wave `owner`: its query positions and bests.
 template <bool kTri, int M>
-__device__ void batch_loop(const QueryArgs &a, int64_t start, int64_t stride, int64_t q_end, WaveStack<M> &S) {
+__device__ void run_stack(const QueryArgs &a, BatchLds<M> &L, int self, int owner, int sp, BatchStats &stats) {
     const int lane = threadIdx.x % 64;
     const uint64_t lt = lanemask_lt();
-    const unsigned long long none = pack_best(a.maxd2, INT_MAX);
-    unsigned long long n_exp = 0, n_lbox = 0, n_lex = 0, n_q = 0;   // statistics (wave-uniform)
+    WaveStack<M> &S = L.st[self];
+    WaveStack<M> &O = L.st[owner];
+    WaveMail &mail = L.mail;
+    // the stack never exceeds kBatchCap + 62: a round of width k pushes at most
+    // 2k entries, widths are cut to (kBatchCap - sp) / 2, and width-1 rounds are
+    // a plain depth-first walk whose growth is bounded by the tree depth; each
+    // query expands each internal node at most once, so the round cap only stops
+    // a corrupted buffer from looping
+    for (int64_t round = 0; sp > 0 && round < static_cast<int64_t>(M + 1) * a.n + 64; ++round) {
+        if (sp >= kDonateMin) {
+            int give = 0;
+            if (lane == 0 && lds_load(&mail.idle) > 0 && lds_cas(&mail.state, 0, 3)) give = 1;
+            if (__shfl(give, 0)) {
+                const int i = sp - 64 + lane;
+                mail.node[lane] = S.node[i];
+                mail.dist[lane] = S.dist[i];
+                mail.slot[lane] = S.slot[i];
+                sp -= 64;
+                if (lane == 0) {
+                    mail.owner = owner;
+                    mail.count = 64;
+                    lds_add(&mail.outstanding[owner], 1);
+                    lds_store(&mail.state, 1);
+                }
+            }
+        }
+        int take = sp < 64 ? sp : 64;
+        const int room = (kBatchCap - sp) / 2;
+        if (take > room) take = room > 1 ? room : 1;
+        const bool pop = lane < take;
+        const int idx = sp - 1 - lane;
+        int32_t node = 0, slot = 0;
+        float nd = INFINITY;
+        if (pop) {
+            node = S.node[idx];
+            nd = S.dist[idx];
+            slot = S.slot[idx];
+            if (slot >= M) { node = -1; slot = 0; }
+        }
+        sp -= take;
+        bool act = pop && node >= 0 && node < a.n - 1;
+        unsigned long long best = act ? O.best[slot] : 0ull;
+        act = act && nd <= __uint_as_float(static_cast<uint32_t>(best >> 32)) * kPruneSlack;
+        float4 l0, l1, l2, r0, r1, r2;
+        int32_t lref = 0, rref = 0;
+        f3 qp = f3{0.0f, 0.0f, 0.0f};
+        unsigned long long cand = ~0ull;
+        if (act) {
+            qp = f3{O.q[0][slot], O.q[1][slot], O.q[2][slot]};
+            const float4 *rec = a.nodes + 6 * static_cast<int64_t>(node);
+            l0 = rec[0]; l1 = rec[1]; l2 = rec[2]; r0 = rec[3]; r1 = rec[4]; r2 = rec[5];
+            lref = __float_as_int(l0.w);
+            rref = __float_as_int(r0.w);
+            if (lref >= a.n - 1 || rref >= a.n - 1 || ~lref >= a.n || ~rref >= a.n) act = false;
+        }
+        const float pbound = __uint_as_float(static_cast<uint32_t>(best >> 32)) * kPruneSlack;
+        const bool tl = act && lref < 0 && leaf_box_dist2<kTri>(qp, l0, l1, l2) <= pbound;
+        const bool tr = act && rref < 0 && leaf_box_dist2<kTri>(qp, r0, r1, r2) <= pbound;
+        if (a.counters) {
+            stats.exp += __popcll(__ballot(act));
+            stats.lbox += __popcll(__ballot(act && lref < 0)) + __popcll(__ballot(act && rref < 0));
+            stats.lex += __popcll(__ballot(tl)) + __popcll(__ballot(tr));
+        }
+        if (tl) cand = pack_best(leaf_dist2<kTri>(qp, l0, l1, l2), __float_as_int(l1.w));
+        if (tr) {
+            const unsigned long long c = pack_best(leaf_dist2<kTri>(qp, r0, r1, r2), __float_as_int(r1.w));
+            if (c < cand) cand = c;
+        }
+        if (cand != ~0ull) atomicMin(&O.best[slot], cand);
+        best = act ? O.best[slot] : 0ull;
+        const float bound = __uint_as_float(static_cast<uint32_t>(best >> 32)) * kPruneSlack;
+        const float dl = (act && lref >= 0) ? box_dist2(qp, xyz(l0), xyz(l1)) : INFINITY;
+        const float dr = (act && rref >= 0) ? box_dist2(qp, xyz(r0), xyz(r1)) : INFINITY;
+        const bool pl = act && lref >= 0 && dl <= bound;
+        const bool pr = act && rref >= 0 && dr <= bound;
+        const uint64_t bl = __ballot(pl), br = __ballot(pr);
+        const int off = sp + __popcll(bl & lt) + __popcll(br & lt);
+        // The bound above only holds for a valid tree; the clamp keeps a
+        // corrupted buffer from writing past this wave's stack.
+        if (pl && pr) {
+            const bool left_near = dl <= dr;   // nearer child on top of the stack
+            if (off < kBatchAlloc) {
+                S.node[off] = left_near ? rref : lref;
+                S.dist[off] = left_near ? dr : dl;
+                S.slot[off] = static_cast<uint8_t>(slot);
+            }
+            if (off + 1 < kBatchAlloc) {
+                S.node[off + 1] = left_near ? lref : rref;
+                S.dist[off + 1] = left_near ? dl : dr;
+                S.slot[off + 1] = static_cast<uint8_t>(slot);
+            }
+        } else if ((pl || pr) && off < kBatchAlloc) {
+            S.node[off] = pl ? lref : rref;
+            S.dist[off] = pl ? dl : dr;
+            S.slot[off] = static_cast<uint8_t>(slot);
+        }
+        sp += __popcll(bl) + __popcll(br);
+        sp = sp < kBatchAlloc ? sp : kBatchAlloc;
+    }
+}
 
-    for (int64_t qb = start; qb < q_end; qb += stride) {
+// Takes the mailbox's chunk, if there is one, and runs it to the end.
+template <bool kTri, int M>
+__device__ bool help_once(const QueryArgs &a, BatchLds<M> &L, int self, BatchStats &stats) {
+    const int lane = threadIdx.x % 64;
+    WaveMail &mail = L.mail;
+    int got = 0;
+    if (lane == 0 && lds_load(&mail.state) == 1 && lds_cas(&mail.state, 1, 2)) got = 1;
+    if (!__shfl(got, 0)) return false;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const int owner = mail.owner, n = mail.count;
+    if (owner < 0 || owner >= kBatchWaves || n < 0 || n > 64) {
+        if (lane == 0) { atomicOr(a.status, 16); lds_store(&mail.state, 0); }
+        return true;
+    }
+    WaveStack<M> &S = L.st[self];
+    if (lane < n) {
+        S.node[lane] = mail.node[lane];
+        S.dist[lane] = mail.dist[lane];
+        S.slot[lane] = mail.slot[lane];
+    }
+    if (lane == 0) {
+        lds_add(&mail.idle, -1);
+        lds_store(&mail.state, 0);
+    }
+    run_stack<kTri, M>(a, L, self, owner, n, stats);
+    if (lane == 0) {
+        lds_add(&mail.outstanding[owner], -1);
+        lds_add(&mail.idle, 1);
+    }
+    return true;
+}
+
+// Helps other waves until cond() holds (cond is evaluated by every lane on
+// LDS words, so it is wave-uniform).
+template <bool kTri, int M, typename Cond>
+__device__ void wait_helping(const QueryArgs &a, BatchLds<M> &L, int self, BatchStats &stats, Cond cond) {
+    const int lane = threadIdx.x % 64;
+    if (lane == 0) lds_add(&L.mail.idle, 1);
+    for (int spin = 0; !cond();) {
+        if (help_once<kTri, M>(a, L, self, stats)) {
+            spin = 0;
+        } else if (++spin > kIdleSpinLimit) {
+            if (lane == 0) atomicOr(a.status, 16);
+            break;
+        } else {
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    if (lane == 0) lds_add(&L.mail.idle, -1);
+}
+
+// The workgroup's kBatchWaves waves process the query batches [qb, qb + M)
+// below q_end (positions in the processing order): wave w takes qb = start +
+// w M, then steps by stride or, with a queue, M times the batch numbers it
+// takes from the queue.  Every wave of the workgroup calls this.
+template <bool kTri, int M>
+__device__ void batch_loop(const QueryArgs &a, int64_t start, int64_t stride, int64_t q_end, BatchLds<M> &L) {
+    const int lane = threadIdx.x % 64;
+    const int self = threadIdx.x / 64;
+    const uint64_t lt = lanemask_lt();
+    const unsigned long long none = pack_best(a.maxd2, INT_MAX);
+    WaveStack<M> &S = L.st[self];
+    WaveMail &mail = L.mail;
+    BatchStats stats;
+    if (threadIdx.x == 0) {
+        mail.state = 0;
+        mail.idle = 0;
+        mail.done = 0;
+        for (int w = 0; w < kBatchWaves; ++w) mail.outstanding[w] = 0;
+    }
+    __syncthreads();
+
+    auto next = [&](int64_t qb) -> int64_t {
+        if (!a.queue) return qb + stride;
+        uint32_t b = 0;
+        if (lane == 0) b = atomicAdd(a.queue, 1u);
+        return static_cast<int64_t>(__shfl(b, 0)) * M;
+    };
+    for (int64_t qb = a.queue ? next(0) : start + static_cast<int64_t>(self) * M; qb < q_end; qb = next(qb)) {
         const int nb = static_cast<int>(q_end - qb < M ? q_end - qb : M);
         const int64_t qid = lane < nb ? query_at(a, qb + lane) : -1;
         const bool own = qid >= 0;
@@ -158,20 +394,19 @@ __device__ void batch_loop(const QueryArgs &a, int64_t start, int64_t stride, in
             p = load3(a.queries, a.nq, qid);
             S.q[0][lane] = p.x; S.q[1][lane] = p.y; S.q[2][lane] = p.z;
             S.best[lane] = none;
-            S.leaf[lane] = -1;
         }
         int sp = 0;
         if (a.n == 1) {
             if (own) {
                 const unsigned long long c = pack_best(single_leaf_dist2<kTri>(a, p), a.prim[0]);
-                if (c < none) { S.best[lane] = c; S.leaf[lane] = 0; }
+                if (c < none) S.best[lane] = c;
             }
         } else if (a.n > 1) {
             unsigned long long seeded = none;
             if (a.seed && own) {
                 // one greedy root-to-leaf walk (nearer internal child first) gives an
                 // upper bound before the wide expansion starts
-                int32_t cleaf = -1, node = 0;
+                int32_t node = 0;
                 for (int lvl = 0; lvl < 64 && node >= 0 && node < a.n - 1; ++lvl) {
                     const float4 *rec = a.nodes + 6 * static_cast<int64_t>(node);
                     const float4 l0 = rec[0], l1 = rec[1], l2 = rec[2], r0 = rec[3], r1 = rec[4], r2 = rec[5];
@@ -183,17 +418,17 @@ __device__ void batch_loop(const QueryArgs &a, int64_t start, int64_t stride, in
                     }
                     if (lref < 0) {
                         const unsigned long long c = pack_best(leaf_dist2<kTri>(p, l0, l1, l2), __float_as_int(l1.w));
-                        if (c < seeded) { seeded = c; cleaf = ~lref; }
+                        if (c < seeded) seeded = c;
                     }
                     if (rref < 0) {
                         const unsigned long long c = pack_best(leaf_dist2<kTri>(p, r0, r1, r2), __float_as_int(r1.w));
-                        if (c < seeded) { seeded = c; cleaf = ~rref; }
+                        if (c < seeded) seeded = c;
                     }
                     const float dl = lref >= 0 ? box_dist2(p, xyz(l0), xyz(l1)) : INFINITY;
                     const float dr = rref >= 0 ? box_dist2(p, xyz(r0), xyz(r1)) : INFINITY;
                     node = (lref >= 0 && dl <= dr) ? lref : (rref >= 0 ? rref : -1);
                 }
-                if (seeded < none) { S.best[lane] = seeded; S.leaf[lane] = cleaf; }
+                if (seeded < none) S.best[lane] = seeded;
             }
             const f3 rlo = f3{a.root[0], a.root[1], a.root[2]};
             const f3 rhi = f3{a.root[4], a.root[5], a.root[6]};
@@ -209,101 +444,19 @@ __device__ void batch_loop(const QueryArgs &a, int64_t start, int64_t stride, in
             }
             sp = __popcll(bm);
         }
-        // the stack never exceeds kBatchCap + 62: a round of width k pushes at most
-        // 2k entries, widths are cut to (kBatchCap - sp) / 2, and width-1 rounds are
-        // a plain depth-first walk whose growth is bounded by the tree depth
-        // each query expands each internal node at most once: the round cap only
-        // stops a corrupted buffer from looping
-        for (int64_t round = 0; sp > 0 && round < static_cast<int64_t>(M + 1) * a.n + 64; ++round) {
-            int take = sp < 64 ? sp : 64;
-            const int room = (kBatchCap - sp) / 2;
-            if (take > room) take = room > 1 ? room : 1;
-            const bool pop = lane < take;
-            const int idx = sp - 1 - lane;
-            int32_t node = 0, slot = 0;
-            float nd = INFINITY;
-            if (pop) {
-                node = S.node[idx];
-                nd = S.dist[idx];
-                slot = S.slot[idx];
-                if (slot >= M) { node = -1; slot = 0; }
-            }
-            sp -= take;
-            bool act = pop && node >= 0 && node < a.n - 1;
-            unsigned long long best = act ? S.best[slot] : 0ull;
-            act = act && nd <= __uint_as_float(static_cast<uint32_t>(best >> 32)) * kPruneSlack;
-            float4 l0, l1, l2, r0, r1, r2;
-            int32_t lref = 0, rref = 0;
-            f3 qp = f3{0.0f, 0.0f, 0.0f};
-            unsigned long long cand = ~0ull;
-            int32_t cand_leaf = -1;
-            if (act) {
-                qp = f3{S.q[0][slot], S.q[1][slot], S.q[2][slot]};
-                const float4 *rec = a.nodes + 6 * static_cast<int64_t>(node);
-                l0 = rec[0]; l1 = rec[1]; l2 = rec[2]; r0 = rec[3]; r1 = rec[4]; r2 = rec[5];
-                lref = __float_as_int(l0.w);
-                rref = __float_as_int(r0.w);
-                if (lref >= a.n - 1 || rref >= a.n - 1 || ~lref >= a.n || ~rref >= a.n) act = false;
-            }
-            const float pbound = __uint_as_float(static_cast<uint32_t>(best >> 32)) * kPruneSlack;
-            const bool tl = act && lref < 0 && leaf_box_dist2<kTri>(qp, l0, l1, l2) <= pbound;
-            const bool tr = act && rref < 0 && leaf_box_dist2<kTri>(qp, r0, r1, r2) <= pbound;
-            if (a.counters) {
-                n_exp += __popcll(__ballot(act));
-                n_lbox += __popcll(__ballot(act && lref < 0)) + __popcll(__ballot(act && rref < 0));
-                n_lex += __popcll(__ballot(tl)) + __popcll(__ballot(tr));
-            }
-            if (tl) {
-                cand = pack_best(leaf_dist2<kTri>(qp, l0, l1, l2), __float_as_int(l1.w));
-                cand_leaf = ~lref;
-            }
-            if (tr) {
-                const unsigned long long c = pack_best(leaf_dist2<kTri>(qp, r0, r1, r2), __float_as_int(r1.w));
-                if (c < cand) { cand = c; cand_leaf = ~rref; }
-            }
-            if (cand != ~0ull) atomicMin(&S.best[slot], cand);
-            // the lane holding the minimum records its leaf (ids are unique, so at
-            // most one lane per query matches); a later round may overwrite it
-            if (cand != ~0ull && S.best[slot] == cand) S.leaf[slot] = cand_leaf;
-            best = act ? S.best[slot] : 0ull;
-            const float bound = __uint_as_float(static_cast<uint32_t>(best >> 32)) * kPruneSlack;
-            const float dl = (act && lref >= 0) ? box_dist2(qp, xyz(l0), xyz(l1)) : INFINITY;
-            const float dr = (act && rref >= 0) ? box_dist2(qp, xyz(r0), xyz(r1)) : INFINITY;
-            const bool pl = act && lref >= 0 && dl <= bound;
-            const bool pr = act && rref >= 0 && dr <= bound;
-            const uint64_t bl = __ballot(pl), br = __ballot(pr);
-            const int off = sp + __popcll(bl & lt) + __popcll(br & lt);
-            // The bound above only holds for a valid tree; the clamp keeps a
-            // corrupted buffer from writing past this wave's stack.
-            if (pl && pr) {
-                const bool left_near = dl <= dr;   // nearer child on top of the stack
-                if (off < kBatchAlloc) {
-                    S.node[off] = left_near ? rref : lref;
-                    S.dist[off] = left_near ? dr : dl;
-                    S.slot[off] = static_cast<uint8_t>(slot);
-                }
-                if (off + 1 < kBatchAlloc) {
-                    S.node[off + 1] = left_near ? lref : rref;
-                    S.dist[off + 1] = left_near ? dl : dr;
-                    S.slot[off + 1] = static_cast<uint8_t>(slot);
-                }
-            } else if ((pl || pr) && off < kBatchAlloc) {
-                S.node[off] = pl ? lref : rref;
-                S.dist[off] = pl ? dl : dr;
-                S.slot[off] = static_cast<uint8_t>(slot);
-            }
-            sp += __popcll(bl) + __popcll(br);
-            sp = sp < kBatchAlloc ? sp : kBatchAlloc;
-        }
+        run_stack<kTri, M>(a, L, self, self, sp, stats);
+        // chunks given away must be finished before the results are final
+        wait_helping<kTri, M>(a, L, self, stats, [&]() { return lds_load(&mail.outstanding[self]) == 0; });
         if (own) {
             const unsigned long long b = S.best[lane];
-            const int32_t id = static_cast<int32_t>(b & 0xffffffffull);
-            const int32_t leaf = id == INT_MAX ? -1 : S.leaf[lane];
-            write_result<kTri>(a, qid, p, leaf, id, __uint_as_float(static_cast<uint32_t>(b >> 32)));
+            write_result_id<kTri>(a, qid, p, static_cast<int32_t>(b & 0xffffffffull),
+                                  __uint_as_float(static_cast<uint32_t>(b >> 32)));
         }
-        if (a.counters) n_q += __popcll(__ballot(own));
+        if (a.counters) stats.nq += __popcll(__ballot(own));
     }
-    if (a.counters && lane == 0) add_counters(a, n_exp, n_lbox, n_lex, n_q);
+    if (lane == 0) lds_add(&mail.done, 1);
+    wait_helping<kTri, M>(a, L, self, stats, [&]() { return lds_load(&mail.done) == kBatchWaves; });
+    if (a.counters && lane == 0) add_counters(a, stats.exp, stats.lbox, stats.lex, stats.nq);
 }
 
 }  // namespace mgu

@@ -58,13 +58,16 @@ def check_closest(got, verts, faces, queries, max_dist2=math.inf):
     return ref
 
 
-KERNELS = [("lane", 0), ("batch", 1), ("batch", 8), ("batch", 32), ("seeded", 4)]
+KERNELS = [("lane", 0), ("batch", 1), ("batch", 8), ("batch", 32), ("seeded", 4), ("dynamic", 8)]
 
 
 def qa(kernel, batch):
-    """Traversal keyword arguments: "seeded" is the batch kernel with a greedy first descent."""
+    """Traversal keyword arguments: "seeded" is the batch kernel with a greedy first descent,
+    "dynamic" that kernel taking its batches from a work counter."""
     if kernel == "seeded":
         return {"kernel": "batch", "batch": batch, "seed": True}
+    if kernel == "dynamic":
+        return {"kernel": "batch", "batch": batch, "seed": True, "dynamic": True}
     return {"kernel": kernel, "batch": batch}
 
 
