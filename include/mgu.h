@@ -152,12 +152,21 @@ mg_status mg_mesh_gaussian_update_backward(const float *verts, int32_t n_verts, 
  *   node_parent int32  [n-1]     (parent << 1) | slot, -1 for the root (node 0)
  *   nodes       float4 [n-1][6]  per internal node, slot 0 = left child (float4
  *                                0..2), slot 1 = right child (float4 3..5):
- *                                internal child: (lo.xyz, ref) (hi.xyz, 0) (unused)
+ *                                internal child (triangles): (lo.xyz, ref) (hi.xyz, a) (d.xyz, b)
+ *                                internal child (points):    (lo.xyz, ref) (hi.xyz, 0) (unused)
  *                                leaf triangle:  (v0.xyz, ref) (v1.xyz, id) (v2.xyz, 0)
  *                                leaf point:     (p.xyz, ref)  (p.xyz, id)  (unused)
  *                                ref (int bits): >= 0 internal node, < 0 leaf ~ref;
  *                                id: original primitive id.  A leaf's box is the
- *                                min/max of its vertices; refit rewrites all of it.
+ *                                min/max of its vertices.  Normal slab of an
+ *                                internal child: d is the unit sum of the area-
+ *                                weighted normals of the faces below it (for the
+ *                                vertices of the last build/refit; zero with
+ *                                a = -inf, b = +inf when that sum vanishes), and
+ *                                a <= d.x <= b for every point x of those faces
+ *                                (a conservative bound, formed bottom-up from the
+ *                                children's slabs and the node's box).  The
+ *                                refit rewrites all of it.
  *   node_aux    int32  [n-1]     refit schedule: index among the "top" nodes (those
  *                                with more than 2^chunk_log2 leaves), or -1
  *   top_nodes   int32  [n]       node id of each top node (header.n_top of them)
@@ -166,8 +175,9 @@ mg_status mg_mesh_gaussian_update_backward(const float *verts, int32_t n_verts, 
  *   subtrees    int32  [3][n]    per subtree (header.n_sub): root reference, first
  *                                and last leaf; the subtrees (at most 2^chunk_log2
  *                                leaves, children of top nodes) cut the tree
- *   top_box     float  [2][6][n] refit scratch: subtree-root boxes per top node slot
- *   top_scratch uint32 [11][n]   second-phase refit scratch when n_top is large
+ *   top_box     float  [2][11][n] refit scratch: subtree-root box, normal sum and
+ *                                slab per top node slot
+ *   top_scratch uint32 [26][n]   second-phase refit scratch when n_top is large
  *   inv_prim    int32  [n]       original primitive id -> leaf (inverse of prim)
  * ---------------------------------------------------------------------- */
 
@@ -482,8 +492,10 @@ typedef struct mg_batch_options {
 
 /* Bytes of the device plan for these scenes (scenes: host array).  Reads each
  * scene BVH's top-node count from its device header (a synchronous copy):
- * scenes with more than 1024 top nodes get second-phase refit scratch in the
- * plan. */
+ * scenes with more than 384 top nodes get second-phase refit scratch in the
+ * plan.  A scene may have at most 262,144 faces (the batched refit keeps
+ * subtrees of up to 512 leaves in LDS); larger ones give
+ * MG_ERR_INVALID_ARGUMENT. */
 mg_status mg_batch_plan_size(const mg_batch_scene *scenes, int32_t n_scenes, size_t *plan_bytes);
 
 /* Validate the scenes and write the device plan (scene table, work-item

@@ -24,8 +24,8 @@ namespace mgu {
 namespace {
 
 constexpr int kBlock = 256;                 // 4 waves
-constexpr int kBatchTopLds = 768;           // top nodes per scene kept in LDS by the batched refit
-constexpr int kBatchMaxChunkLog2 = 10;      // subtrees of up to 1024 leaves (scenes up to 524,288 faces)
+constexpr int kBatchTopLds = 384;           // top nodes per scene kept in LDS by the batched refit
+constexpr int kBatchMaxChunkLog2 = 9;       // subtrees of up to 512 leaves (scenes up to 262,144 faces)
 constexpr int kMaxScenes = 64;
 constexpr int kSpin = 1 << 22;
 
@@ -35,7 +35,7 @@ struct PlanScene {
     const int32_t *top_child, *subtrees;
     const int32_t *n_top, *n_sub;           // the scene BVH's counts (device)
     float *top_box;                         // [n_frames][2][6][n_top] deposited subtree-root boxes
-    uint32_t *top_scratch;                  // [n_frames][11][n_top] when n_top > kBatchTopLds, else null
+    uint32_t *top_scratch;                  // [n_frames][kTopStatePlanes][n_top] when n_top > kBatchTopLds, else null
     int32_t n_top_host, n_sub_host;         // counts read at plan time
     int32_t batch, seed, query_tile;        // this scene's traversal (plan defaults resolved)
     int32_t chunk_log2;
@@ -82,7 +82,7 @@ inline mg_status read_schedule(const mg_batch_scene &s, Schedule &S) {
 // Scratch words of one frame of a scene: deposited boxes, and second-phase
 // state when the top nodes exceed the LDS capacity.
 inline int64_t frame_scratch_words(int32_t T) {
-    return 12 * static_cast<int64_t>(T) + (T > kBatchTopLds ? 11 * static_cast<int64_t>(T) : 0);
+    return 2 * kTopBoxPlanes * static_cast<int64_t>(T) + (T > kBatchTopLds ? kTopStatePlanes * static_cast<int64_t>(T) : 0);
 }
 
 // Plan layout: header, 2 x total_sf dependency counters, then per scene-frame
@@ -148,8 +148,8 @@ __device__ RefitArgs refit_args(const PlanScene &P, int64_t t, PlanHeader *h) {
     a.top_child = P.top_child;
     a.subtrees = P.subtrees;
     a.tstride = P.n_top_host;
-    a.top_box = P.top_box + t * 12 * static_cast<int64_t>(P.n_top_host);
-    a.top_scratch = P.top_scratch ? P.top_scratch + t * 11 * static_cast<int64_t>(P.n_top_host) : nullptr;
+    a.top_box = P.top_box + t * 2 * kTopBoxPlanes * static_cast<int64_t>(P.n_top_host);
+    a.top_scratch = P.top_scratch ? P.top_scratch + t * kTopStatePlanes * static_cast<int64_t>(P.n_top_host) : nullptr;
     a.root = s.roots + 8 * t;
     a.status = &h->status;
     a.n_top = P.n_top;
@@ -240,9 +240,10 @@ __global__ __launch_bounds__(kBlock) void batch_persistent_kernel(PlanHeader *h)
             if (T != P.n_top_host) {
                 if (threadIdx.x == 0) atomicOr(&h->status, 2);   // the BVH was rebuilt after planning
             } else if (T > 0 && T <= kBatchTopLds) {
-                refit_top<true, kBlock>(r, T, reinterpret_cast<uint32_t *>(smem), kBatchTopLds);
+                refit_top<true, kBlock, (kBatchTopLds + kBlock - 1) / kBlock>(r, T, reinterpret_cast<uint32_t *>(smem),
+                                                                              kBatchTopLds);
             } else if (T > kBatchTopLds) {
-                refit_top<true, kBlock>(r, T, r.top_scratch, T);
+                refit_top<true, kBlock, 1>(r, T, r.top_scratch, T);
             }
             signal(&refit_done[sf], 1u);
         } else {
@@ -359,13 +360,13 @@ extern "C" mg_status mg_batch_plan_init(const mg_batch_scene *scenes, int32_t n_
         P.n_top_host = S.n_top;
         P.n_sub_host = S.n_sub;
         P.chunk_log2 = S.chunk_log2;
-        // per-frame scratch: [n_frames][12][T] deposited boxes, then [n_frames][11][T] phase-2 state
+        // per-frame scratch: [n_frames][2][kTopBoxPlanes][T] deposits, then [n_frames][kTopStatePlanes][T] phase-2 state
         P.top_box = reinterpret_cast<float *>(scratch);
-        scratch += static_cast<int64_t>(s.n_frames) * 12 * S.n_top;
+        scratch += static_cast<int64_t>(s.n_frames) * 2 * kTopBoxPlanes * S.n_top;
         P.top_scratch = nullptr;
         if (S.n_top > kBatchTopLds) {
             P.top_scratch = scratch;
-            scratch += static_cast<int64_t>(s.n_frames) * 11 * S.n_top;
+            scratch += static_cast<int64_t>(s.n_frames) * kTopStatePlanes * S.n_top;
         }
         P.sf_base = static_cast<int32_t>(sf);
         P.n_chunks = S.n_sub;

@@ -54,8 +54,8 @@ inline mg_lbvh_layout make_layout(int64_t n, int kind) {
     L.off_top_nodes = o;   o += align256(4 * n);
     L.off_top_child = o;   o += align256(8 * n);
     L.off_subtrees = o;    o += align256(12 * n);
-    L.off_top_box = o;     o += align256(48 * n);
-    L.off_top_scratch = o; o += align256(44 * n);
+    L.off_top_box = o;     o += align256(8 * kTopBoxPlanes * n);
+    L.off_top_scratch = o; o += align256(4 * kTopStatePlanes * n);
     L.off_inv_prim = o;    o += align256(4 * n);
     L.total_bytes = o;
     return L;
@@ -491,15 +491,23 @@ __global__ __launch_bounds__(kThreads) void refit_sub_kernel(RefitArgs a) {
 
 // Phase 1 with one workgroup thread per two leaves of the largest subtree
 // (at least 256 threads), so the climbs of a subtree mostly run side by side.
+template <bool kTri, int kThreads>
+void launch_refit_sub_t(const RefitArgs &a, size_t lds, int grid, hipStream_t s) {
+    if (lds > 65536)    // beyond the default dynamic LDS limit (gfx950 has 160 KB per workgroup)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&refit_sub_kernel<kTri, kThreads>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    hipLaunchKernelGGL((refit_sub_kernel<kTri, kThreads>), dim3(grid), dim3(kThreads), lds, s, a);
+}
+
 template <bool kTri>
 void launch_refit_sub(const RefitArgs &a, int64_t C, int grid, hipStream_t s) {
     const size_t lds = refit_sub_lds(C);
     if (C >= 2048)
-        hipLaunchKernelGGL((refit_sub_kernel<kTri, 1024>), dim3(grid), dim3(1024), lds, s, a);
+        launch_refit_sub_t<kTri, 1024>(a, lds, grid, s);
     else if (C >= 1024)
-        hipLaunchKernelGGL((refit_sub_kernel<kTri, 512>), dim3(grid), dim3(512), lds, s, a);
+        launch_refit_sub_t<kTri, 512>(a, lds, grid, s);
     else
-        hipLaunchKernelGGL((refit_sub_kernel<kTri, 256>), dim3(grid), dim3(256), lds, s, a);
+        launch_refit_sub_t<kTri, 256>(a, lds, grid, s);
 }
 
 // Phase 2: one workgroup, one top node per thread while they fit in LDS.
@@ -507,8 +515,8 @@ template <bool kTri>
 __global__ __launch_bounds__(1024) void refit_top_kernel(RefitArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int T = *a.n_top;
-    if (T > 0 && T <= kTopLds) refit_top<kTri, 1024>(a, T, reinterpret_cast<uint32_t *>(smem), kTopLds);
-    else if (T > kTopLds) refit_top<kTri, 1024>(a, T, a.top_scratch, a.n);
+    if (T > 0 && T <= kTopLds) refit_top<kTri, 1024, 1>(a, T, reinterpret_cast<uint32_t *>(smem), kTopLds);
+    else if (T > kTopLds) refit_top<kTri, 1024, 1>(a, T, a.top_scratch, a.n);
 }
 
 mg_status check_kind(int32_t kind) {
@@ -545,10 +553,14 @@ mg_status launch_refit(const float *verts, int64_t nv, void *bvh, int64_t n, int
     else
         launch_refit_sub<false>(a, C, grid, s);
     if (n > C) {   // otherwise the one subtree is the whole tree and phase 1 wrote the root
+        const size_t lds = refit_top_lds(kTopLds);
+        const void *fn = kind == MG_PRIM_TRIANGLES ? reinterpret_cast<const void *>(&refit_top_kernel<true>)
+                                                   : reinterpret_cast<const void *>(&refit_top_kernel<false>);
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
         if (kind == MG_PRIM_TRIANGLES)
-            hipLaunchKernelGGL(refit_top_kernel<true>, dim3(1), dim3(1024), refit_top_lds(kTopLds), s, a);
+            hipLaunchKernelGGL(refit_top_kernel<true>, dim3(1), dim3(1024), lds, s, a);
         else
-            hipLaunchKernelGGL(refit_top_kernel<false>, dim3(1), dim3(1024), refit_top_lds(kTopLds), s, a);
+            hipLaunchKernelGGL(refit_top_kernel<false>, dim3(1), dim3(1024), lds, s, a);
     }
     return launch_status();
 }

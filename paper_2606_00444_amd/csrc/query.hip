@@ -40,6 +40,7 @@ __global__ __launch_bounds__(kLaneBlock) void traverse_lane_kernel(QueryArgs a) 
     const int64_t q = query_at(a, pos);
     if (q < 0) return;
     const f3 p = load3(a.queries, a.nq, q);
+    const float dq = slab_query_margin(p);
     float best = a.maxd2;
     int32_t best_id = INT_MAX, best_leaf = -1;
     unsigned long long n_exp = 0, n_lbox = 0, n_lex = 0;
@@ -74,8 +75,8 @@ __global__ __launch_bounds__(kLaneBlock) void traverse_lane_kernel(QueryArgs a) 
             if (rref < 0 && leaf_box_dist2<kTri>(p, r0, r1, r2) <= best * kPruneSlack)
                 consider(leaf_dist2<kTri>(p, r0, r1, r2), __float_as_int(r1.w), ~rref);
             const float bound = best * kPruneSlack;
-            const float dl = lref >= 0 ? box_dist2(p, xyz(l0), xyz(l1)) : INFINITY;
-            const float dr = rref >= 0 ? box_dist2(p, xyz(r0), xyz(r1)) : INFINITY;
+            const float dl = lref >= 0 ? child_bound<kTri>(p, dq, l0, l1, l2) : INFINITY;
+            const float dr = rref >= 0 ? child_bound<kTri>(p, dq, r0, r1, r2) : INFINITY;
             const bool gl = lref >= 0 && dl <= bound, gr = rref >= 0 && dr <= bound;
             if (gl && gr) {
                 const bool left_first = dl <= dr;
@@ -125,6 +126,7 @@ __global__ __launch_bounds__(kLaneBlock) void knn_lane_kernel(QueryArgs a, int k
     const int64_t q = static_cast<int64_t>(blockIdx.x) * kLaneBlock + lane;
     if (q >= a.nq) return;
     const f3 p = load3(a.queries, a.nq, q);
+    const float dq = slab_query_margin(p);
     float bd[K];
     int32_t bid[K], bleaf[K];
 #pragma unroll
@@ -178,8 +180,8 @@ __global__ __launch_bounds__(kLaneBlock) void knn_lane_kernel(QueryArgs a, int k
             if (rref < 0 && leaf_box_dist2<true>(p, r0, r1, r2) <= kth() * kPruneSlack)
                 consider(leaf_dist2<true>(p, r0, r1, r2), __float_as_int(r1.w), ~rref);
             const float bound = kth() * kPruneSlack;
-            const float dl = lref >= 0 ? box_dist2(p, xyz(l0), xyz(l1)) : INFINITY;
-            const float dr = rref >= 0 ? box_dist2(p, xyz(r0), xyz(r1)) : INFINITY;
+            const float dl = lref >= 0 ? child_bound<true>(p, dq, l0, l1, l2) : INFINITY;
+            const float dr = rref >= 0 ? child_bound<true>(p, dq, r0, r1, r2) : INFINITY;
             const bool gl = lref >= 0 && dl <= bound, gr = rref >= 0 && dr <= bound;
             if (gl && gr) {
                 const bool left_first = dl <= dr;

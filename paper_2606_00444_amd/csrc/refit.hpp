@@ -23,9 +23,13 @@
 // when the root is.  Boxes, child indices and flags live in LDS (or in global
 // scratch when there are more top nodes than fit).
 //
-// Boxes are exact (min/max only), so any schedule gives bitwise the same
-// records.  Every index read from the buffer is range-checked; a corrupted
-// buffer sets the error word instead of faulting or hanging.
+// Triangle BVHs also carry a normal slab per internal child (see Slab below):
+// a node's is formed from its two children's, in slot order, by the thread
+// that finishes the node.  Boxes are exact (min/max only) and slabs are
+// evaluated in a fixed order with contraction off, so any schedule gives
+// bitwise the same records.  Every index read from the buffer is
+// range-checked; a corrupted buffer sets the error word instead of faulting or
+// hanging.
 #pragma once
 
 #include "mgu_internal.hpp"
@@ -42,9 +46,9 @@ struct RefitArgs {
     const int32_t *top_nodes;     // [T] node id of each top node
     const int32_t *top_child;     // [2][n] top index of each child, -1 when it roots a subtree
     const int32_t *subtrees;      // [3][n_sub]: root reference, first leaf, last leaf
-    float *top_box;               // [2][6][tstride] deposited subtree-root boxes
+    float *top_box;               // [2][kTopBoxPlanes][tstride] deposited subtree roots: box, normal sum, slab
     int64_t tstride;
-    uint32_t *top_scratch;        // [11][tstride] phase-2 state when T exceeds the LDS capacity
+    uint32_t *top_scratch;        // [kTopStatePlanes][tstride] phase-2 state when T exceeds the LDS capacity
     float *root;                  // root box: lo at [0..2], hi at [4..6]
     int32_t *status;              // error word
     const int32_t *n_top;         // number of top nodes (device)
@@ -54,11 +58,119 @@ struct RefitArgs {
 };
 
 constexpr int kTopLds = 1024;     // top nodes handled with LDS state in the plain refit
+constexpr int kTopBoxPlanes = 11; // per deposit slot: box (6), normal sum (3), slab (2)
+constexpr int kTopStatePlanes = 26;
 
-// LDS bytes of phase 1 for subtrees of up to C leaves, and of phase 2 for Tl
-// top nodes (6 box planes, 2 child indices, node id, done and ready flags).
-constexpr size_t refit_sub_lds(int64_t C) { return static_cast<size_t>(C) * 32; }
-constexpr size_t refit_top_lds(int64_t Tl) { return static_cast<size_t>(Tl) * 44; }
+// LDS bytes of phase 1 for subtrees of up to C leaves (per local node: 6 box
+// planes, arrival counter, parent link, and per child slot its normal sum and
+// slab), and of phase 2 for Tl top nodes (6 box planes, 2 child indices, node
+// id, done and ready flags, own normal sum and slab, and per slot the
+// deposited subtree root's normal sum and slab).
+constexpr size_t refit_sub_lds(int64_t C) { return static_cast<size_t>(C) * 72; }
+constexpr size_t refit_top_lds(int64_t Tl) { return static_cast<size_t>(Tl) * 4 * kTopStatePlanes; }
+
+// ------------------------------------------------------------- normal slabs
+// An internal child slot of a triangle BVH stores, besides its box, a unit
+// direction d (the normalised sum of the area-weighted normals of the faces
+// below it, for the current vertices) and [a, b] with a <= d.x <= b for every
+// point x of those faces; the distance from q to them is then at least
+// max(a - d.q, d.q - b, 0).  A parent's [a, b] comes from its children's: with
+// alpha = d.d_c and r = d - alpha d_c, d.x = alpha (d_c.x) + r.x, where the
+// first term lies in alpha [a_c, b_c] and the second in the range of r.x over
+// the parent's box (for a leaf child, [a_c, b_c] is its triangle's extent along
+// its own normal); the result is intersected with the range of d.x over the
+// box.  Every extent is widened by 2^-18 of the box's coordinate magnitudes,
+// which covers the float32 rounding of these sums at every level.
+struct Slab {
+    f3 s;                         // unnormalised normal sum
+    float a, b;
+};
+
+// Unit direction of a normal sum by the hardware reciprocal square root (any
+// direction gives a valid slab, since the extents are taken along the stored
+// one; |d| is 1 to about 2^-22, which the traversal's bound allows for).
+// Sums too small to normalise safely give no direction.
+__device__ __forceinline__ f3 slab_dir(f3 s) {
+    const float l2 = dot(s, s);
+    if (!(l2 > 1e-30f) || !(l2 < 1e30f)) return f3{0.0f, 0.0f, 0.0f};
+    return __builtin_amdgcn_rsqf(l2) * s;
+}
+
+__device__ __forceinline__ float slab_margin(f3 lo, f3 hi) {
+    return 0x1p-18f * (((fabsf(lo.x) + fabsf(hi.x)) + (fabsf(lo.y) + fabsf(hi.y))) + (fabsf(lo.z) + fabsf(hi.z)));
+}
+
+// [mn, mx] of r.x over the box [lo, hi].
+__device__ __forceinline__ void box_range(f3 r, f3 lo, f3 hi, float &mn, float &mx) {
+    mn = (fminf(r.x * lo.x, r.x * hi.x) + fminf(r.y * lo.y, r.y * hi.y)) + fminf(r.z * lo.z, r.z * hi.z);
+    mx = (fmaxf(r.x * lo.x, r.x * hi.x) + fmaxf(r.y * lo.y, r.y * hi.y)) + fmaxf(r.z * lo.z, r.z * hi.z);
+}
+
+__device__ Slab leaf_slab(f3 x, f3 y, f3 z, f3 lo, f3 hi) {
+#pragma clang fp contract(off)
+    Slab S;
+    S.s = cross(y - x, z - x);
+    const f3 d = slab_dir(S.s);
+    if (d.x == 0.0f && d.y == 0.0f && d.z == 0.0f) {
+        S.a = -INFINITY;
+        S.b = INFINITY;
+        return S;
+    }
+    const float px = dot(d, x), py = dot(d, y), pz = dot(d, z);
+    const float e = slab_margin(lo, hi);
+    S.a = fminf(fminf(px, py), pz) - e;
+    S.b = fmaxf(fmaxf(px, py), pz) + e;
+    return S;
+}
+
+// The slab of a node with box [lo, hi] from its children's (slot order); d is
+// its unit direction.
+__device__ Slab join_slab(const Slab &c0, const Slab &c1, f3 lo, f3 hi, f3 &d) {
+#pragma clang fp contract(off)
+    Slab P;
+    P.s = c0.s + c1.s;
+    d = slab_dir(P.s);
+    if (d.x == 0.0f && d.y == 0.0f && d.z == 0.0f) {
+        P.a = -INFINITY;
+        P.b = INFINITY;
+        return P;
+    }
+    float a, b;
+    box_range(d, lo, hi, a, b);
+    float ca = INFINITY, cb = -INFINITY;
+    const Slab *cs[2] = {&c0, &c1};
+    for (int k = 0; k < 2; ++k) {
+        const Slab &c = *cs[k];
+        const f3 dc = slab_dir(c.s);
+        if (!(c.a > -INFINITY) || !(c.b < INFINITY) || (dc.x == 0.0f && dc.y == 0.0f && dc.z == 0.0f)) {
+            ca = fminf(ca, a);
+            cb = fmaxf(cb, b);
+            continue;
+        }
+        const float al = dot(d, dc);
+        const f3 r = d - al * dc;
+        float rmn, rmx;
+        box_range(r, lo, hi, rmn, rmx);
+        ca = fminf(ca, (al >= 0.0f ? al * c.a : al * c.b) + rmn);
+        cb = fmaxf(cb, (al >= 0.0f ? al * c.b : al * c.a) + rmx);
+    }
+    const float e = slab_margin(lo, hi);
+    P.a = fmaxf(a, ca) - e;
+    P.b = fminf(b, cb) + e;
+    return P;
+}
+
+// Record slot of an internal child: (lo, ref) (hi, a) (d, b); points carry no slab.
+template <bool kTri>
+__device__ __forceinline__ void write_internal(float4 *rec, int32_t ref, f3 lo, f3 hi, f3 d, const Slab &S) {
+    rec[0] = make_float4(lo.x, lo.y, lo.z, __int_as_float(ref));
+    if (kTri) {
+        rec[1] = make_float4(hi.x, hi.y, hi.z, S.a);
+        rec[2] = make_float4(d.x, d.y, d.z, S.b);
+    } else {
+        rec[1] = make_float4(hi.x, hi.y, hi.z, 0.0f);
+    }
+}
 
 __device__ __forceinline__ void write_root(float *root, f3 lo, f3 hi) {
     root[0] = lo.x; root[1] = lo.y; root[2] = lo.z;
@@ -85,14 +197,19 @@ __device__ __forceinline__ void lds_empty(uint32_t *b, int64_t stride, int64_t j
     b[3 * stride + j] = e_hi; b[4 * stride + j] = e_hi; b[5 * stride + j] = e_hi;
 }
 
-// Deposit the box of a subtree root into slot `slot` of its top parent p.
-__device__ __forceinline__ void deposit(const RefitArgs &a, int32_t p, int slot, f3 lo, f3 hi) {
+// Deposit the box, normal sum and slab of a subtree root into slot `slot` of
+// its top parent p.
+__device__ __forceinline__ void deposit(const RefitArgs &a, int32_t p, int slot, f3 lo, f3 hi, const Slab &S) {
     const int32_t t = a.node_aux[p];
     if (t < 0 || t >= a.tstride) { atomicOr(a.status, 8); return; }
-    float *b = a.top_box + static_cast<int64_t>(slot) * 6 * a.tstride + t;
-    b[0] = lo.x; b[a.tstride] = lo.y; b[2 * a.tstride] = lo.z;
-    b[3 * a.tstride] = hi.x; b[4 * a.tstride] = hi.y; b[5 * a.tstride] = hi.z;
+    float *b = a.top_box + static_cast<int64_t>(slot) * kTopBoxPlanes * a.tstride + t;
+    const int64_t ts = a.tstride;
+    b[0] = lo.x; b[ts] = lo.y; b[2 * ts] = lo.z;
+    b[3 * ts] = hi.x; b[4 * ts] = hi.y; b[5 * ts] = hi.z;
+    b[6 * ts] = S.s.x; b[7 * ts] = S.s.y; b[8 * ts] = S.s.z;
+    b[9 * ts] = S.a; b[10 * ts] = S.b;
 }
+
 
 // Phase 1 for subtree k by a workgroup of kThreads threads (a compile-time
 // stride: blockDim would be reloaded from the dispatch packet, and that load's
@@ -106,6 +223,7 @@ __device__ void refit_subtree(const RefitArgs &a, int64_t k, unsigned char *smem
     uint32_t *s_box = reinterpret_cast<uint32_t *>(smem);          // [6][C]
     uint32_t *s_cnt = s_box + 6 * C;                               // [C]
     int32_t *s_par = reinterpret_cast<int32_t *>(s_cnt + C);       // [C]
+    float *s_dep = reinterpret_cast<float *>(s_par + C);           // [2 slots][5][C]: normal sum, slab
     const int64_t size = l - f + 1;
     if (f < 0 || l >= a.n || size < 1 || size > C) {
         if (threadIdx.x == 0) atomicOr(a.status, 4);
@@ -128,6 +246,8 @@ __device__ void refit_subtree(const RefitArgs &a, int64_t k, unsigned char *smem
             x = y = z = load3(a.verts, a.nv, id);
         }
         f3 lo = fmin3(fmin3(x, y), z), hi = fmax3(fmax3(x, y), z);
+        Slab S{f3{0.0f, 0.0f, 0.0f}, -INFINITY, INFINITY};
+        if (kTri) S = leaf_slab(x, y, z, lo, hi);
         const int32_t tag = a.leaf_parent[i];
         if (tag < 0) {            // a single leaf is the root
             write_root(a.root, lo, hi);
@@ -140,17 +260,29 @@ __device__ void refit_subtree(const RefitArgs &a, int64_t k, unsigned char *smem
         rec[1] = make_float4(y.x, y.y, y.z, __int_as_float(id));
         if (kTri) rec[2] = make_float4(z.x, z.y, z.z, 0.0f);
         if (r == ~static_cast<int32_t>(i)) {      // a one-leaf subtree
-            deposit(a, p, slot, lo, hi);
+            deposit(a, p, slot, lo, hi, S);
             continue;
         }
         // a valid tree is at most 62 levels deep
         for (int level = 0; level < 64; ++level) {
             const int64_t j = p - f;
             if (j < 0 || j >= size) { atomicOr(a.status, 4); break; }
+            if (kTri) {
+                float *dep = s_dep + static_cast<int64_t>(slot) * 5 * C + j;
+                dep[0] = S.s.x; dep[C] = S.s.y; dep[2 * C] = S.s.z; dep[3 * C] = S.a; dep[4 * C] = S.b;
+            }
             lds_union(s_box, C, j, lo, hi);
             const uint32_t old = __hip_atomic_fetch_add(&s_cnt[j], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (old == 0) break;                  // the sibling finishes node p
             lds_read(s_box, C, j, lo, hi);
+            f3 d = f3{0.0f, 0.0f, 0.0f};
+            if (kTri) {
+                Slab c0, c1;
+                const float *d0 = s_dep + j, *d1 = s_dep + 5 * C + j;
+                c0.s = f3{d0[0], d0[C], d0[2 * C]}; c0.a = d0[3 * C]; c0.b = d0[4 * C];
+                c1.s = f3{d1[0], d1[C], d1[2 * C]}; c1.a = d1[3 * C]; c1.b = d1[4 * C];
+                S = join_slab(c0, c1, lo, hi, d);
+            }
             const int32_t c = p;
             const int32_t ptag = s_par[j];
             if (ptag < 0) {
@@ -161,10 +293,9 @@ __device__ void refit_subtree(const RefitArgs &a, int64_t k, unsigned char *smem
             slot = ptag & 1;
             if (p >= a.n - 1) { atomicOr(a.status, 4); break; }
             rec = a.nodes + 6 * static_cast<int64_t>(p) + 3 * slot;
-            rec[0] = make_float4(lo.x, lo.y, lo.z, __int_as_float(c));
-            rec[1] = make_float4(hi.x, hi.y, hi.z, 0.0f);
+            write_internal<kTri>(rec, c, lo, hi, d, S);
             if (c == r) {
-                deposit(a, p, slot, lo, hi);
+                deposit(a, p, slot, lo, hi, S);
                 break;
             }
         }
@@ -172,22 +303,26 @@ __device__ void refit_subtree(const RefitArgs &a, int64_t k, unsigned char *smem
 }
 
 // Phase 2 over T top nodes with state at st (stride planes of uint32: 6 box
-// planes, 2 child planes, node id, done, ready), in LDS or global scratch;
+// planes, 2 child planes, node id, done, ready, normal sum and slab (5), the
+// two slots' deposited normal sums and slabs (10)), in LDS or global scratch;
 // one workgroup of kThreads.  Returns after the root's box is written.
 //
 // While every thread owns at most kOwn nodes (T <= kOwn kThreads), a thread
 // keeps its nodes' child indices, ids, boxes and flags in registers, so a
 // round costs one LDS read of the children's flags and one of their boxes;
-// larger T keep everything in the planes.
-template <bool kTri, int kThreads>
+// larger T keep everything in the planes.  (kOwn stays small: every owned node
+// carries a copy of the finishing code, and registers are scarce at 1024
+// threads.)
+template <bool kTri, int kThreads, int kOwn>
 __device__ void refit_top(const RefitArgs &a, int T, uint32_t *st, int64_t stride) {
-    constexpr int kOwn = 4;
     __shared__ int s_root, s_root_done;
     uint32_t *bx = st;
     int32_t *ch = reinterpret_cast<int32_t *>(st + 6 * stride);
     int32_t *node = reinterpret_cast<int32_t *>(st + 8 * stride);
     uint32_t *done = st + 9 * stride;
     uint32_t *rdy = st + 10 * stride;
+    float *sl = reinterpret_cast<float *>(st + 11 * stride);      // [5][stride]: normal sum, a, b
+    float *dp = reinterpret_cast<float *>(st + 16 * stride);      // [2][5][stride]: deposits
     if (threadIdx.x == 0) {
         s_root = -1;
         s_root_done = 0;
@@ -199,9 +334,11 @@ __device__ void refit_top(const RefitArgs &a, int T, uint32_t *st, int64_t strid
             const int32_t c = a.top_child[s * a.n + t];
             ch[s * stride + t] = c;
             if (c >= 0) continue;                 // a top child: merged in a later round
-            const float *b = a.top_box + static_cast<int64_t>(s) * 6 * a.tstride + t;
+            const float *b = a.top_box + static_cast<int64_t>(s) * kTopBoxPlanes * a.tstride + t;
             lo = fmin3(lo, f3{b[0], b[a.tstride], b[2 * a.tstride]});
             hi = fmax3(hi, f3{b[3 * a.tstride], b[4 * a.tstride], b[5 * a.tstride]});
+            if (kTri)
+                for (int q = 0; q < 5; ++q) dp[(s * 5 + q) * stride + t] = b[(6 + q) * a.tstride];
         }
         bx[0 * stride + t] = f2ord(lo.x); bx[1 * stride + t] = f2ord(lo.y); bx[2 * stride + t] = f2ord(lo.z);
         bx[3 * stride + t] = f2ord(hi.x); bx[4 * stride + t] = f2ord(hi.y); bx[5 * stride + t] = f2ord(hi.z);
@@ -216,19 +353,42 @@ __device__ void refit_top(const RefitArgs &a, int T, uint32_t *st, int64_t strid
         return;
     }
     const int root = s_root;
-    // finish node t (its top children are done): union, records of its top children
+    auto plane_slab = [&](const float *pl, int c) {
+        Slab S;
+        S.s = f3{pl[c], pl[stride + c], pl[2 * stride + c]};
+        S.a = pl[3 * stride + c];
+        S.b = pl[4 * stride + c];
+        return S;
+    };
+    // finish node t (its top children are done): union, slab, records of its top children
     auto finish = [&](int t, int32_t pn, int32_t c0, int32_t c1, f3 lo, f3 hi) {
         const int32_t cs[2] = {c0, c1};
+        f3 clo[2], chi[2];
         for (int s = 0; s < 2; ++s) {
             const int32_t c = cs[s];
             if (c < 0) continue;
-            f3 clo, chi;
-            lds_read(bx, stride, c, clo, chi);
-            lo = fmin3(lo, clo);
-            hi = fmax3(hi, chi);
-            float4 *rec = a.nodes + 6 * static_cast<int64_t>(pn) + 3 * s;
-            rec[0] = make_float4(clo.x, clo.y, clo.z, __int_as_float(node[c]));
-            rec[1] = make_float4(chi.x, chi.y, chi.z, 0.0f);
+            lds_read(bx, stride, c, clo[s], chi[s]);
+            lo = fmin3(lo, clo[s]);
+            hi = fmax3(hi, chi[s]);
+        }
+        if (kTri) {
+            Slab cslab[2];
+            for (int s = 0; s < 2; ++s) cslab[s] = cs[s] >= 0 ? plane_slab(sl, cs[s]) : plane_slab(dp + s * 5 * stride, t);
+            f3 d;
+            const Slab S = join_slab(cslab[0], cslab[1], lo, hi, d);
+            sl[t] = S.s.x; sl[stride + t] = S.s.y; sl[2 * stride + t] = S.s.z;
+            sl[3 * stride + t] = S.a; sl[4 * stride + t] = S.b;
+            for (int s = 0; s < 2; ++s) {
+                if (cs[s] < 0) continue;
+                write_internal<true>(a.nodes + 6 * static_cast<int64_t>(pn) + 3 * s, node[cs[s]], clo[s], chi[s],
+                                     slab_dir(cslab[s].s), cslab[s]);
+            }
+        } else {
+            for (int s = 0; s < 2; ++s) {
+                if (cs[s] < 0) continue;
+                write_internal<false>(a.nodes + 6 * static_cast<int64_t>(pn) + 3 * s, node[cs[s]], clo[s], chi[s],
+                                      f3{0.0f, 0.0f, 0.0f}, Slab{});
+            }
         }
         bx[0 * stride + t] = f2ord(lo.x); bx[1 * stride + t] = f2ord(lo.y); bx[2 * stride + t] = f2ord(lo.z);
         bx[3 * stride + t] = f2ord(hi.x); bx[4 * stride + t] = f2ord(hi.y); bx[5 * stride + t] = f2ord(hi.z);

@@ -83,6 +83,25 @@ __device__ __forceinline__ float leaf_box_dist2(f3 p, float4 f0, float4 f1, floa
     return dot(d, d);
 }
 
+// Margin of a query's slab distances: 2^-20 of its coordinate magnitudes
+// covers the float32 rounding of d.q.
+__device__ __forceinline__ float slab_query_margin(f3 q) {
+    return 0x1p-20f * ((fabsf(q.x) + fabsf(q.y)) + fabsf(q.z));
+}
+
+// Lower bound of the squared distance from q to the faces below an internal
+// child slot (c0, c1, c2) = (lo, ref) (hi, a) (d, b): the larger of the box
+// distance and, for triangles, the normal-slab distance (dq: the query's
+// slab margin; the factor 1 - 2^-19 allows for |d| differing from 1).
+template <bool kTri>
+__device__ __forceinline__ float child_bound(f3 q, float dq, float4 c0, float4 c1, float4 c2) {
+    const float bd = box_dist2(q, xyz(c0), xyz(c1));
+    if (!kTri) return bd;
+    const float s = c2.x * q.x + c2.y * q.y + c2.z * q.z;
+    const float g = fmaxf(c1.w - s, s - c2.w) - dq;
+    return g > 0.0f ? fmaxf(bd, (g * g) * (1.0f - 0x1p-19f)) : bd;
+}
+
 __device__ __forceinline__ unsigned long long pack_best(float d2, int32_t id) {
     return (static_cast<unsigned long long>(__float_as_uint(d2)) << 32) | static_cast<uint32_t>(id);
 }
@@ -145,12 +164,13 @@ __device__ __forceinline__ float single_leaf_dist2(const QueryArgs &a, f3 p) {
 // --------------------------------------------------------------- batch kernel
 // The waves of a workgroup each process batches of M queries with an LDS work
 // stack shared by the batch's queries; each round pops up to 64 entries (one
-// per lane).  A wave whose stack is deep hands its top 64 entries to an idle
-// wave of the same workgroup through a one-chunk mailbox, so a batch holding
-// an expensive query (one nearly equidistant from many faces) is finished by
-// several waves.  The per-query bests (d^2 bits, original id) stay with the
-// owning wave and are lowered by LDS atomics from whichever wave tests a face;
-// the owner writes its results once every chunk it gave away is done.
+// per lane).  A wave whose stack is deep puts its top 64 entries into the
+// workgroup's one-chunk mailbox whenever it is empty, and a wave that has
+// finished a batch empties the mailbox before it starts another, so a batch
+// holding an expensive query (one nearly equidistant from many faces) is
+// finished by several waves.  The per-query bests (d^2 bits, original id) stay
+// with the owning wave and are lowered by LDS atomics from whichever wave tests
+// a face; the owner writes its results once every chunk it gave away is done.
 
 constexpr int kDonateMin = 128;          // a wave keeps at least 64 entries after giving 64
 constexpr int kIdleSpinLimit = 1 << 22;  // bounded waits: error word instead of a hang
@@ -171,7 +191,6 @@ struct WaveMail {
     int32_t count;                      // entries in the chunk
     int32_t owner;                      // wave whose batch the entries belong to
     int32_t state;                      // 0 empty, 1 full, 2 being taken, 3 being filled
-    int32_t idle;                       // waves waiting for work
     int32_t done;                       // waves that have finished all their batches
     int32_t outstanding[kBatchWaves];   // chunks of each wave's batch held elsewhere
 };
@@ -217,7 +236,7 @@ __device__ void run_stack(const QueryArgs &a, BatchLds<M> &L, int self, int owne
     for (int64_t round = 0; sp > 0 && round < static_cast<int64_t>(M + 1) * a.n + 64; ++round) {
         if (sp >= kDonateMin) {
             int give = 0;
-            if (lane == 0 && lds_load(&mail.idle) > 0 && lds_cas(&mail.state, 0, 3)) give = 1;
+            if (lane == 0 && lds_load(&mail.state) == 0 && lds_cas(&mail.state, 0, 3)) give = 1;
             if (__shfl(give, 0)) {
                 const int i = sp - 64 + lane;
                 mail.node[lane] = S.node[i];
@@ -277,8 +296,9 @@ __device__ void run_stack(const QueryArgs &a, BatchLds<M> &L, int self, int owne
         if (cand != ~0ull) atomicMin(&O.best[slot], cand);
         best = act ? O.best[slot] : 0ull;
         const float bound = __uint_as_float(static_cast<uint32_t>(best >> 32)) * kPruneSlack;
-        const float dl = (act && lref >= 0) ? box_dist2(qp, xyz(l0), xyz(l1)) : INFINITY;
-        const float dr = (act && rref >= 0) ? box_dist2(qp, xyz(r0), xyz(r1)) : INFINITY;
+        const float dq = slab_query_margin(qp);
+        const float dl = (act && lref >= 0) ? child_bound<kTri>(qp, dq, l0, l1, l2) : INFINITY;
+        const float dr = (act && rref >= 0) ? child_bound<kTri>(qp, dq, r0, r1, r2) : INFINITY;
         const bool pl = act && lref >= 0 && dl <= bound;
         const bool pr = act && rref >= 0 && dr <= bound;
         const uint64_t bl = __ballot(pl), br = __ballot(pr);
@@ -327,15 +347,9 @@ __device__ bool help_once(const QueryArgs &a, BatchLds<M> &L, int self, BatchSta
         S.dist[lane] = mail.dist[lane];
         S.slot[lane] = mail.slot[lane];
     }
-    if (lane == 0) {
-        lds_add(&mail.idle, -1);
-        lds_store(&mail.state, 0);
-    }
+    if (lane == 0) lds_store(&mail.state, 0);
     run_stack<kTri, M>(a, L, self, owner, n, stats);
-    if (lane == 0) {
-        lds_add(&mail.outstanding[owner], -1);
-        lds_add(&mail.idle, 1);
-    }
+    if (lane == 0) lds_add(&mail.outstanding[owner], -1);
     return true;
 }
 
@@ -344,7 +358,6 @@ __device__ bool help_once(const QueryArgs &a, BatchLds<M> &L, int self, BatchSta
 template <bool kTri, int M, typename Cond>
 __device__ void wait_helping(const QueryArgs &a, BatchLds<M> &L, int self, BatchStats &stats, Cond cond) {
     const int lane = threadIdx.x % 64;
-    if (lane == 0) lds_add(&L.mail.idle, 1);
     for (int spin = 0; !cond();) {
         if (help_once<kTri, M>(a, L, self, stats)) {
             spin = 0;
@@ -355,7 +368,6 @@ __device__ void wait_helping(const QueryArgs &a, BatchLds<M> &L, int self, Batch
             __builtin_amdgcn_s_sleep(2);
         }
     }
-    if (lane == 0) lds_add(&L.mail.idle, -1);
 }
 
 // The workgroup's kBatchWaves waves process the query batches [qb, qb + M)
@@ -373,7 +385,6 @@ __device__ void batch_loop(const QueryArgs &a, int64_t start, int64_t stride, in
     BatchStats stats;
     if (threadIdx.x == 0) {
         mail.state = 0;
-        mail.idle = 0;
         mail.done = 0;
         for (int w = 0; w < kBatchWaves; ++w) mail.outstanding[w] = 0;
     }
@@ -406,6 +417,7 @@ __device__ void batch_loop(const QueryArgs &a, int64_t start, int64_t stride, in
             if (a.seed && own) {
                 // one greedy root-to-leaf walk (nearer internal child first) gives an
                 // upper bound before the wide expansion starts
+                const float dq = slab_query_margin(p);
                 int32_t node = 0;
                 for (int lvl = 0; lvl < 64 && node >= 0 && node < a.n - 1; ++lvl) {
                     const float4 *rec = a.nodes + 6 * static_cast<int64_t>(node);
@@ -424,8 +436,8 @@ __device__ void batch_loop(const QueryArgs &a, int64_t start, int64_t stride, in
                         const unsigned long long c = pack_best(leaf_dist2<kTri>(p, r0, r1, r2), __float_as_int(r1.w));
                         if (c < seeded) seeded = c;
                     }
-                    const float dl = lref >= 0 ? box_dist2(p, xyz(l0), xyz(l1)) : INFINITY;
-                    const float dr = rref >= 0 ? box_dist2(p, xyz(r0), xyz(r1)) : INFINITY;
+                    const float dl = lref >= 0 ? child_bound<kTri>(p, dq, l0, l1, l2) : INFINITY;
+                    const float dr = rref >= 0 ? child_bound<kTri>(p, dq, r0, r1, r2) : INFINITY;
                     node = (lref >= 0 && dl <= dr) ? lref : (rref >= 0 ? rref : -1);
                 }
                 if (seeded < none) S.best[lane] = seeded;
@@ -453,6 +465,9 @@ __device__ void batch_loop(const QueryArgs &a, int64_t start, int64_t stride, in
                                   __uint_as_float(static_cast<uint32_t>(b >> 32)));
         }
         if (a.counters) stats.nq += __popcll(__ballot(own));
+        // work already started in the workgroup goes before a new batch
+        while (help_once<kTri, M>(a, L, self, stats)) {
+        }
     }
     if (lane == 0) lds_add(&mail.done, 1);
     wait_helping<kTri, M>(a, L, self, stats, [&]() { return lds_load(&mail.done) == kBatchWaves; });

@@ -104,4 +104,42 @@ def decode_bvh(bvh):
     elif n == 1:
         lb[0] = root
     out["internal_box"], out["leaf_box"] = ib, lb
+    if bvh.kind == 0 and m:
+        # normal slab of the internal child in each slot: direction (float4 2 .xyz), a (float4 1 .w), b (float4 2 .w)
+        out["slab_dir"] = nodes[:, :, 2, :3].astype(np.float64)
+        out["slab_a"] = nodes[:, :, 1, 3].astype(np.float64)
+        out["slab_b"] = nodes[:, :, 2, 3].astype(np.float64)
     return out
+
+
+def check_slabs(got, verts):
+    """Every vertex of every face below an internal child lies inside that child's stored
+    slab, a <= d.x <= b, evaluated in float64 on the stored float32 values (no tolerance):
+    walks each leaf up through all of its internal ancestors."""
+    V = np.asarray(verts, dtype=np.float64)
+    n = got["prim"].size
+    if n < 3:
+        return 0
+    tri = V[:, got["leaf_faces"]]                          # [3 coord][3 vert][n]
+    node_parent = got["node_parent"]
+    cur = got["leaf_parent"] >> 1                           # each leaf's parent (an internal node)
+    leaves = np.arange(n)
+    checked = 0
+    for _ in range(70):
+        live = cur > 0                                      # the root (node 0) has no slab
+        if not live.any():
+            break
+        c = cur[live]
+        tag = node_parent[c]
+        ps, sl = tag >> 1, tag & 1
+        d = got["slab_dir"][ps, sl]                         # [k][3]
+        a, b = got["slab_a"][ps, sl], got["slab_b"][ps, sl]
+        x = tri[:, :, leaves[live]]                         # [3][3][k]
+        proj = np.einsum("kc,cvk->vk", d, x)
+        assert np.all(a[None] <= proj) and np.all(proj <= b[None]), "a vertex lies outside a slab"
+        assert np.all(np.isfinite(a) | (np.linalg.norm(d, axis=1) == 0))
+        checked += c.size
+        nxt = node_parent[c] >> 1
+        cur = cur.copy()
+        cur[live] = np.where(tag < 0, 0, nxt)
+    return checked

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import need_gpu, dev, decode_bvh
+from gpu_helpers import need_gpu, dev, decode_bvh, check_slabs
 from synth import make_config
 from oracle import lbvh as ol
 from oracle import morton as om
@@ -117,6 +117,27 @@ def test_refit_matches_oracle_and_fresh_root(device):
         np.testing.assert_array_equal(decode_bvh(fresh)["root_box"], got["root_box"])
         # topology untouched by refit
         np.testing.assert_array_equal(got["child"], ref["tree"]["child"])
+
+
+@pytest.mark.parametrize("cfg,small,frames", [(1, False, (0, 40)), (2, False, (0, 150)), (5, False, (0, 60))])
+def test_slabs_enclose_their_faces(device, cfg, small, frames):
+    """The normal slab of every internal child contains every vertex of the faces below
+    it, after the build and after a refit to a deformed frame (includes the 500,000-face
+    template, whose subtrees hold up to 1024 leaves)."""
+    import paper_2606_00444_amd as mg
+    sc = make_config(cfg, small=small)
+    F = dev(sc.faces, device)
+    bvh = mg.lbvh_build(dev(sc.verts0, device), F)
+    for t in frames:
+        V = sc.frames([t])[0]
+        mg.lbvh_refit(bvh, dev(V, device))
+        got = decode_bvh(bvh)
+        assert got["status"] == 0
+        n = sc.faces.shape[1]
+        assert check_slabs(got, V) >= n
+        # internal children carry unit directions (a closed surface's normal sums rarely vanish)
+        internal = got["child"].T >= 0
+        assert (np.abs(np.linalg.norm(got["slab_dir"][internal], axis=1) - 1) < 1e-5).mean() > 0.99
 
 
 def test_refit_repeated_is_bitwise_stable(device):
