@@ -30,8 +30,14 @@ namespace mgu {
 namespace {
 
 constexpr int kSortThreads = 256;          // 4 waves
-constexpr int kSortItems = 16;             // keys per lane
-constexpr int kSortTile = kSortThreads * kSortItems;
+
+// Keys per lane of a sort pass: about 256 tiles whatever the size (at least 2
+// and at most 16 keys per lane), so small sorts still spread over the chip.
+inline int sort_items_for(int64_t n) {
+    int items = 2;
+    while (items < 16 && int64_t(kSortThreads) * items * 256 < n) items <<= 1;
+    return items;
+}
 constexpr uint32_t kFlagAgg = 1u << 30;    // look-back word: tile aggregate
 constexpr uint32_t kFlagPrefix = 2u << 30; //                 inclusive prefix
 constexpr uint32_t kValueMask = (1u << 30) - 1;
@@ -77,7 +83,8 @@ struct WsLayout {
 
 inline WsLayout make_ws(int64_t n) {
     WsLayout W{};
-    W.tiles = (n + kSortTile - 1) / kSortTile;
+    const int64_t tile = int64_t(kSortThreads) * sort_items_for(n);
+    W.tiles = (n + tile - 1) / tile;
     int64_t o = 0;
     W.keys_a = o;   o += align256(4 * n);
     W.vals_a = o;   o += align256(4 * n);
@@ -250,34 +257,37 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t *s_t
     return before + inc - x;
 }
 
-// One stable LSD pass over digit (key >> shift) & 255.  vals_in == nullptr
-// means the values are the input positions (first pass).
+// One stable LSD pass over digit (key >> shift) & 255 for tiles of
+// kSortThreads * kItems keys.  vals_in == nullptr means the values are the
+// input positions (first pass).
+template <int kItems>
 __global__ __launch_bounds__(kSortThreads) void radix_pass_kernel(
     const uint32_t *__restrict__ keys_in, const int32_t *__restrict__ vals_in,
     uint32_t *__restrict__ keys_out, int32_t *__restrict__ vals_out, int64_t n, int shift,
     const uint32_t *__restrict__ hist, uint32_t *lookback, uint32_t *tile_counter, int32_t *status) {
+    constexpr int kTile = kSortThreads * kItems;
     __shared__ uint32_t s_tile;
     __shared__ uint32_t s_wave_cnt[4][256];
     __shared__ uint32_t s_digit_start[256];
     __shared__ uint32_t s_global[256];
     __shared__ uint32_t s_tmp[4];
-    __shared__ uint32_t s_keys[kSortTile];
-    __shared__ int32_t s_vals[kSortTile];
+    __shared__ uint32_t s_keys[kTile];
+    __shared__ int32_t s_vals[kTile];
 
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
     if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
     for (int i = tid; i < 4 * 256; i += kSortThreads) (&s_wave_cnt[0][0])[i] = 0;
     __syncthreads();
     const int64_t tile = s_tile;
-    const int64_t base = tile * kSortTile;
+    const int64_t base = tile * kTile;
 
-    uint32_t key[kSortItems];
-    int32_t val[kSortItems];
-    uint32_t rank[kSortItems];
+    uint32_t key[kItems];
+    int32_t val[kItems];
+    uint32_t rank[kItems];
     const uint64_t lt = lanemask_lt();
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
-        const int64_t idx = base + (static_cast<int64_t>(wave) * kSortItems + j) * kWave + lane;
+    for (int j = 0; j < kItems; ++j) {
+        const int64_t idx = base + (static_cast<int64_t>(wave) * kItems + j) * kWave + lane;
         const bool valid = idx < n;
         key[j] = valid ? keys_in[idx] : 0u;
         val[j] = valid ? (vals_in ? vals_in[idx] : static_cast<int32_t>(idx)) : 0;
@@ -343,8 +353,8 @@ __global__ __launch_bounds__(kSortThreads) void radix_pass_kernel(
 
     // scatter into the tile in digit order (stable), then write out coalesced
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
-        const int64_t idx = base + (static_cast<int64_t>(wave) * kSortItems + j) * kWave + lane;
+    for (int j = 0; j < kItems; ++j) {
+        const int64_t idx = base + (static_cast<int64_t>(wave) * kItems + j) * kWave + lane;
         if (idx < n) {
             const uint32_t dj = (key[j] >> shift) & 0xffu;
             const uint32_t pos = s_digit_start[dj] + s_wave_cnt[wave][dj] + rank[j];
@@ -353,7 +363,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_pass_kernel(
         }
     }
     __syncthreads();
-    const int64_t count = (n - base) < kSortTile ? (n - base) : kSortTile;
+    const int64_t count = (n - base) < kTile ? (n - base) : kTile;
     for (int i = tid; i < count; i += kSortThreads) {
         const uint32_t k = s_keys[i];
         const uint32_t out = s_global[(k >> shift) & 0xffu] + i;
@@ -620,11 +630,18 @@ extern "C" mg_status mg_lbvh_build(const float *verts, int32_t n_verts, const in
     const int32_t *vsrc[4] = {nullptr, vb, va, vb};
     uint32_t *kdst[4] = {kb, ka, kb, codes};
     int32_t *vdst[4] = {vb, va, vb, prim};
+    const int items = sort_items_for(n);
     for (int p = 0; p < 4; ++p) {
-        hipLaunchKernelGGL(radix_pass_kernel, dim3(static_cast<unsigned>(W.tiles)), dim3(kSortThreads), 0, s,
-                           ksrc[p], vsrc[p], kdst[p], vdst[p], n, 8 * p, hist + 256 * p,
-                           lookback + static_cast<int64_t>(p) * 256 * W.tiles, &hdr->tile_counter[p],
-                           &hdr->status);
+        auto pass = [&](auto kernel) {
+            hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(W.tiles)), dim3(kSortThreads), 0, s, ksrc[p],
+                               vsrc[p], kdst[p], vdst[p], n, 8 * p, hist + 256 * p,
+                               lookback + static_cast<int64_t>(p) * 256 * W.tiles, &hdr->tile_counter[p],
+                               &hdr->status);
+        };
+        if (items <= 2) pass(radix_pass_kernel<2>);
+        else if (items <= 4) pass(radix_pass_kernel<4>);
+        else if (items <= 8) pass(radix_pass_kernel<8>);
+        else pass(radix_pass_kernel<16>);
     }
     hipLaunchKernelGGL(hierarchy_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, codes, prim,
                        at<int32_t>(bvh, L.off_inv_prim), n, fz,

@@ -86,14 +86,19 @@ struct Slab {
     float a, b;
 };
 
+// Dot product with explicit fused multiply-adds (the same rounding wherever
+// it is inlined).
+__device__ __forceinline__ float fdot(f3 a, f3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
+
 // Unit direction of a normal sum by the hardware reciprocal square root (any
 // direction gives a valid slab, since the extents are taken along the stored
 // one; |d| is 1 to about 2^-22, which the traversal's bound allows for).
 // Sums too small to normalise safely give no direction.
 __device__ __forceinline__ f3 slab_dir(f3 s) {
-    const float l2 = dot(s, s);
-    if (!(l2 > 1e-30f) || !(l2 < 1e30f)) return f3{0.0f, 0.0f, 0.0f};
-    return __builtin_amdgcn_rsqf(l2) * s;
+    const float l2 = fdot(s, s);
+    const bool ok = l2 > 1e-30f && l2 < 1e30f;
+    const float k = ok ? __builtin_amdgcn_rsqf(l2) : 0.0f;
+    return k * s;
 }
 
 __device__ __forceinline__ float slab_margin(f3 lo, f3 hi) {
@@ -106,57 +111,52 @@ __device__ __forceinline__ void box_range(f3 r, f3 lo, f3 hi, float &mn, float &
     mx = (fmaxf(r.x * lo.x, r.x * hi.x) + fmaxf(r.y * lo.y, r.y * hi.y)) + fmaxf(r.z * lo.z, r.z * hi.z);
 }
 
-__device__ Slab leaf_slab(f3 x, f3 y, f3 z, f3 lo, f3 hi) {
+__device__ __forceinline__ Slab leaf_slab(f3 x, f3 y, f3 z, f3 lo, f3 hi) {
 #pragma clang fp contract(off)
     Slab S;
     S.s = cross(y - x, z - x);
     const f3 d = slab_dir(S.s);
-    if (d.x == 0.0f && d.y == 0.0f && d.z == 0.0f) {
-        S.a = -INFINITY;
-        S.b = INFINITY;
-        return S;
-    }
-    const float px = dot(d, x), py = dot(d, y), pz = dot(d, z);
+    const float px = fdot(d, x), py = fdot(d, y), pz = fdot(d, z);
     const float e = slab_margin(lo, hi);
-    S.a = fminf(fminf(px, py), pz) - e;
-    S.b = fmaxf(fmaxf(px, py), pz) + e;
+    const bool none = d.x == 0.0f && d.y == 0.0f && d.z == 0.0f;
+    S.a = none ? -INFINITY : fminf(fminf(px, py), pz) - e;
+    S.b = none ? INFINITY : fmaxf(fmaxf(px, py), pz) + e;
     return S;
+}
+
+// Bound of d.x over a child (slab c, direction dc) inside the box [lo, hi];
+// a child without a slab contributes the box's own range [ba, bb].
+__device__ __forceinline__ void child_range(f3 d, const Slab &c, f3 dc, f3 lo, f3 hi, float ba, float bb,
+                                            float &ca, float &cb) {
+#pragma clang fp contract(off)
+    const float al = fdot(d, dc);
+    const f3 r = f3{fmaf(-al, dc.x, d.x), fmaf(-al, dc.y, d.y), fmaf(-al, dc.z, d.z)};
+    float rmn, rmx;
+    box_range(r, lo, hi, rmn, rmx);
+    const bool pos = al >= 0.0f;
+    const float lo_c = (pos ? al * c.a : al * c.b) + rmn;
+    const float hi_c = (pos ? al * c.b : al * c.a) + rmx;
+    const bool has = c.a > -INFINITY && c.b < INFINITY && (dc.x != 0.0f || dc.y != 0.0f || dc.z != 0.0f);
+    ca = has ? lo_c : ba;
+    cb = has ? hi_c : bb;
 }
 
 // The slab of a node with box [lo, hi] from its children's (slot order); d is
 // its unit direction.
-__device__ Slab join_slab(const Slab &c0, const Slab &c1, f3 lo, f3 hi, f3 &d) {
+__device__ __forceinline__ Slab join_slab(const Slab &c0, const Slab &c1, f3 lo, f3 hi, f3 &d) {
 #pragma clang fp contract(off)
     Slab P;
     P.s = c0.s + c1.s;
     d = slab_dir(P.s);
-    if (d.x == 0.0f && d.y == 0.0f && d.z == 0.0f) {
-        P.a = -INFINITY;
-        P.b = INFINITY;
-        return P;
-    }
     float a, b;
     box_range(d, lo, hi, a, b);
-    float ca = INFINITY, cb = -INFINITY;
-    const Slab *cs[2] = {&c0, &c1};
-    for (int k = 0; k < 2; ++k) {
-        const Slab &c = *cs[k];
-        const f3 dc = slab_dir(c.s);
-        if (!(c.a > -INFINITY) || !(c.b < INFINITY) || (dc.x == 0.0f && dc.y == 0.0f && dc.z == 0.0f)) {
-            ca = fminf(ca, a);
-            cb = fmaxf(cb, b);
-            continue;
-        }
-        const float al = dot(d, dc);
-        const f3 r = d - al * dc;
-        float rmn, rmx;
-        box_range(r, lo, hi, rmn, rmx);
-        ca = fminf(ca, (al >= 0.0f ? al * c.a : al * c.b) + rmn);
-        cb = fmaxf(cb, (al >= 0.0f ? al * c.b : al * c.a) + rmx);
-    }
+    float a0, b0, a1, b1;
+    child_range(d, c0, slab_dir(c0.s), lo, hi, a, b, a0, b0);
+    child_range(d, c1, slab_dir(c1.s), lo, hi, a, b, a1, b1);
     const float e = slab_margin(lo, hi);
-    P.a = fmaxf(a, ca) - e;
-    P.b = fminf(b, cb) + e;
+    const bool none = d.x == 0.0f && d.y == 0.0f && d.z == 0.0f;
+    P.a = none ? -INFINITY : fmaxf(a, fminf(a0, a1)) - e;
+    P.b = none ? INFINITY : fminf(b, fmaxf(b0, b1)) + e;
     return P;
 }
 
