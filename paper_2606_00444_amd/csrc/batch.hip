@@ -189,24 +189,74 @@ __device__ QueryArgs query_args(const PlanScene &P, int64_t t, const RefitArgs &
 
 static_assert(kBlock == 64 * kBatchWaves, "a query tile is run by the workgroup's kBatchWaves waves");
 
-template <int M>
-__device__ void query_tile(const QueryArgs &q, int64_t q0, int64_t q1, unsigned char *smem) {
-    batch_loop<true, M>(q, q0, static_cast<int64_t>(kBatchWaves) * M, q1, *reinterpret_cast<BatchLds<M> *>(smem));
-}
-
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 constexpr size_t kSmemBytes = cmax(cmax(refit_top_lds(kBatchTopLds), refit_sub_lds(int64_t(1) << kBatchMaxChunkLog2)),
                                    sizeof(BatchLds<16>));
 
-__global__ __launch_bounds__(kBlock) void batch_persistent_kernel(PlanHeader *h) {
-    __shared__ __align__(16) unsigned char smem[kSmemBytes];
-    __shared__ int64_t s_item;
+// The work of each phase is a function of its own (not inlined), so the
+// kernel needs the registers of its largest phase rather than of all of them
+// at once.  Each reads the launch's dynamic LDS (kSmemBytes).
+__device__ __noinline__ void item_refit_sub(PlanHeader *h, int si, int64_t t, int64_t k) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const PlanScene &P = h->scenes[si];
+    refit_subtree<true, kBlock>(refit_args(P, t, h), k, smem);
+    signal(&counters_of(h)[P.sf_base + t], 1u);
+}
+
+__device__ __noinline__ void item_repose(PlanHeader *h, int si, int64_t t, int64_t k) {
+    const PlanScene &P = h->scenes[si];
+    const mg_batch_scene &s = P.s;
+    const int64_t G = s.n_gauss;
+    const float *verts = s.frames + t * 3 * static_cast<int64_t>(s.n_verts);
+    Inputs in{verts, s.n_verts, s.faces, s.n_faces, s.gface, s.bary, s.q_local, s.log_scale, nullptr, G};
+    float *mean = s.mean + t * 3 * G;
+    float *quat = s.quat ? s.quat + t * 4 * G : nullptr;
+    float *cov = s.cov ? s.cov + t * 6 * G : nullptr;
+    const int64_t g0 = k * h->gauss_tile;
+    const int64_t g1 = g0 + h->gauss_tile < G ? g0 + h->gauss_tile : G;
+    for (int64_t g = g0 + threadIdx.x; g < g1; g += kBlock) repose_store(in, g, mean, quat, cov, nullptr);
+}
+
+__device__ __noinline__ void item_refit_top(PlanHeader *h, int si, int64_t t) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const PlanScene &P = h->scenes[si];
+    const int sf = P.sf_base + static_cast<int>(t);
     uint32_t *done_chunks = counters_of(h);
     uint32_t *refit_done = done_chunks + h->total_sf;
+    wait_for(&done_chunks[sf], static_cast<uint32_t>(P.n_chunks), &h->status);
+    const RefitArgs r = refit_args(P, t, h);
+    const int T = *P.n_top;
+    if (T != P.n_top_host) {
+        if (threadIdx.x == 0) atomicOr(&h->status, 2);   // the BVH was rebuilt after planning
+    } else if (T > 0 && T <= kBatchTopLds) {
+        refit_top<true, kBlock, (kBatchTopLds + kBlock - 1) / kBlock>(r, T, reinterpret_cast<uint32_t *>(smem),
+                                                                      kBatchTopLds);
+    } else if (T > kBatchTopLds) {
+        refit_top<true, kBlock, 1>(r, T, r.top_scratch, T);
+    }
+    signal(&refit_done[sf], 1u);
+}
+
+template <int M>
+__device__ __noinline__ void item_query(PlanHeader *h, int si, int64_t t, int64_t k) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const PlanScene &P = h->scenes[si];
+    const int sf = P.sf_base + static_cast<int>(t);
+    wait_for(&counters_of(h)[h->total_sf + sf], 1u, &h->status);
+    const QueryArgs q = query_args(P, t, refit_args(P, t, h), P.seed);
+    const int64_t q0 = k * P.query_tile;
+    const int64_t q1 = q0 + P.query_tile < q.nq ? q0 + P.query_tile : q.nq;
+    batch_loop<true, M>(q, q0, static_cast<int64_t>(kBatchWaves) * M, q1, *reinterpret_cast<BatchLds<M> *>(smem));
+}
+
+// At most 128 registers per lane (four waves per SIMD): with the phases
+// outlined, that costs a few spills in exchange for four times the waves.
+__global__ __launch_bounds__(kBlock, 4) void batch_persistent_kernel(PlanHeader *h) {
+    __shared__ int64_t s_item;
     const int64_t total = h->phase_end[3];
     const int ns = h->n_scenes;
     for (;;) {
-        __syncthreads();                    // smem and s_item of the previous item are free
+        __syncthreads();                    // LDS and s_item of the previous item are free
         if (threadIdx.x == 0) s_item = atomicAdd(&h->queue, 1u);
         __syncthreads();
         const int64_t item = s_item;
@@ -219,44 +269,19 @@ __global__ __launch_bounds__(kBlock) void batch_persistent_kernel(PlanHeader *h)
         const int64_t local = item - P.first[phase];
         const int64_t per = phase == 0 ? P.n_chunks : phase == 1 ? P.g_tiles : phase == 2 ? 1 : P.q_tiles;
         const int64_t t = local / per, k = local % per;
-        const int sf = P.sf_base + static_cast<int>(t);
-        const RefitArgs r = refit_args(P, t, h);
         if (phase == 0) {
-            refit_subtree<true, kBlock>(r, k, smem);
-            signal(&done_chunks[sf], 1u);
+            item_refit_sub(h, si, t, k);
         } else if (phase == 1) {
-            const mg_batch_scene &s = P.s;
-            const int64_t G = s.n_gauss;
-            Inputs in{r.verts, s.n_verts, s.faces, s.n_faces, s.gface, s.bary, s.q_local, s.log_scale, nullptr, G};
-            float *mean = s.mean + t * 3 * G;
-            float *quat = s.quat ? s.quat + t * 4 * G : nullptr;
-            float *cov = s.cov ? s.cov + t * 6 * G : nullptr;
-            const int64_t g0 = k * h->gauss_tile;
-            const int64_t g1 = g0 + h->gauss_tile < G ? g0 + h->gauss_tile : G;
-            for (int64_t g = g0 + threadIdx.x; g < g1; g += kBlock) repose_store(in, g, mean, quat, cov, nullptr);
+            item_repose(h, si, t, k);
         } else if (phase == 2) {
-            wait_for(&done_chunks[sf], static_cast<uint32_t>(P.n_chunks), &h->status);
-            const int T = *P.n_top;
-            if (T != P.n_top_host) {
-                if (threadIdx.x == 0) atomicOr(&h->status, 2);   // the BVH was rebuilt after planning
-            } else if (T > 0 && T <= kBatchTopLds) {
-                refit_top<true, kBlock, (kBatchTopLds + kBlock - 1) / kBlock>(r, T, reinterpret_cast<uint32_t *>(smem),
-                                                                              kBatchTopLds);
-            } else if (T > kBatchTopLds) {
-                refit_top<true, kBlock, 1>(r, T, r.top_scratch, T);
-            }
-            signal(&refit_done[sf], 1u);
+            item_refit_top(h, si, t);
         } else {
-            wait_for(&refit_done[sf], 1u, &h->status);
-            const QueryArgs q = query_args(P, t, r, P.seed);
-            const int64_t q0 = k * P.query_tile;
-            const int64_t q1 = q0 + P.query_tile < q.nq ? q0 + P.query_tile : q.nq;
             switch (P.batch) {
-                case 1: query_tile<1>(q, q0, q1, smem); break;
-                case 2: query_tile<2>(q, q0, q1, smem); break;
-                case 8: query_tile<8>(q, q0, q1, smem); break;
-                case 16: query_tile<16>(q, q0, q1, smem); break;
-                default: query_tile<4>(q, q0, q1, smem); break;
+                case 1: item_query<1>(h, si, t, k); break;
+                case 2: item_query<2>(h, si, t, k); break;
+                case 8: item_query<8>(h, si, t, k); break;
+                case 16: item_query<16>(h, si, t, k); break;
+                default: item_query<4>(h, si, t, k); break;
             }
         }
     }
@@ -401,7 +426,7 @@ extern "C" mg_status mg_batch_run(void *plan, size_t plan_bytes, void *stream) {
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     hipLaunchKernelGGL(batch_reset_kernel, dim3(8), dim3(256), 0, s, h);
     // persistent workgroups: 4 per compute unit (the kernel stops when the queue is empty)
-    hipLaunchKernelGGL(batch_persistent_kernel, dim3(4 * cus), dim3(kBlock), 0, s, h);
+    hipLaunchKernelGGL(batch_persistent_kernel, dim3(4 * cus), dim3(kBlock), kSmemBytes, s, h);
     return launch_status();
 }
 
