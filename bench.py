@@ -58,6 +58,13 @@ WORKLOADS = {
 }
 METRIC = "frames/s and closest-point queries/s, refit vs rebuild; achieved HBM GB/s"
 # (timed steps, warm-up steps) per workload: each default run times about a second of GPU work
+# Algorithmic float32 operations of the closest-point traversal per counted unit:
+# a node expansion bounds its two internal children (box distance 17 and
+# normal-slab distance 12 each, plus the query's slab margin 6), a leaf bound
+# test takes the triangle's bounds and their box distance (29), an exact test
+# is the closest point on a triangle (80).
+OPS_EXPANSION, OPS_LEAF_BOUND, OPS_EXACT = 64.0, 29.0, 80.0
+
 DEFAULT_STEPS = {"c1": (60, 10), "c2": (200, 10), "c3": (10, 2), "c4": (200, 10), "c5": (20, 3), "track": (199, 0), "sdf": (200, 10), "contact": (200, 10)}
 
 
@@ -243,7 +250,7 @@ def run_contact(args):
     mg.closest_point_query(bvh, live, xs, normal=True, out=rec, counters=cnt)
     torch.cuda.synchronize()
     n_exp, n_lbox, n_lex, n_q = (int(x) for x in cnt.cpu())
-    ops = 34.0 * n_exp + 29.0 * n_lbox + 80.0 * n_lex
+    ops = OPS_EXPANSION * n_exp + OPS_LEAF_BOUND * n_lbox + OPS_EXACT * n_lex
     achieved = ops / (ph["closest"] * 1e-3) / 1e12
     out = {
         "metric": METRIC, "value": round(1000.0 / ms_per_step, 2), "unit": "frames/s", "n_gpus": 1,
@@ -433,7 +440,7 @@ def run_track(args):
         mg.closest_point_query(bvh, tv, out[0], out=rec, counters=cnt)
     torch.cuda.synchronize()
     n_exp, n_lbox, n_lex, n_q = (int(x) for x in cnt.cpu())
-    ops = 34.0 * n_exp + 29.0 * n_lbox + 80.0 * n_lex
+    ops = OPS_EXPANSION * n_exp + OPS_LEAF_BOUND * n_lbox + OPS_EXACT * n_lex
     if ph["query"] >= ph["rebuild"]:
         achieved = ops / (ph["query"] * 1e-3) / 1e12
         kname = "knn_lane_kernel" if args.knn > 1 else "traverse_batch_kernel"
@@ -672,7 +679,7 @@ def run_refine(args):
     mg.closest_point_query(r.bvh, r.V, Y, out=r.rec, counters=cnt, **r.query)
     torch.cuda.synchronize()
     n_exp, n_lbox, n_lex, n_q = (int(x) for x in cnt.cpu())
-    ops = 34.0 * n_exp + 29.0 * n_lbox + 80.0 * n_lex
+    ops = OPS_EXPANSION * n_exp + OPS_LEAF_BOUND * n_lbox + OPS_EXACT * n_lex
     achieved = ops / (ph["closest"] * 1e-3) / 1e12
     out = {
         "metric": METRIC, "value": round(1000.0 / ms_per_step, 2), "unit": "Adam steps/s", "n_gpus": 1,
@@ -739,8 +746,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=None,
                     help="queries the oracle baseline runs per query set (default: c1/c2/c5 8000, c3 all)")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of a HIP graph")
-    ap.add_argument("--streams", type=int, choices=(1, 2), default=2,
-                    help="c1/c2/c5: run the rebuild comparison path on a second stream (2) or serially (1)")
+    ap.add_argument("--streams", type=int, choices=(1, 2, 3), default=3,
+                    help="c1/c2/c5: run the rebuild comparison path on a second stream (2), also the projection "
+                         "onto the rebuilt target on a third (3), or everything serially (1)")
     ap.add_argument("--phase", choices=["copy", "update", "refit", "collide", "rebuild", "target_queries"],
                     help="profiling aid (c1/c2/c5): run only this phase --reps times, eagerly, and exit")
     ap.add_argument("--reps", type=int, default=60)
@@ -847,15 +855,24 @@ def main():
     def phase_rebuild(j):
         mg.lbvh_build(tgt_v[j], tgt_f[j], bvh=tbvh[j])
 
-    def phase_target_queries(j):
+    def phase_collide_target(j):
         mg.closest_point_query(tbvh[j], tgt_v[j], particles, normal=True, out=col_t, **o_ct)
+
+    def phase_project(j):
         mg.closest_point_query(tbvh[j], tgt_v[j], V0, out=proj, **o_pr)
 
+    def phase_target_queries(j):
+        phase_collide_target(j)
+        phase_project(j)
+
     # The refit path (template) and the rebuild comparison path (varying target) share
-    # no data: with --streams 2 the rebuild path runs on a second HIP stream (default
+    # no data: with --streams 2 or 3 the rebuild path runs on a second HIP stream (default
     # priority), forked from and joined back into the launch stream every step, so each
-    # path's kernels can use compute units the other leaves idle.
-    side = torch.cuda.Stream() if args.streams == 2 else None
+    # path's kernels can use compute units the other leaves idle.  With --streams 3 the
+    # two query sets against the rebuilt target (particles, template vertices) also run
+    # side by side, the projection on a third stream forked after the rebuild.
+    side = torch.cuda.Stream() if args.streams >= 2 else None
+    side2 = torch.cuda.Stream() if args.streams == 3 else None
     def frame_update(k):
         """The frame update: copy frame k, re-pose the Gaussians, refit.  (Running the
         re-pose beside the refit on another stream was measured slower: the fork and
@@ -878,10 +895,18 @@ def main():
         side.wait_stream(main)
         with torch.cuda.stream(side):
             phase_rebuild(j)
-            phase_target_queries(j)
+            if side2 is not None:
+                side2.wait_stream(side)
+                with torch.cuda.stream(side2):
+                    phase_project(j)
+                phase_collide_target(j)
+            else:
+                phase_target_queries(j)
         frame_update(k)
         phase_collide()
         main.wait_stream(side)
+        if side2 is not None:
+            main.wait_stream(side2)
 
     if args.phase:
         # profiling aid: one phase alone, eagerly, so per-dispatch counters see only it
@@ -1000,9 +1025,7 @@ def main():
     n_q //= len(frames_c)
     trav = {"node_expansions_per_query": round(n_exp / n_q, 1), "leaf_bound_tests_per_query": round(n_lbox / n_q, 1),
             "exact_leaf_tests_per_query": round(n_lex / n_q, 1)}
-    # algorithmic float32 operations per unit: expansion = two child box
-    # distances (34), leaf bound = triangle bounds + box distance (29), exact test (80)
-    coll_ops = 34.0 * n_exp + 29.0 * n_lbox + 80.0 * n_lex
+    coll_ops = OPS_EXPANSION * n_exp + OPS_LEAF_BOUND * n_lbox + OPS_EXACT * n_lex
     single = {k: ph[k] for k in ("gaussian_update", "refit", "collide")}   # the kernels of one phase
     dom = max(single, key=single.get)
     if dom == "collide":
