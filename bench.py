@@ -18,7 +18,7 @@ over all scenes x frames, against the plain per-frame path on the same GPU),
 and c4 the differentiable form (one step = one Adam step of the template
 projection loss, forward + backward + update).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3|c4|c5]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c4|c5|track|sdf|contact]
 Prints one JSON line.
 """
 
@@ -38,8 +38,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+# The small configuration (icosphere, 5,120 faces, no varying-topology target) is a
+# parity-test case (tests/), not a bench line.
 WORKLOADS = {
-    "c1": (1, "icosphere 2,562 V / 5,120 F, 30,720 Gaussians, 10,000 queries, 60 frames"),
     "c2": (2, "UV-sphere template 20,002 V / 40,000 F, 100,000 Gaussians, 50,000 particles, "
               "200 frames, marching-tetrahedra targets ~46-53k F"),
     "c3": (3, "batched: 6 UV-sphere scenes of 5k/10k/20k/30k/40k/50k F, 20k-300k Gaussians, "
@@ -65,7 +66,7 @@ METRIC = "frames/s and closest-point queries/s, refit vs rebuild; achieved HBM G
 # is the closest point on a triangle (80).
 OPS_EXPANSION, OPS_LEAF_BOUND, OPS_EXACT = 64.0, 29.0, 80.0
 
-DEFAULT_STEPS = {"c1": (60, 10), "c2": (200, 10), "c3": (10, 2), "c4": (200, 10), "c5": (20, 3), "track": (199, 0), "sdf": (200, 10), "contact": (200, 10)}
+DEFAULT_STEPS = {"c2": (200, 10), "c3": (10, 2), "c4": (200, 10), "c5": (20, 3), "track": (199, 0), "sdf": (200, 10), "contact": (200, 10)}
 
 
 def _target_job(args):
@@ -744,13 +745,13 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=None,
-                    help="queries the oracle baseline runs per query set (default: c1/c2/c5 8000, c3 all)")
+                    help="queries the oracle baseline runs per query set (default: c2/c5 8000, c3 all)")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of a HIP graph")
     ap.add_argument("--streams", type=int, choices=(1, 2, 3), default=3,
-                    help="c1/c2/c5: run the rebuild comparison path on a second stream (2), also the projection "
+                    help="c2/c5: run the rebuild comparison path on a second stream (2), also the projection "
                          "onto the rebuilt target on a third (3), or everything serially (1)")
     ap.add_argument("--phase", choices=["copy", "update", "refit", "collide", "rebuild", "target_queries"],
-                    help="profiling aid (c1/c2/c5): run only this phase --reps times, eagerly, and exit")
+                    help="profiling aid (c2/c5): run only this phase --reps times, eagerly, and exit")
     ap.add_argument("--reps", type=int, default=60)
     ap.add_argument("--knn", type=int, default=1, help="track: NearestSurface with the k nearest faces (1-8)")
     ap.add_argument("--copy-calibration", type=int, metavar="MB", default=0,
@@ -759,7 +760,7 @@ def main():
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration, args.reps)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     steps, warmup = DEFAULT_STEPS[args.workload]
     args.steps = steps if args.steps is None else args.steps

@@ -250,9 +250,10 @@ mg_status mg_lbvh_refit(const float *verts, int32_t n_verts, void *bvh, size_t b
  *   MG_QUERY_BATCH  one wave per `batch` queries (1, 2, 4, 8, 16 or 32) sharing
  *                   an LDS work stack, up to 64 node expansions per step; suits
  *                   few queries or queries with many near-equidistant faces
- *   MG_QUERY_AUTO   BATCH with batch 4 and seed on
- * batch == 0 means 4.  NULL options also turn the seed on; with options given,
- * seed is as set.  seed != 0 (BATCH only): each query first descends
+ *   MG_QUERY_AUTO   BATCH with the default batch and seed on
+ * batch == 0 means the default: the largest of 16, 8, 4, 2, 1 with
+ * n_queries >= 2048 batch (at least 512 workgroups of four waves).  NULL
+ * options also turn the seed on; with options given, seed is as set.  seed != 0 (BATCH only): each query first descends
  * greedily (nearer child first) to one leaf to start from a tight bound before
  * the wide expansion.  order (device int32 [n_queries] permutation, or NULL):
  * queries are processed in the order order[0], order[1], ... - e.g. the prim

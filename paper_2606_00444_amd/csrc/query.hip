@@ -282,15 +282,20 @@ inline const T *cat(const void *base, int64_t off) {
     return reinterpret_cast<const T *>(static_cast<const char *>(base) + off);
 }
 
-// Default traversal when the caller gives no options: batches of 4 queries per
-// wave with a greedy seed descent (the best or close to it on every workload
-// measured; the autotuner refines per workload).
+// Default traversal when the caller gives no options: the batch kernel with a
+// greedy seed descent and the largest batch (16, 8, 4, 2 or 1 queries per wave)
+// that leaves at least 512 workgroups of four waves (the autotuner's choice on
+// the workloads measured; it refines per workload).
 inline void resolve(const mg_query_options *o, int64_t nq, int &kernel, int &batch, int &seed) {
     kernel = o ? o->kernel : MG_QUERY_AUTO;
     batch = o ? o->batch : 0;
     seed = o ? (o->seed != 0) : 1;
     if (kernel == MG_QUERY_AUTO) kernel = MG_QUERY_BATCH;
-    if (batch <= 0) batch = 4;
+    if (batch <= 0) {
+        // the largest batch that still gives at least 512 workgroups (two per CU)
+        batch = 16;
+        while (batch > 1 && nq < static_cast<int64_t>(2048) * batch) batch >>= 1;
+    }
 }
 
 __global__ void zero_word_kernel(uint32_t *w) { *w = 0u; }
