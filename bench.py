@@ -663,7 +663,7 @@ def run_refine(args):
         "repose_mean": graph_ms(lambda _: mg.mesh_gaussian_update(r.V, F, b["face"], b["bary"], b["q_local"],
                                                                   b["log_scale"], out={"mean": r.mu}, quat=False,
                                                                   cov=False), reps, torch),
-        "build_mu": graph_ms(lambda _: mg.lbvh_build(r.mu, None, bvh=r.bvh_mu), reps, torch),
+        "refit_mu": graph_ms(lambda _: mg.lbvh_refit(r.bvh_mu, r.mu), reps, torch),
         "chamfer": graph_ms(lambda _: mg.chamfer(r.mu, r.bvh_mu, Y, r.bvh_y, out=dict(r.ch), **r.nn_query),
                             reps, torch),
         "backward": graph_ms(lambda _: (mg.point_mesh_backward(r.V, F, Y, r.rec, 1.0 / r.ny, r.gV),

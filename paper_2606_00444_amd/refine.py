@@ -9,7 +9,9 @@ definitions) and its gradient with the library's kernels, then applies Adam
   3. closest point on (V, F) of every target              (mg_closest_point_query)
   4. P = mean squared distance                            (mg_mean)
   5. re-pose the Gaussian means mu(V)                     (mg_mesh_gaussian_update)
-  6. point LBVH over mu, both nearest-neighbour maps, CD  (mg_lbvh_build, mg_chamfer)
+  6. refit the point LBVH over mu (built once from mu(V0):
+     the means move little per step and nearest points stay
+     exact on any tree), both nearest-neighbour maps, CD   (mg_lbvh_refit, mg_chamfer)
   7. dP/dV, dCD/dmu, and dCD/dV through the binding       (mg_point_mesh_backward,
                                                            mg_chamfer_backward,
                                                            mg_mesh_gaussian_update_backward)
@@ -25,7 +27,6 @@ import math
 import torch
 
 from . import api
-from ._lib import MG_PRIM_POINTS
 
 
 class TemplateRefiner:
@@ -60,7 +61,9 @@ class TemplateRefiner:
         self.max_steps = max_steps
         self.bvh = api.lbvh_build(verts0, faces)
         self.bvh_y = api.lbvh_build(targets, None)
-        self.bvh_mu = api.LBVH(G, MG_PRIM_POINTS, dev)
+        mu0 = api.mesh_gaussian_update(verts0, faces, binding["face"], binding["bary"], binding["q_local"],
+                                       binding["log_scale"], binding.get("offset"), quat=False, cov=False)["mean"]
+        self.bvh_mu = api.lbvh_build(mu0, None)
         if lr is None:
             ext = (verts0.max(dim=1).values - verts0.min(dim=1).values).double()
             lr = 1e-3 * math.sqrt(float((ext * ext).sum()))
@@ -88,7 +91,7 @@ class TemplateRefiner:
         api.mean(self.rec["dist2"], out=row[0:1])
         api.mesh_gaussian_update(self.V, self.faces, b["face"], b["bary"], b["q_local"], b["log_scale"],
                                  b.get("offset"), out={"mean": self.mu}, quat=False, cov=False)
-        api.lbvh_build(self.mu, None, bvh=self.bvh_mu)
+        api.lbvh_refit(self.bvh_mu, self.mu)
         api.chamfer(self.mu, self.bvh_mu, self.targets, self.bvh_y, out=dict(self.ch, means=row[1:3]),
                     **self.nn_query)
         if self.ny:
