@@ -229,26 +229,43 @@ __device__ void refit_subtree(const RefitArgs &a, int64_t k, unsigned char *smem
         if (threadIdx.x == 0) atomicOr(a.status, 4);
         return;
     }
+    // A leaf's primitive, parent tag and vertices.  The first leaf of every
+    // thread is loaded before the LDS set-up and its barrier, so the two rounds
+    // of global loads overlap.
+    struct Leaf {
+        f3 x, y, z;
+        int32_t id, tag;
+    };
+    auto load_leaf = [&](int64_t i) {
+        Leaf L;
+        L.id = a.prim[i];
+        L.tag = a.leaf_parent[i];
+        if (kTri) {
+            L.x = load3(a.verts, a.nv, a.leaf_faces[i]);
+            L.y = load3(a.verts, a.nv, a.leaf_faces[a.n + i]);
+            L.z = load3(a.verts, a.nv, a.leaf_faces[2 * a.n + i]);
+        } else {
+            L.x = L.y = L.z = load3(a.verts, a.nv, L.id);
+        }
+        return L;
+    };
+    const int64_t i0 = f + threadIdx.x;
+    Leaf first{};
+    if (i0 <= l) first = load_leaf(i0);
     for (int64_t j = threadIdx.x; j < size; j += kThreads) {
         s_cnt[j] = 0;
         lds_empty(s_box, C, j);
         s_par[j] = f + j < a.n - 1 ? a.node_parent[f + j] : -1;
     }
     __syncthreads();
-    for (int64_t i = f + threadIdx.x; i <= l; i += kThreads) {
-        const int32_t id = a.prim[i];
-        f3 x, y, z;
-        if (kTri) {
-            x = load3(a.verts, a.nv, a.leaf_faces[i]);
-            y = load3(a.verts, a.nv, a.leaf_faces[a.n + i]);
-            z = load3(a.verts, a.nv, a.leaf_faces[2 * a.n + i]);
-        } else {
-            x = y = z = load3(a.verts, a.nv, id);
-        }
+    for (int64_t i = i0; i <= l; i += kThreads) {
+        const Leaf L = i == i0 ? first : load_leaf(i);
+        const int32_t id = L.id;
+        const f3 x = L.x, y = L.y, z = L.z;
         f3 lo = fmin3(fmin3(x, y), z), hi = fmax3(fmax3(x, y), z);
         Slab S{f3{0.0f, 0.0f, 0.0f}, -INFINITY, INFINITY};
         if (kTri) S = leaf_slab(x, y, z, lo, hi);
-        const int32_t tag = a.leaf_parent[i];
+        const int32_t tag = L.tag;
         if (tag < 0) {            // a single leaf is the root
             write_root(a.root, lo, hi);
             continue;
