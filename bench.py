@@ -243,12 +243,16 @@ def run_contact(args):
     xs = S.x.clone()
     vs = S.v.clone()
     rec = S.rec
+    # the next step's query would start from the last step's faces (a copy here,
+    # so that the timed launches do not feed each other)
+    hint = rec["face"].clone()
     ph = {"refit": graph_ms(lambda _: mg.lbvh_refit(bvh, live), 50, torch),
-          "closest": graph_ms(lambda _: mg.closest_point_query(bvh, live, xs, normal=True, out=rec), 20, torch)}
+          "closest": graph_ms(lambda _: mg.closest_point_query(bvh, live, xs, normal=True, out=rec, hint=hint), 20,
+                              torch)}
     S.x.copy_(xs)
     S.v.copy_(vs)
     cnt = torch.zeros(4, dtype=torch.int64, device=dev)
-    mg.closest_point_query(bvh, live, xs, normal=True, out=rec, counters=cnt)
+    mg.closest_point_query(bvh, live, xs, normal=True, out=rec, counters=cnt, hint=hint)
     torch.cuda.synchronize()
     n_exp, n_lbox, n_lex, n_q = (int(x) for x in cnt.cpu())
     ops = OPS_EXPANSION * n_exp + OPS_LEAF_BOUND * n_lbox + OPS_EXACT * n_lex
@@ -814,6 +818,7 @@ def main():
                 "normal": torch.empty(3, n, device=dev) if normal else None}
 
     col = qout(Q, True)
+    col["face"].fill_(-1)                                   # no previous frame yet: no hints
     col_t = qout(Q, True)
     proj = qout(NV, False)
     tgt_v = [D(v) for v, _ in targets_np]
@@ -850,8 +855,11 @@ def main():
     def phase_refit():
         mg.lbvh_refit(bvh, live)
 
-    def phase_collide(counters=None):
-        mg.closest_point_query(bvh, live, particles, normal=True, out=col, counters=counters, **o_col)
+    def phase_collide(counters=None, hint=None):
+        # each particle starts from its face of the previous frame (the step's own
+        # output array, which the call overwrites), unless a hint array is given
+        mg.closest_point_query(bvh, live, particles, normal=True, out=col, counters=counters,
+                               hint=col["face"] if hint is None else hint, **o_col)
 
     def phase_rebuild(j):
         mg.lbvh_build(tgt_v[j], tgt_f[j], bvh=tbvh[j])
@@ -909,14 +917,28 @@ def main():
         if side2 is not None:
             main.wait_stream(side2)
 
+    # A collision launch timed alone starts from the previous frame's answers, as
+    # in the step (a copy, so that repeated launches do not feed each other).
+    def prev_hints(f):
+        phase_copy(max(f - 1, 0))
+        phase_refit()
+        phase_collide(hint=none_hint)
+        h = col["face"].clone()
+        phase_copy(f)
+        phase_refit()
+        return h
+
+    none_hint = torch.full((Q,), -1, dtype=torch.int32, device=dev)
+
     if args.phase:
         # profiling aid: one phase alone, eagerly, so per-dispatch counters see only it
         frames_c = sample_frames(T)
+        hints_c = [prev_hints(f) for f in frames_c] if args.phase == "collide" else None
 
         def collide_at(r):             # one collision launch per sampled frame, cyclically
             phase_copy(frames_c[r % len(frames_c)])
             phase_refit()
-            phase_collide()
+            phase_collide(hint=hints_c[r % len(frames_c)])
 
         phases = {"copy": lambda r: phase_copy(r % T), "update": lambda r: phase_update(),
                   "refit": lambda r: phase_refit(), "collide": collide_at,
@@ -986,9 +1008,8 @@ def main():
     # spread across the sequence (the same frames a --phase collide run cycles through)
     per_frame = []
     for f in sample_frames(T):
-        phase_copy(f)
-        phase_refit()
-        per_frame.append(timed(lambda r: phase_collide(), max(10, reps // 6)))
+        h = prev_hints(f)
+        per_frame.append(timed(lambda r: phase_collide(hint=h), max(10, reps // 6)))
     ph["collide"] = float(np.mean(per_frame))
     # the target BVHs share one buffer: time their queries on one freshly built target
     phase_rebuild(0)
@@ -1017,9 +1038,8 @@ def main():
     cnt = torch.zeros(4, dtype=torch.int64, device=dev)
     frames_c = sample_frames(T)
     for f in frames_c:
-        phase_copy(f)
-        phase_refit()
-        phase_collide(cnt)
+        h = prev_hints(f)
+        phase_collide(cnt, hint=h)
     torch.cuda.synchronize()
     n_exp, n_lbox, n_lex, n_q = (int(x) for x in cnt.cpu())
     n_exp, n_lbox, n_lex = (x / len(frames_c) for x in (n_exp, n_lbox, n_lex))   # per launch

@@ -264,8 +264,14 @@ mg_status mg_lbvh_refit(const float *verts, int32_t n_verts, void *bvh, size_t b
  * waves stay resident and take query batches one at a time from this counter,
  * which the call zeroes on its stream before the traversal (no initial value
  * needed); calls that may overlap in time must use different words.  Without a
- * queue, batches are dealt to the waves statically.  Results do not depend on
- * these choices except among exact ties, which all pick the lowest original id. */
+ * queue, batches are dealt to the waves statically.  hint (device int32
+ * [n_queries], or NULL): an original primitive id per query (-1 or out of range:
+ * none), e.g. the previous frame's result; each query starts from that
+ * primitive's distance instead of the seed descent, which makes frame-to-frame
+ * queries on a slowly moving mesh cheap.  hint may be the output id array of
+ * the same call (a query reads its hint before writing its result).  Results
+ * do not depend on any of these choices except among exact ties, which all
+ * pick the lowest original id. */
 #define MG_QUERY_AUTO  0
 #define MG_QUERY_LANE  1
 #define MG_QUERY_BATCH 2
@@ -278,7 +284,7 @@ typedef struct mg_query_options {
     const int32_t *order;
     uint64_t *counters;
     uint32_t *queue;
-    int64_t reserved;
+    const int32_t *hint;
 } mg_query_options;
 
 /* ------------------------------------------------------------------------

@@ -206,13 +206,14 @@ def lbvh_refit(bvh, verts):
     return bvh
 
 
-def _opts(kernel, batch, seed=False, order=None, counters=None, queue=None):
+def _opts(kernel, batch, seed=False, order=None, counters=None, queue=None, hint=None):
     """ctypes options for the traversal ("auto" | "lane" | "batch"); None when automatic.
 
     queue: a device int32 [1] work counter for the batch kernel's dynamic
-    batch assignment (zeroed by the call itself), or None for static."""
+    batch assignment (zeroed by the call itself), or None for static.
+    hint: device int32 [Q] original ids to start the queries from, or None."""
     auto = kernel in (None, "auto") and not batch and not seed and order is None and counters is None
-    if auto and queue is None:
+    if auto and queue is None and hint is None:
         return None
     k = {"auto": MG_QUERY_AUTO, None: MG_QUERY_AUTO, "lane": MG_QUERY_LANE, "batch": MG_QUERY_BATCH}[kernel]
     o = QueryOptions()
@@ -223,6 +224,10 @@ def _opts(kernel, batch, seed=False, order=None, counters=None, queue=None):
         if queue.dtype != torch.int32 or queue.numel() < 1:
             raise TypeError("queue must be int32 [1]")
         o.queue = _ptr(queue)
+    if hint is not None:
+        if hint.dtype != torch.int32 or not hint.is_contiguous():
+            raise TypeError("hint must be a contiguous int32 tensor")
+        o.hint = _ptr(hint)
     if order is not None:
         if order.dtype != torch.int32:
             raise TypeError("order must be int32")
@@ -247,6 +252,13 @@ def _queue(dynamic, device):
     return torch.empty(1, dtype=torch.int32, device=device) if dynamic else None
 
 
+def _hint(hint, nq):
+    """A hint array checked for length (None passes through)."""
+    if hint is not None and hint.numel() < nq:
+        raise ValueError(f"hint has {hint.numel()} entries for {nq} queries")
+    return hint
+
+
 def _query_out(nq, device, point, bary, dist2, normal):
     return {
         "face": torch.empty(nq, dtype=torch.int32, device=device),
@@ -259,13 +271,14 @@ def _query_out(nq, device, point, bary, dist2, normal):
 
 def closest_point_query(bvh, verts, queries, max_dist2=math.inf, *, point=True, bary=True, dist2=True,
                         normal=False, out=None, kernel=None, batch=0, seed=False, dynamic=False, order=None,
-                        counters=None):
+                        counters=None, hint=None):
     """Closest point on the mesh of a triangle LBVH for every query [3][Q].
 
     kernel: None/"auto", "lane" or "batch" (batch = queries per wave), dynamic:
-    batches taken from a work counter instead of dealt statically - see
-    mg_query_options.  out: a dict of output tensors to fill (face, and point, bary, dist2, normal
-    or None each).
+    batches taken from a work counter instead of dealt statically; hint: int32
+    [Q] face ids to start from (e.g. the previous frame's out["face"], which may
+    be the very array this call overwrites) - see mg_query_options.  out: a dict
+    of output tensors to fill (face, and point, bary, dist2, normal or None each).
     """
     if bvh.kind != MG_PRIM_TRIANGLES:
         raise ValueError("closest_point_query needs a triangle BVH")
@@ -274,7 +287,7 @@ def closest_point_query(bvh, verts, queries, max_dist2=math.inf, *, point=True, 
     _call("mg_closest_point_query", _ptr(bvh.buf), bvh.nbytes, bvh.n, _ptr(verts), verts.shape[1],
           _ptr(queries), nq, float(max_dist2), _ptr(o["face"]), _ptr(o.get("point")), _ptr(o.get("bary")),
           _ptr(o.get("dist2")), _ptr(o.get("normal")),
-          _opts(kernel, batch, seed, order, counters, _queue(dynamic, queries.device)), _stream())
+          _opts(kernel, batch, seed, order, counters, _queue(dynamic, queries.device), _hint(hint, nq)), _stream())
     return o
 
 
@@ -305,7 +318,7 @@ def knn_surface_query(bvh, verts, queries, k=4, eps=0.0, max_dist2=math.inf, *, 
 
 
 def nearest_point_query(bvh, points, queries, max_dist2=math.inf, *, kernel=None, batch=0, seed=False,
-                        dynamic=False, order=None, counters=None):
+                        dynamic=False, order=None, counters=None, hint=None):
     """(index [Q] int32, dist2 [Q]) of the nearest point of a point LBVH."""
     if bvh.kind != MG_PRIM_POINTS:
         raise ValueError("nearest_point_query needs a point BVH")
@@ -314,7 +327,7 @@ def nearest_point_query(bvh, points, queries, max_dist2=math.inf, *, kernel=None
     d2 = torch.empty(nq, device=queries.device)
     _call("mg_nearest_point_query", _ptr(bvh.buf), bvh.nbytes, bvh.n, _ptr(points), _ptr(queries), nq,
           float(max_dist2), _ptr(idx), _ptr(d2),
-          _opts(kernel, batch, seed, order, counters, _queue(dynamic, queries.device)), _stream())
+          _opts(kernel, batch, seed, order, counters, _queue(dynamic, queries.device), _hint(hint, nq)), _stream())
     return idx, d2
 
 

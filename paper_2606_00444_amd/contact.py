@@ -21,14 +21,16 @@ class Spheres:
         self.radius, self.restitution, self.gravity = float(radius), float(restitution), tuple(map(float, gravity))
         n = x.shape[1]
         self.rec = api._query_out(n, x.device, True, False, False, True)
+        self.rec["face"].fill_(-1)              # no previous step: no hints
         self.contact = torch.empty(n, dtype=torch.int32, device=x.device)
         self.query = dict(query or {})
 
     def step(self, bvh, verts, dt):
-        """One step against the mesh of bvh (refit to verts by the caller)."""
+        """One step against the mesh of bvh (refit to verts by the caller).  Each
+        sphere's closest-point query starts from its face of the previous step."""
         n = self.x.shape[1]
         _call("mg_particles_integrate", _ptr(self.x), _ptr(self.v), n, *self.gravity, float(dt), _stream())
-        api.closest_point_query(bvh, verts, self.x, normal=True, out=self.rec, **self.query)
+        api.closest_point_query(bvh, verts, self.x, normal=True, out=self.rec, hint=self.rec["face"], **self.query)
         _call("mg_contact_response", _ptr(self.x), _ptr(self.v), n, _ptr(self.rec["point"]),
               _ptr(self.rec["normal"]), _ptr(self.rec["face"]), self.radius, self.restitution, _ptr(self.contact),
               _stream())

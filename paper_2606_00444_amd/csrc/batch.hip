@@ -184,6 +184,7 @@ __device__ QueryArgs query_args(const PlanScene &P, int64_t t, const RefitArgs &
     a.order = nullptr;
     a.counters = nullptr;
     a.queue = nullptr;
+    a.hint = nullptr;
     return a;
 }
 

@@ -44,6 +44,14 @@ __global__ __launch_bounds__(kLaneBlock) void traverse_lane_kernel(QueryArgs a) 
     float best = a.maxd2;
     int32_t best_id = INT_MAX, best_leaf = -1;
     unsigned long long n_exp = 0, n_lbox = 0, n_lex = 0;
+    {
+        const unsigned long long h = hint_best<kTri>(a, q, p, pack_best(a.maxd2, INT_MAX));
+        if (h != pack_best(a.maxd2, INT_MAX)) {
+            best = __uint_as_float(static_cast<uint32_t>(h >> 32));
+            best_id = static_cast<int32_t>(h & 0xffffffffull);
+            best_leaf = a.inv_prim[best_id];
+        }
+    }
 
     auto consider = [&](float d2, int32_t id, int32_t leaf) {
         ++n_lex;
@@ -329,6 +337,7 @@ mg_status launch_traverse(QueryArgs a, const mg_query_options *opts, hipStream_t
     a.order = opts ? opts->order : nullptr;
     a.counters = opts ? reinterpret_cast<unsigned long long *>(opts->counters) : nullptr;
     a.queue = opts ? opts->queue : nullptr;
+    a.hint = opts ? opts->hint : nullptr;
     if (kernel == MG_QUERY_LANE) {
         hipLaunchKernelGGL(traverse_lane_kernel<kTri>, dim3(blocks_for(a.nq, kLaneBlock)), dim3(kLaneBlock), 0, s, a);
         return launch_status();

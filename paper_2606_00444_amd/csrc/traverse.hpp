@@ -41,6 +41,7 @@ struct QueryArgs {
     const int32_t *inv_prim;            // [n] leaf of each original id (id -> position in leaf order)
     int32_t *status;                    // error word of the BVH header
     uint32_t *queue;                    // batch kernel: dynamic batch counter (zeroed before launch) or nullptr
+    const int32_t *hint;                // [nq] original id to start each query from, or nullptr
 };
 
 // Query processed in position i (order[i], or i); -1 if the order entry is out of range.
@@ -147,6 +148,32 @@ __device__ void write_result_id(const QueryArgs &a, int64_t q, f3 p, int32_t id,
         if (leaf < 0 || leaf >= a.n) { atomicOr(a.status, 16); leaf = -1; }
     }
     write_result<kTri>(a, q, p, leaf, id, d2);
+}
+
+// Squared distance from p to primitive `id` (original numbering) through its
+// leaf; +inf if id or its leaf is out of range.
+template <bool kTri>
+__device__ __forceinline__ float prim_dist2(const QueryArgs &a, f3 p, int32_t id) {
+    if (id < 0 || id >= a.n) return INFINITY;
+    const int32_t leaf = a.inv_prim[id];
+    if (leaf < 0 || leaf >= a.n) return INFINITY;
+    if (kTri) {
+        float w1, w2;
+        return tri_closest(p, load3(a.verts, a.nv, a.leaf_faces[leaf]), load3(a.verts, a.nv, a.leaf_faces[a.n + leaf]),
+                           load3(a.verts, a.nv, a.leaf_faces[2 * a.n + leaf]), w1, w2);
+    }
+    const f3 d = p - load3(a.verts, a.nv, id);
+    return dot(d, d);
+}
+
+// The starting best of query q from its hint: (d^2 bits, id), or `none`.
+template <bool kTri>
+__device__ __forceinline__ unsigned long long hint_best(const QueryArgs &a, int64_t q, f3 p, unsigned long long none) {
+    if (!a.hint) return none;
+    const int32_t h = a.hint[q];
+    const float d2 = prim_dist2<kTri>(a, p, h);
+    const unsigned long long c = pack_best(d2, h);
+    return d2 < INFINITY && c < none ? c : none;
 }
 
 // Test of the single leaf of a one-primitive BVH (no records exist).
@@ -413,8 +440,9 @@ __device__ void batch_loop(const QueryArgs &a, int64_t start, int64_t stride, in
                 if (c < none) S.best[lane] = c;
             }
         } else if (a.n > 1) {
-            unsigned long long seeded = none;
-            if (a.seed && own) {
+            // a hinted primitive's distance starts the query; without one, the seed descent
+            unsigned long long seeded = own ? hint_best<kTri>(a, qid, p, none) : none;
+            if (a.seed && own && seeded == none) {
                 // one greedy root-to-leaf walk (nearer internal child first) gives an
                 // upper bound before the wide expansion starts
                 const float dq = slab_query_margin(p);
@@ -440,8 +468,8 @@ __device__ void batch_loop(const QueryArgs &a, int64_t start, int64_t stride, in
                     const float dr = rref >= 0 ? child_bound<kTri>(p, dq, r0, r1, r2) : INFINITY;
                     node = (lref >= 0 && dl <= dr) ? lref : (rref >= 0 ? rref : -1);
                 }
-                if (seeded < none) S.best[lane] = seeded;
             }
+            if (own && seeded < none) S.best[lane] = seeded;
             const f3 rlo = f3{a.root[0], a.root[1], a.root[2]};
             const f3 rhi = f3{a.root[4], a.root[5], a.root[6]};
             const float rd = own ? box_dist2(p, rlo, rhi) : INFINITY;

@@ -233,3 +233,53 @@ def test_autotuner_picks_a_valid_traversal(device, tmp_path, monkeypatch):
     assert autotune.tune_closest(bvh, Vd, q, reps=2) == res       # cached
     got = mg.closest_point_query(bvh, Vd, q, **autotune.options(res))
     check_closest(got, sc.verts0, sc.faces, sc.queries)
+
+
+@pytest.mark.parametrize("kernel,batch", KERNELS)
+def test_hints_do_not_change_results(device, kernel, batch):
+    """Starting queries from hinted faces (the previous frame's answers, random ids, -1,
+    out-of-range ids, and the output array itself as the hint) gives bitwise the
+    results of the unhinted traversal."""
+    import paper_2606_00444_amd as mg
+    import torch
+    sc = make_config(2, small=True)
+    F = dev(sc.faces, device)
+    bvh = mg.lbvh_build(dev(sc.verts0, device), F)
+    Q = dev(sc.queries, device)
+    nq, nf = sc.queries.shape[1], sc.faces.shape[1]
+    mg.lbvh_refit(bvh, dev(sc.frames([9])[0], device))
+    prev = mg.closest_point_query(bvh, dev(sc.frames([9])[0], device), Q, **qa(kernel, batch))["face"].clone()
+    V = dev(sc.frames([10])[0], device)
+    mg.lbvh_refit(bvh, V)
+    base = mg.closest_point_query(bvh, V, Q, normal=True, **qa(kernel, batch))
+    rng = np.random.default_rng(404)
+    hints = {
+        "previous frame": prev,
+        "random": torch.from_numpy(rng.integers(0, nf, nq).astype(np.int32)).to(device),
+        "none": torch.full((nq,), -1, dtype=torch.int32, device=device),
+        "mixed, out of range": torch.from_numpy(rng.integers(-5, nf + 5, nq).astype(np.int32)).to(device),
+    }
+    for name, h in hints.items():
+        got = mg.closest_point_query(bvh, V, Q, normal=True, hint=h, **qa(kernel, batch))
+        for k in ("face", "dist2", "point", "bary", "normal"):
+            assert torch.equal(got[k], base[k]), (name, k)
+    # the output face array as its own hint (each query reads its hint before writing)
+    out = {k: (v.clone() if v is not None else None) for k, v in base.items()}
+    out["face"].copy_(prev)
+    got = mg.closest_point_query(bvh, V, Q, normal=True, out=out, hint=out["face"], **qa(kernel, batch))
+    for k in ("face", "dist2", "point", "bary", "normal"):
+        assert torch.equal(got[k], base[k]), ("aliased", k)
+
+
+@pytest.mark.parametrize("kernel,batch", [("lane", 0), ("seeded", 8)])
+def test_nearest_point_hints(device, kernel, batch):
+    import paper_2606_00444_amd as mg
+    import torch
+    rng = np.random.default_rng(405)
+    P = rng.random((3, 20000)).astype(np.float32)
+    q = rng.random((3, 5000)).astype(np.float32)
+    bvh = mg.lbvh_build(dev(P, device), None)
+    idx, d2 = mg.nearest_point_query(bvh, dev(P, device), dev(q, device), **qa(kernel, batch))
+    h = torch.from_numpy(rng.integers(-3, 20003, 5000).astype(np.int32)).to(device)
+    idx2, d22 = mg.nearest_point_query(bvh, dev(P, device), dev(q, device), hint=h, **qa(kernel, batch))
+    assert torch.equal(idx, idx2) and torch.equal(d2, d22)
