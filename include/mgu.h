@@ -269,9 +269,11 @@ mg_status mg_lbvh_refit(const float *verts, int32_t n_verts, void *bvh, size_t b
  * none), e.g. the previous frame's result; each query starts from that
  * primitive's distance instead of the seed descent, which makes frame-to-frame
  * queries on a slowly moving mesh cheap.  hint may be the output id array of
- * the same call (a query reads its hint before writing its result).  Results
- * do not depend on any of these choices except among exact ties, which all
- * pick the lowest original id. */
+ * the same call (a query reads its hint before writing its result).  warm
+ * (mg_chamfer only, which ignores hint): non-zero means nn_ab and nn_ba hold
+ * earlier answers on entry (e.g. the previous call's) that start the queries
+ * of their directions.  Results do not depend on any of these choices except
+ * among exact ties, which all pick the lowest original id. */
 #define MG_QUERY_AUTO  0
 #define MG_QUERY_LANE  1
 #define MG_QUERY_BATCH 2
@@ -280,7 +282,7 @@ typedef struct mg_query_options {
     int32_t kernel;
     int32_t batch;
     int32_t seed;
-    int32_t reserved0;
+    int32_t warm;
     const int32_t *order;
     uint64_t *counters;
     uint32_t *queue;
@@ -412,7 +414,9 @@ mg_status mg_mean(const float *x, int64_t n, double *out, void *ws, size_t ws_by
  * nn_ab[i] / d_ab[i]: nearest b of a_i and its squared distance (via bvh_b,
  * a MG_PRIM_POINTS BVH over b); nn_ba / d_ba likewise via bvh_a over a;
  * out[0] = mean d_ab, out[1] = mean d_ba (device float64).  opts as for
- * mg_nearest_point_query (applies to both directions). */
+ * mg_nearest_point_query (applies to both directions) except hint, which is
+ * ignored: with opts->warm set, the entries of nn_ab and nn_ba on entry are
+ * the hints of their directions (ids out of range count as none). */
 mg_status mg_chamfer(const float *a, int32_t na, const void *bvh_a, size_t bvh_a_bytes,
                      const float *b, int32_t nb, const void *bvh_b, size_t bvh_b_bytes,
                      int32_t *nn_ab, float *d_ab, int32_t *nn_ba, float *d_ba, double *out,

@@ -39,7 +39,7 @@ class LbvhLayout(ctypes.Structure):
 
 
 class QueryOptions(ctypes.Structure):
-    _fields_ = [("kernel", I32), ("batch", I32), ("seed", I32), ("reserved0", I32), ("order", P),
+    _fields_ = [("kernel", I32), ("batch", I32), ("seed", I32), ("warm", I32), ("order", P),
                 ("counters", P), ("queue", P), ("hint", P)]
 
 

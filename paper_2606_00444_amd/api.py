@@ -206,20 +206,22 @@ def lbvh_refit(bvh, verts):
     return bvh
 
 
-def _opts(kernel, batch, seed=False, order=None, counters=None, queue=None, hint=None):
+def _opts(kernel, batch, seed=False, order=None, counters=None, queue=None, hint=None, warm=False):
     """ctypes options for the traversal ("auto" | "lane" | "batch"); None when automatic.
 
     queue: a device int32 [1] work counter for the batch kernel's dynamic
     batch assignment (zeroed by the call itself), or None for static.
-    hint: device int32 [Q] original ids to start the queries from, or None."""
+    hint: device int32 [Q] original ids to start the queries from, or None.
+    warm (chamfer): start from the nearest-neighbour arrays' current contents."""
     auto = kernel in (None, "auto") and not batch and not seed and order is None and counters is None
-    if auto and queue is None and hint is None:
+    if auto and queue is None and hint is None and not warm:
         return None
     k = {"auto": MG_QUERY_AUTO, None: MG_QUERY_AUTO, "lane": MG_QUERY_LANE, "batch": MG_QUERY_BATCH}[kernel]
     o = QueryOptions()
     o.kernel = k
     o.batch = int(batch or 0)
     o.seed = 1 if auto else int(bool(seed))           # the automatic choice has the seed on
+    o.warm = int(bool(warm))
     if queue is not None:
         if queue.dtype != torch.int32 or queue.numel() < 1:
             raise TypeError("queue must be int32 [1]")
@@ -351,11 +353,12 @@ def mean(x, out=None):
     return out
 
 
-def chamfer(a, bvh_a, b, bvh_b, *, out=None, kernel=None, batch=0, seed=False):
+def chamfer(a, bvh_a, b, bvh_b, *, out=None, kernel=None, batch=0, seed=False, warm=False):
     """Two-sided Chamfer pieces: dict nn_ab, d_ab, nn_ba, d_ba and means [2] (float64).
 
     out: optional dict of preallocated outputs with those keys (means may be any
-    contiguous float64 [2] view)."""
+    contiguous float64 [2] view).  warm: out's nn_ab / nn_ba hold earlier answers
+    (e.g. the previous step's; -1 for none) that start the queries."""
     na, nb = _f32(a, 3, "a").shape[1], _f32(b, 3, "b").shape[1]
     dev = a.device
     o = dict(out or {})
@@ -366,7 +369,7 @@ def chamfer(a, bvh_a, b, bvh_b, *, out=None, kernel=None, batch=0, seed=False):
     ws = _rws(dev)
     _call("mg_chamfer", _ptr(a), na, _ptr(bvh_a.buf), bvh_a.nbytes, _ptr(b), nb, _ptr(bvh_b.buf),
           bvh_b.nbytes, _ptr(_i32(o["nn_ab"])), _ptr(_f32(o["d_ab"])), _ptr(_i32(o["nn_ba"])), _ptr(_f32(o["d_ba"])),
-          _ptr(_f64(o["means"], "means")), _ptr(ws), ws.numel(), _opts(kernel, batch, seed), _stream())
+          _ptr(_f64(o["means"], "means")), _ptr(ws), ws.numel(), _opts(kernel, batch, seed, warm=warm), _stream())
     return o
 
 

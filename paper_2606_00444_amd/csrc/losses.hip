@@ -181,9 +181,20 @@ extern "C" mg_status mg_chamfer(const float *a, int32_t na, const void *bvh_a, s
         return MG_ERR_INVALID_ARGUMENT;
     if ((na > 0 && !a) || (nb > 0 && !b)) return MG_ERR_INVALID_ARGUMENT;
     if (!ws || ws_bytes < sizeof(double) * kReduceMaxBlocks) return MG_ERR_WORKSPACE_TOO_SMALL;
-    mg_status st = mg_nearest_point_query(bvh_b, bvh_b_bytes, nb, b, a, na, INFINITY, nn_ab, d_ab, opts, stream);
+    // each direction's hints are its own previous answers (warm) or none
+    mg_query_options o_ab{}, o_ba{};
+    const mg_query_options *p_ab = opts, *p_ba = opts;
+    if (opts) {
+        o_ab = *opts;
+        o_ab.hint = opts->warm ? nn_ab : nullptr;
+        o_ba = *opts;
+        o_ba.hint = opts->warm ? nn_ba : nullptr;
+        p_ab = &o_ab;
+        p_ba = &o_ba;
+    }
+    mg_status st = mg_nearest_point_query(bvh_b, bvh_b_bytes, nb, b, a, na, INFINITY, nn_ab, d_ab, p_ab, stream);
     if (st != MG_OK) return st;
-    st = mg_nearest_point_query(bvh_a, bvh_a_bytes, na, a, b, nb, INFINITY, nn_ba, d_ba, opts, stream);
+    st = mg_nearest_point_query(bvh_a, bvh_a_bytes, na, a, b, nb, INFINITY, nn_ba, d_ba, p_ba, stream);
     if (st != MG_OK) return st;
     hipStream_t s = as_stream(stream);
     st = launch_mean(d_ab, na, out, ws, s);

@@ -6,12 +6,14 @@ definitions) and its gradient with the library's kernels, then applies Adam
 
   1. clear the gradient accumulators                     (mg_fill)
   2. refit the template BVH to V                          (mg_lbvh_refit)
-  3. closest point on (V, F) of every target              (mg_closest_point_query)
+  3. closest point on (V, F) of every target, starting
+     from the previous step's face                        (mg_closest_point_query)
   4. P = mean squared distance                            (mg_mean)
   5. re-pose the Gaussian means mu(V)                     (mg_mesh_gaussian_update)
   6. refit the point LBVH over mu (built once from mu(V0):
      the means move little per step and nearest points stay
-     exact on any tree), both nearest-neighbour maps, CD   (mg_lbvh_refit, mg_chamfer)
+     exact on any tree), both nearest-neighbour maps from
+     the previous step's, CD                              (mg_lbvh_refit, mg_chamfer)
   7. dP/dV, dCD/dmu, and dCD/dV through the binding       (mg_point_mesh_backward,
                                                            mg_chamfer_backward,
                                                            mg_mesh_gaussian_update_backward)
@@ -57,6 +59,9 @@ class TemplateRefiner:
         self.rec = api._query_out(ny, dev, True, True, True, False)
         self.ch = {"nn_ab": torch.empty(G, dtype=torch.int32, device=dev), "d_ab": torch.empty(G, device=dev),
                    "nn_ba": torch.empty(ny, dtype=torch.int32, device=dev), "d_ba": torch.empty(ny, device=dev)}
+        # each step's queries start from the previous step's answers (none at first)
+        for t in (self.rec["face"], self.ch["nn_ab"], self.ch["nn_ba"]):
+            t.fill_(-1)
         self.history = torch.zeros(max_steps, 3, dtype=torch.float64, device=dev)
         self.max_steps = max_steps
         self.bvh = api.lbvh_build(verts0, faces)
@@ -86,13 +91,13 @@ class TemplateRefiner:
         api.fill(self.gV, 0.0)
         api.fill(self.gmu, 0.0)
         api.lbvh_refit(self.bvh, self.V)
-        api.closest_point_query(self.bvh, self.V, self.targets, out=self.rec, **self.query)
+        api.closest_point_query(self.bvh, self.V, self.targets, out=self.rec, hint=self.rec["face"], **self.query)
         row = hist_row if hist_row is not None else torch.empty(3, dtype=torch.float64, device=self.V.device)
         api.mean(self.rec["dist2"], out=row[0:1])
         api.mesh_gaussian_update(self.V, self.faces, b["face"], b["bary"], b["q_local"], b["log_scale"],
                                  b.get("offset"), out={"mean": self.mu}, quat=False, cov=False)
         api.lbvh_refit(self.bvh_mu, self.mu)
-        api.chamfer(self.mu, self.bvh_mu, self.targets, self.bvh_y, out=dict(self.ch, means=row[1:3]),
+        api.chamfer(self.mu, self.bvh_mu, self.targets, self.bvh_y, out=dict(self.ch, means=row[1:3]), warm=True,
                     **self.nn_query)
         if self.ny:
             api.point_mesh_backward(self.V, self.faces, self.targets, self.rec, 1.0 / self.ny, self.gV)

@@ -283,3 +283,24 @@ def test_nearest_point_hints(device, kernel, batch):
     h = torch.from_numpy(rng.integers(-3, 20003, 5000).astype(np.int32)).to(device)
     idx2, d22 = mg.nearest_point_query(bvh, dev(P, device), dev(q, device), hint=h, **qa(kernel, batch))
     assert torch.equal(idx, idx2) and torch.equal(d2, d22)
+
+
+def test_chamfer_warm_start(device):
+    """Chamfer started from earlier nearest-neighbour arrays (valid, absent and out-of-range
+    ids, of their own direction's lengths) gives bitwise the cold results."""
+    import paper_2606_00444_amd as mg
+    import torch
+    rng = np.random.default_rng(406)
+    a = dev(rng.normal(size=(3, 3000)).astype(np.float32), device)
+    b = dev(rng.normal(size=(3, 2000)).astype(np.float32), device)
+    bvh_a, bvh_b = mg.lbvh_build(a, None), mg.lbvh_build(b, None)
+    base = mg.chamfer(a, bvh_a, b, bvh_b)
+    out = {"nn_ab": torch.from_numpy(rng.integers(-3, 2003, 3000).astype(np.int32)).to(device),
+           "nn_ba": torch.from_numpy(rng.integers(-3, 3003, 2000).astype(np.int32)).to(device)}
+    got = mg.chamfer(a, bvh_a, b, bvh_b, out=out, warm=True)
+    for k in ("nn_ab", "d_ab", "nn_ba", "d_ba", "means"):
+        assert torch.equal(got[k], base[k]), k
+    # a second warm call from its own answers
+    again = mg.chamfer(a, bvh_a, b, bvh_b, out=got, warm=True)
+    for k in ("nn_ab", "d_ab", "nn_ba", "d_ba", "means"):
+        assert torch.equal(again[k], base[k]), k
