@@ -86,7 +86,11 @@ def closest_on_triangle(p, a, b, c):
     va = d3 * d6 - d5 * d4
 
     w = np.zeros(shape + (3,))
-    done = np.zeros(shape, bool)
+    # A triangle of zero area is a segment or a point (the hull of collinear vertices):
+    # the region tests below assume a proper triangle, so it takes the edge fallback.
+    nrm = np.cross(ab, ac)
+    flat = _dot(nrm, nrm) == 0
+    done = flat.copy()
 
     def take(mask, w0, w1, w2):
         nonlocal done
@@ -113,7 +117,7 @@ def closest_on_triangle(p, a, b, c):
     dd = np.where(interior, den, 1.0)
     take(interior, 1 - vb / dd - vc / dd, vb / dd, vc / dd)
     pt = w[..., 0:1] * a + w[..., 1:2] * b + w[..., 2:3] * c
-    rest = ~done                                                         # zero-area fallback
+    rest = ~done | flat                                                  # zero-area fallback
     if rest.any():
         best = None
         for (u, s, iu, is_) in ((a, b, 0, 1), (a, c, 0, 2), (b, c, 1, 2)):

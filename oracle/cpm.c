@@ -7,9 +7,11 @@
  * For every query p, every face is tested (NearestSurface read as the single
  * nearest face, Sec. 3.3 Eq. 2 of the paper); exact ties of the squared distance
  * keep the lowest face id.  Closest point on one triangle: Ericson, Real-Time
- * Collision Detection (2005), Sec. 5.1.5 (Voronoi regions); a triangle whose
- * interior denominator is not positive (zero area) falls back to the nearest of
- * its edge segments AB, AC, BC (ties in that order).
+ * Collision Detection (2005), Sec. 5.1.5 (Voronoi regions).  A triangle of zero
+ * area (ab x ac == 0 exactly: its vertices are collinear or repeated, so the
+ * closed triangle is a segment or a point) is handled as the nearest of its edge
+ * segments AB, AC, BC (ties in that order); the region tests assume a proper
+ * triangle (with a == b they would accept edge AB for every query).
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC cpm.c -o libmgu_oracle.so
  */
@@ -38,6 +40,8 @@ static double seg(d3 p, d3 a, d3 b, double *t_out)
 static double tri_closest(d3 p, d3 a, d3 b, d3 c, double w[3])
 {
     d3 ab = sub(b, a), ac = sub(c, a), ap = sub(p, a);
+    d3 n = {ab.y * ac.z - ab.z * ac.y, ab.z * ac.x - ab.x * ac.z, ab.x * ac.y - ab.y * ac.x};
+    if (dot(n, n) == 0.0) goto flat;
     double d1 = dot(ab, ap), d2 = dot(ac, ap);
     if (d1 <= 0.0 && d2 <= 0.0) { w[0] = 1; w[1] = 0; w[2] = 0; goto done; }
     d3 bp = sub(p, b);
@@ -67,7 +71,9 @@ static double tri_closest(d3 p, d3 a, d3 b, d3 c, double w[3])
             double v = vb / den, u = vc / den;
             w[0] = 1 - v - u; w[1] = v; w[2] = u; goto done;
         }
-        /* zero area: nearest edge segment */
+    }
+flat:
+    {   /* zero area: nearest edge segment */
         double t, best = seg(p, a, b, &t);
         w[0] = 1 - t; w[1] = t; w[2] = 0;
         double d = seg(p, a, c, &t);

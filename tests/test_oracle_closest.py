@@ -97,6 +97,30 @@ def test_zero_area_triangle_uses_segments():
         np.testing.assert_allclose(w[0] * a + w[1] * b + w[2] * c, pt, atol=1e-15)
 
 
+def test_repeated_vertex_triangles_are_segments():
+    """A triangle with two equal vertices is the segment between the distinct ones (or a
+    point): the nearest point is the clamped projection onto that segment, whichever two
+    vertices repeat, and both codings of the mesh query find it as the unique nearest."""
+    u, v = np.array([0.0, 0, 0]), np.array([2.0, 0, 0])
+    P = np.array([[1.0, 1.0, 0.0], [0.5, -0.3, 0.4], [-1.0, 0.2, 0.0], [3.0, 0.0, 1.0]])
+    want = np.stack([np.clip(P[:, 0], 0, 2), np.zeros(4), np.zeros(4)], axis=1)
+    for tri in ((u, u, v), (u, v, u), (v, u, u), (u, v, v), (v, v, u), (v, u, v)):
+        for p, q in zip(P, want):
+            pt, w = oc.closest_on_triangle(p, *tri)
+            np.testing.assert_allclose(pt, q, atol=1e-15)
+            np.testing.assert_allclose(w.sum(), 1.0, atol=1e-15)
+    pt, _ = oc.closest_on_triangle(P[0], u, u, u)                       # all three equal: the point
+    np.testing.assert_array_equal(pt, u)
+    # mesh: one proper triangle far away, and the six degenerate faces
+    verts = np.array([[0.0, 2.0, 50, 51, 50], [0, 0, 50, 50, 51], [0, 0, 0, 0, 0]])
+    faces = np.array([[2, 0, 0, 1, 0, 1, 1], [3, 0, 1, 0, 1, 1, 0], [4, 1, 0, 0, 1, 0, 1]])
+    for impl in ("c", "numpy"):
+        r = oc.closest_point_mesh(verts, faces, P.T, impl=impl)
+        np.testing.assert_array_equal(r["face"], [1, 1, 1, 1])            # lowest of the tied faces
+        np.testing.assert_allclose(r["point"], want.T, atol=1e-15)
+        np.testing.assert_allclose(r["dist2"], ((P - want) ** 2).sum(1), rtol=1e-15)
+
+
 def test_mesh_closest_cube_and_ties():
     # unit cube, 12 faces; a query far along +x lands on the x = 1 side
     V = np.array([[x, y, z] for x in (0, 1) for y in (0, 1) for z in (0, 1)], dtype=np.float64).T
