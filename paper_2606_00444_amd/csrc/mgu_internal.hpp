@@ -40,6 +40,18 @@ __device__ __forceinline__ float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y 
 __device__ __forceinline__ f3 cross(f3 a, f3 b) {
     return f3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
+// a*b - c*d with both products rounded (not fused): exactly zero whenever the two
+// products are the same, as the region determinants and the cross product of a
+// triangle with two equal vertices are.
+__device__ __forceinline__ float det2(float a, float b, float c, float d) {
+#pragma clang fp contract(off)
+    return a * b - c * d;
+}
+// Cross product of rounded products: exactly zero when a == b or either is zero,
+// so a triangle with two equal vertices has no normal.
+__device__ __forceinline__ f3 cross_rounded(f3 a, f3 b) {
+    return f3{det2(a.y, b.z, a.z, b.y), det2(a.z, b.x, a.x, b.z), det2(a.x, b.y, a.y, b.x)};
+}
 __device__ __forceinline__ f3 fmin3(f3 a, f3 b) { return f3{fminf(a.x, b.x), fminf(a.y, b.y), fminf(a.z, b.z)}; }
 __device__ __forceinline__ f3 fmax3(f3 a, f3 b) { return f3{fmaxf(a.x, b.x), fmaxf(a.y, b.y), fmaxf(a.z, b.z)}; }
 
@@ -59,7 +71,12 @@ __device__ __forceinline__ void store3(float *__restrict__ p, int64_t n, int64_t
 // is not positive (zero area in float32) falls back to the nearest of its edge
 // segments, ties in the order ab, ac, bc.  Quotients use the hardware
 // reciprocal (about 1 ulp); vertex regions return the vertex exactly.
+// Triangles with two equal vertices (segments) are answered exactly: their region
+// determinants va, vb, vc are exact zeros (det2), and an edge region also needs
+// its squared length (d1 - d3 for AB, e43 + e56 for BC) to be positive, since its
+// other tests hold for every p when that edge has zero length.
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 
 __device__ __forceinline__ float seg_closest(f3 p, f3 a, f3 b, float &t) {
     f3 ab = b - a;
@@ -78,25 +95,24 @@ __device__ __forceinline__ float tri_closest(f3 p, f3 a, f3 b, f3 c, float &w1, 
     } else {
         f3 bp = p - b;
         float d3 = dot(ab, bp), d4 = dot(ac, bp);
-        float vc = d1 * d4 - d3 * d2;
+        float vc = det2(d1, d4, d3, d2);
         if (d3 >= 0.0f && d4 <= d3) {
             w1 = 1.0f; w2 = 0.0f;
-        } else if (vc <= 0.0f && d1 >= 0.0f && d3 <= 0.0f) {
-            float den = d1 - d3;
-            w1 = den != 0.0f ? d1 * rcp(den) : 0.0f; w2 = 0.0f;
+        } else if (vc <= 0.0f && d1 >= 0.0f && d3 <= 0.0f && d1 - d3 > 0.0f) {
+            w1 = d1 * rcp(d1 - d3); w2 = 0.0f;
         } else {
             f3 cp = p - c;
             float d5 = dot(ab, cp), d6 = dot(ac, cp);
-            float vb = d5 * d2 - d1 * d6;
-            float va = d3 * d6 - d5 * d4;
+            float vb = det2(d5, d2, d1, d6);
+            float va = det2(d3, d6, d5, d4);
+            float e43 = d4 - d3, e56 = d5 - d6;
             if (d6 >= 0.0f && d5 <= d6) {
                 w1 = 0.0f; w2 = 1.0f;
             } else if (vb <= 0.0f && d2 >= 0.0f && d6 <= 0.0f) {
                 float den = d2 - d6;
                 w1 = 0.0f; w2 = den != 0.0f ? d2 * rcp(den) : 0.0f;
-            } else if (va <= 0.0f && (d4 - d3) >= 0.0f && (d5 - d6) >= 0.0f) {
-                float den = (d4 - d3) + (d5 - d6);
-                float t = den != 0.0f ? (d4 - d3) * rcp(den) : 0.0f;
+            } else if (va <= 0.0f && e43 >= 0.0f && e56 >= 0.0f && e43 + e56 > 0.0f) {
+                float t = e43 * rcp(e43 + e56);
                 w1 = 1.0f - t; w2 = t;
             } else {
                 float den = va + vb + vc;
@@ -122,10 +138,10 @@ __device__ __forceinline__ float tri_closest(f3 p, f3 a, f3 b, f3 c, float &w1, 
 }
 
 // Unit normal of triangle abc from its stored winding; zero when |ab| == 0 or
-// |ab x ac| == 0 (degenerate).
+// |ab x ac| == 0 (degenerate; exact for repeated vertices, see cross_rounded).
 __device__ __forceinline__ f3 tri_normal(f3 a, f3 b, f3 c) {
     f3 e1 = b - a;
-    f3 n = cross(e1, c - a);
+    f3 n = cross_rounded(e1, c - a);
     float l1 = dot(e1, e1), ln = dot(n, n);
     if (l1 == 0.0f || ln == 0.0f) return f3{0.0f, 0.0f, 0.0f};
     float r = 1.0f / sqrtf(ln);

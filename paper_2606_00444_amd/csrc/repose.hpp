@@ -21,7 +21,7 @@ __device__ __forceinline__ Frame triangle_frame(f3 v0, f3 v1, f3 v2, f3 &e1, f3 
     Frame F;
     e1 = v1 - v0;
     e2 = v2 - v0;
-    nraw = cross(e1, e2);
+    nraw = cross_rounded(e1, e2);      // exactly zero for two equal vertices
     F.l1 = sqrtf(dot(e1, e1));
     F.ln = sqrtf(dot(nraw, nraw));
     F.degenerate = (F.l1 == 0.0f) || (F.ln == 0.0f);

@@ -96,3 +96,52 @@ def test_coincident_sheets_of_opposite_winding(device, kernel, batch):
     bent[2] = (0.05 * (V[0] - 20) ** 2 / 20).astype(np.float32)
     for _ in _run(mg, device, V, F2, Q, kernel, batch, frames=(bent,)):
         pass
+
+
+def needles(seed):
+    """A bumpy grid plus isolated faces with a repeated vertex (segments, in every vertex
+    placement) and with three equal vertices (points), hanging above the grid, so that
+    they are the unique nearest face of the queries around them."""
+    V, F = grid(20, 20)
+    rng = np.random.default_rng(seed)
+    V[2] = rng.normal(0, 0.1, V.shape[1]).astype(np.float32)
+    m = 60
+    u = np.stack([rng.uniform(1, 18, m), rng.uniform(1, 18, m), rng.uniform(2, 4, m)])
+    v = u + rng.normal(0, 0.6, (3, m))
+    n0 = V.shape[1]
+    V = np.concatenate([V, u.astype(np.float32), v.astype(np.float32)], axis=1)
+    iu, iv = n0 + np.arange(m), n0 + m + np.arange(m)
+    order = [(iu, iu, iv), (iu, iv, iu), (iv, iu, iu), (iu, iv, iv), (iv, iv, iu), (iv, iu, iv)]
+    Fn = np.concatenate([np.stack(order[j % 6])[:, j:j + 1] for j in range(m)], axis=1)
+    Fp = np.stack([iv[::4], iv[::4], iv[::4]])                            # point faces
+    Fa = np.concatenate([F, Fn, Fp], axis=1)
+    Fa = Fa[:, rng.permutation(Fa.shape[1])].astype(np.int32)
+    t = rng.uniform(-0.2, 1.2, (1, 3 * m))
+    Q = np.repeat(u, 3, axis=1) + t * np.repeat(v - u, 3, axis=1) + rng.normal(0, 0.15, (3, 3 * m))
+    Q = np.concatenate([Q, np.stack([rng.uniform(0, 19, 500), rng.uniform(0, 19, 500),
+                                     rng.uniform(-1, 5, 500)])], axis=1).astype(np.float32)
+    return V, Fa, Q
+
+
+@pytest.mark.parametrize("kernel,batch", KERNELS)
+def test_repeated_vertex_faces_are_segments(device, kernel, batch):
+    """The closest point on a face with a repeated vertex lies on the segment between its
+    distinct vertices, whichever two vertices repeat, after the build and after a refit."""
+    import paper_2606_00444_amd as mg
+    V, F, Q = needles(304)
+    moved = V.copy()
+    moved[2] += np.float32(0.25)
+    near = 0
+    for Vt, res in _run(mg, device, V, F, Q, kernel, batch, frames=(moved,)):
+        tri = F[:, host(res["face"]).astype(np.int64)]
+        near += int(((tri[0] == tri[1]) | (tri[1] == tri[2]) | (tri[0] == tri[2])).sum())
+    assert near >= 100                                                   # the needles were the answers
+
+
+def test_repeated_vertex_faces_knn_and_nearest(device):
+    import paper_2606_00444_amd as mg
+    from test_gpu_knn import _check
+    V, F, Q = needles(305)
+    face, _, _ = _check(mg, V, F, Q, 3, 0.0, device)
+    tri = F[:, np.maximum(face[0], 0)]
+    assert ((tri[0] == tri[1]) | (tri[1] == tri[2]) | (tri[0] == tri[2])).sum() >= 100
