@@ -72,9 +72,11 @@ __device__ __forceinline__ void store3(float *__restrict__ p, int64_t n, int64_t
 // segments, ties in the order ab, ac, bc.  Quotients use the hardware
 // reciprocal (about 1 ulp); vertex regions return the vertex exactly.
 // Triangles with two equal vertices (segments) are answered exactly: their region
-// determinants va, vb, vc are exact zeros (det2), and an edge region also needs
-// its squared length (d1 - d3 for AB, e43 + e56 for BC) to be positive, since its
-// other tests hold for every p when that edge has zero length.
+// determinants va, vb, vc are exact zeros (det2), and edge AB takes d3 < 0
+// strictly, which excludes d1 = d3 = 0 (a == b: the other tests of edge AB hold for
+// every p) and nothing else that reaches it (d3 = 0 past vertex B means d4 > 0, so
+// vc = d1 d4 > 0 unless d1 = 0).  Then a == b ends in vertex A, vertex C or edge AC,
+// and b == c or a == c in vertex A, vertex B or edge AB.
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 
@@ -98,7 +100,7 @@ __device__ __forceinline__ float tri_closest(f3 p, f3 a, f3 b, f3 c, float &w1, 
         float vc = det2(d1, d4, d3, d2);
         if (d3 >= 0.0f && d4 <= d3) {
             w1 = 1.0f; w2 = 0.0f;
-        } else if (vc <= 0.0f && d1 >= 0.0f && d3 <= 0.0f && d1 - d3 > 0.0f) {
+        } else if (vc <= 0.0f && d1 >= 0.0f && d3 < 0.0f) {
             w1 = d1 * rcp(d1 - d3); w2 = 0.0f;
         } else {
             f3 cp = p - c;
@@ -111,8 +113,9 @@ __device__ __forceinline__ float tri_closest(f3 p, f3 a, f3 b, f3 c, float &w1, 
             } else if (vb <= 0.0f && d2 >= 0.0f && d6 <= 0.0f) {
                 float den = d2 - d6;
                 w1 = 0.0f; w2 = den != 0.0f ? d2 * rcp(den) : 0.0f;
-            } else if (va <= 0.0f && e43 >= 0.0f && e56 >= 0.0f && e43 + e56 > 0.0f) {
-                float t = e43 * rcp(e43 + e56);
+            } else if (va <= 0.0f && e43 >= 0.0f && e56 >= 0.0f) {
+                float den = e43 + e56;
+                float t = den != 0.0f ? e43 * rcp(den) : 0.0f;
                 w1 = 1.0f - t; w2 = t;
             } else {
                 float den = va + vb + vc;
