@@ -10,8 +10,8 @@
 // Phase 1 (one workgroup per subtree): a Karras node covers a contiguous leaf
 // range and its index is one end of that range, so the internal nodes of a
 // subtree over leaves [f, l] have indices in [f, l].  The workgroup keeps, per
-// local index, an arrival counter, a box accumulator (order-preserving uint
-// min/max) and the node's parent link in LDS; a leaf's thread writes the leaf's
+// local index, an arrival counter, a box accumulator (LDS float min/max
+// atomics) and the node's parent link in LDS; a leaf's thread writes the leaf's
 // record slot and climbs while it is the second arrival, so the climb reads
 // only LDS.  The subtree root's box is deposited in its top parent's slot of
 // the top-box table.
@@ -177,24 +177,29 @@ __device__ __forceinline__ void write_root(float *root, f3 lo, f3 hi) {
     root[4] = hi.x; root[5] = hi.y; root[6] = hi.z;
 }
 
-__device__ __forceinline__ void lds_union(uint32_t *b, int64_t stride, int64_t j, f3 lo, f3 hi) {
-    atomicMin(&b[0 * stride + j], f2ord(lo.x));
-    atomicMin(&b[1 * stride + j], f2ord(lo.y));
-    atomicMin(&b[2 * stride + j], f2ord(lo.z));
-    atomicMax(&b[3 * stride + j], f2ord(hi.x));
-    atomicMax(&b[4 * stride + j], f2ord(hi.y));
-    atomicMax(&b[5 * stride + j], f2ord(hi.z));
+// Box accumulators in LDS: float min/max atomics (exact, so any order of
+// arrival gives the same box).  The atomics compare -0 and +0 as equal and keep
+// whichever came first, so zeros are made +0 (x + 0 in round-to-nearest) to
+// keep the box bitwise independent of the arrival order.
+__device__ __forceinline__ void lds_union(float *b, int stride, int j, f3 lo, f3 hi) {
+    lo = f3{lo.x + 0.0f, lo.y + 0.0f, lo.z + 0.0f};
+    hi = f3{hi.x + 0.0f, hi.y + 0.0f, hi.z + 0.0f};
+    __hip_atomic_fetch_min(&b[0 * stride + j], lo.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_min(&b[1 * stride + j], lo.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_min(&b[2 * stride + j], lo.z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_max(&b[3 * stride + j], hi.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_max(&b[4 * stride + j], hi.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_max(&b[5 * stride + j], hi.z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__device__ __forceinline__ void lds_read(const uint32_t *b, int64_t stride, int64_t j, f3 &lo, f3 &hi) {
-    lo = f3{ord2f(b[0 * stride + j]), ord2f(b[1 * stride + j]), ord2f(b[2 * stride + j])};
-    hi = f3{ord2f(b[3 * stride + j]), ord2f(b[4 * stride + j]), ord2f(b[5 * stride + j])};
+__device__ __forceinline__ void lds_read(const float *b, int64_t stride, int64_t j, f3 &lo, f3 &hi) {
+    lo = f3{b[0 * stride + j], b[1 * stride + j], b[2 * stride + j]};
+    hi = f3{b[3 * stride + j], b[4 * stride + j], b[5 * stride + j]};
 }
 
-__device__ __forceinline__ void lds_empty(uint32_t *b, int64_t stride, int64_t j) {
-    const uint32_t e_lo = f2ord(INFINITY), e_hi = f2ord(-INFINITY);
-    b[0 * stride + j] = e_lo; b[1 * stride + j] = e_lo; b[2 * stride + j] = e_lo;
-    b[3 * stride + j] = e_hi; b[4 * stride + j] = e_hi; b[5 * stride + j] = e_hi;
+__device__ __forceinline__ void lds_write(float *b, int64_t stride, int64_t j, f3 lo, f3 hi) {
+    b[0 * stride + j] = lo.x; b[1 * stride + j] = lo.y; b[2 * stride + j] = lo.z;
+    b[3 * stride + j] = hi.x; b[4 * stride + j] = hi.y; b[5 * stride + j] = hi.z;
 }
 
 // Deposit the box, normal sum and slab of a subtree root into slot `slot` of
@@ -217,11 +222,11 @@ __device__ __forceinline__ void deposit(const RefitArgs &a, int32_t p, int slot,
 // refit_sub_lds(C) bytes.
 template <bool kTri, int kThreads>
 __device__ void refit_subtree(const RefitArgs &a, int64_t k, unsigned char *smem) {
-    const int64_t C = int64_t(1) << a.chunk_log2;
+    const int C = 1 << a.chunk_log2;
     const int32_t r = a.subtrees[k];
     const int64_t f = a.subtrees[a.n + k], l = a.subtrees[2 * a.n + k];
-    uint32_t *s_box = reinterpret_cast<uint32_t *>(smem);          // [6][C]
-    uint32_t *s_cnt = s_box + 6 * C;                               // [C]
+    float *s_box = reinterpret_cast<float *>(smem);                // [6][C]
+    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(s_box + 6 * C); // [C]
     int32_t *s_par = reinterpret_cast<int32_t *>(s_cnt + C);       // [C]
     float *s_dep = reinterpret_cast<float *>(s_par + C);           // [2 slots][5][C]: normal sum, slab
     const int64_t size = l - f + 1;
@@ -252,9 +257,9 @@ __device__ void refit_subtree(const RefitArgs &a, int64_t k, unsigned char *smem
     const int64_t i0 = f + threadIdx.x;
     Leaf first{};
     if (i0 <= l) first = load_leaf(i0);
-    for (int64_t j = threadIdx.x; j < size; j += kThreads) {
+    for (int j = threadIdx.x; j < size; j += kThreads) {
         s_cnt[j] = 0;
-        lds_empty(s_box, C, j);
+        lds_write(s_box, C, j, f3{INFINITY, INFINITY, INFINITY}, f3{-INFINITY, -INFINITY, -INFINITY});
         s_par[j] = f + j < a.n - 1 ? a.node_parent[f + j] : -1;
     }
     __syncthreads();
@@ -282,10 +287,11 @@ __device__ void refit_subtree(const RefitArgs &a, int64_t k, unsigned char *smem
         }
         // a valid tree is at most 62 levels deep
         for (int level = 0; level < 64; ++level) {
-            const int64_t j = p - f;
-            if (j < 0 || j >= size) { atomicOr(a.status, 4); break; }
+            const int64_t jl = p - f;
+            if (jl < 0 || jl >= size) { atomicOr(a.status, 4); break; }
+            const int j = static_cast<int>(jl);
             if (kTri) {
-                float *dep = s_dep + static_cast<int64_t>(slot) * 5 * C + j;
+                float *dep = s_dep + slot * 5 * C + j;
                 dep[0] = S.s.x; dep[C] = S.s.y; dep[2 * C] = S.s.z; dep[3 * C] = S.a; dep[4 * C] = S.b;
             }
             lds_union(s_box, C, j, lo, hi);
@@ -333,7 +339,7 @@ __device__ void refit_subtree(const RefitArgs &a, int64_t k, unsigned char *smem
 template <bool kTri, int kThreads, int kOwn>
 __device__ void refit_top(const RefitArgs &a, int T, uint32_t *st, int64_t stride) {
     __shared__ int s_root, s_root_done;
-    uint32_t *bx = st;
+    float *bx = reinterpret_cast<float *>(st);
     int32_t *ch = reinterpret_cast<int32_t *>(st + 6 * stride);
     int32_t *node = reinterpret_cast<int32_t *>(st + 8 * stride);
     uint32_t *done = st + 9 * stride;
@@ -357,8 +363,7 @@ __device__ void refit_top(const RefitArgs &a, int T, uint32_t *st, int64_t strid
             if (kTri)
                 for (int q = 0; q < 5; ++q) dp[(s * 5 + q) * stride + t] = b[(6 + q) * a.tstride];
         }
-        bx[0 * stride + t] = f2ord(lo.x); bx[1 * stride + t] = f2ord(lo.y); bx[2 * stride + t] = f2ord(lo.z);
-        bx[3 * stride + t] = f2ord(hi.x); bx[4 * stride + t] = f2ord(hi.y); bx[5 * stride + t] = f2ord(hi.z);
+        lds_write(bx, stride, t, lo, hi);
         done[t] = 0;
         const int32_t pn = a.top_nodes[t];
         node[t] = pn;
@@ -407,8 +412,7 @@ __device__ void refit_top(const RefitArgs &a, int T, uint32_t *st, int64_t strid
                                       f3{0.0f, 0.0f, 0.0f}, Slab{});
             }
         }
-        bx[0 * stride + t] = f2ord(lo.x); bx[1 * stride + t] = f2ord(lo.y); bx[2 * stride + t] = f2ord(lo.z);
-        bx[3 * stride + t] = f2ord(hi.x); bx[4 * stride + t] = f2ord(hi.y); bx[5 * stride + t] = f2ord(hi.z);
+        lds_write(bx, stride, t, lo, hi);
         if (t == root) {
             write_root(a.root, lo, hi);
             s_root_done = 1;

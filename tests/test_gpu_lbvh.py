@@ -152,6 +152,34 @@ def test_refit_repeated_is_bitwise_stable(device):
     assert torch.equal(first, bvh.buf)
 
 
+def test_refit_signed_zeros_bitwise_stable(device):
+    """Coordinates that are -0 or +0 at random (a flat grid through the origin): the
+    boxes, unions of float min/max in any arrival order, are bitwise the same on every
+    refit, and a zero bound is always +0."""
+    import paper_2606_00444_amd as mg
+    n = 48
+    xs, ys = np.meshgrid(np.arange(n) - n // 2, np.arange(n) - n // 2, indexing="ij")
+    rng = np.random.default_rng(91)
+    sign = lambda a: np.where(rng.random(a.shape) < 0.5, -1.0, 1.0)
+    V = np.stack([xs.ravel(), ys.ravel(), np.zeros(n * n)]).astype(np.float64)
+    V[2] *= sign(V[2])                                   # z: -0 or +0
+    V[0] = np.where(V[0] == 0, 0.0 * sign(V[0]), V[0])   # the x = 0 column too
+    V = V.astype(np.float32)
+    assert np.signbit(V[2]).any() and (~np.signbit(V[2])).any()
+    idx = np.arange(n * n).reshape(n, n)
+    a, b, c, d = idx[:-1, :-1].ravel(), idx[1:, :-1].ravel(), idx[1:, 1:].ravel(), idx[:-1, 1:].ravel()
+    F = np.concatenate([np.stack([a, b, c]), np.stack([a, c, d])], axis=1).astype(np.int32)
+    Vd = dev(V, device)
+    bvh = mg.lbvh_build(Vd, dev(F, device))
+    mg.lbvh_refit(bvh, Vd)
+    first = bvh.buf.clone()
+    for _ in range(50):
+        mg.lbvh_refit(bvh, Vd)
+        assert torch.equal(first, bvh.buf)
+    ib = decode_bvh(bvh)["internal_box"]
+    assert not np.signbit(ib[ib == 0]).any()
+
+
 def test_refit_points(device):
     import paper_2606_00444_amd as mg
     rng = np.random.default_rng(42)
