@@ -165,6 +165,7 @@ class LBVH:
     def __init__(self, n_prims, kind, device, buf=None, ws=None):
         self.n = int(n_prims)
         self.kind = int(kind)
+        self.n_verts = None                 # vertex count of the last build (set by lbvh_build)
         self.layout = _layout(self.n, self.kind)
         need = lbvh_workspace_bytes(self.n, self.kind)
         if buf is None:
@@ -196,12 +197,22 @@ def lbvh_build(verts, faces=None, *, bvh=None):
         bvh = LBVH(n, kind, verts.device)
     _call("mg_lbvh_build", _ptr(verts), verts.shape[1], _ptr(faces), n, kind, _ptr(bvh.buf), bvh.nbytes,
           _ptr(bvh.ws), bvh.ws.numel(), _stream())
+    bvh.n_verts = verts.shape[1]
     return bvh
+
+
+def _same_verts(bvh, verts, what):
+    """Vertex arrays later passed with a BVH must have the build's vertex count: the
+    kernels read vertices through the face ids stored at the build, unchecked."""
+    _f32(verts, 3, "verts")
+    if bvh.n_verts is not None and verts.shape[1] != bvh.n_verts:
+        raise ValueError(f"{what}: verts has {verts.shape[1]} vertices, the BVH was built on {bvh.n_verts}")
+    return verts
 
 
 def lbvh_refit(bvh, verts):
     """Recompute every box of bvh for new positions verts (topology unchanged)."""
-    _call("mg_lbvh_refit", _ptr(_f32(verts, 3, "verts")), verts.shape[1], _ptr(bvh.buf), bvh.nbytes, bvh.n,
+    _call("mg_lbvh_refit", _ptr(_same_verts(bvh, verts, "lbvh_refit")), verts.shape[1], _ptr(bvh.buf), bvh.nbytes, bvh.n,
           bvh.kind, _stream())
     return bvh
 
@@ -285,6 +296,7 @@ def closest_point_query(bvh, verts, queries, max_dist2=math.inf, *, point=True, 
     if bvh.kind != MG_PRIM_TRIANGLES:
         raise ValueError("closest_point_query needs a triangle BVH")
     nq = _f32(queries, 3, "queries").shape[1]
+    _same_verts(bvh, verts, "closest_point_query")
     o = out if out is not None else _query_out(nq, queries.device, point, bary, dist2, normal)
     _call("mg_closest_point_query", _ptr(bvh.buf), bvh.nbytes, bvh.n, _ptr(verts), verts.shape[1],
           _ptr(queries), nq, float(max_dist2), _ptr(o["face"]), _ptr(o.get("point")), _ptr(o.get("bary")),
@@ -309,6 +321,7 @@ def knn_surface_query(bvh, verts, queries, k=4, eps=0.0, max_dist2=math.inf, *, 
     if bvh.kind != MG_PRIM_TRIANGLES:
         raise ValueError("knn_surface_query needs a triangle BVH")
     nq = _f32(queries, 3, "queries").shape[1]
+    _same_verts(bvh, verts, "knn_surface_query")
     o = dict(out or {})
     for key, shape, dt in (("face", (k, nq), torch.int32), ("dist2", (k, nq), torch.float32), ("point", (3, nq), torch.float32)):
         if key not in o or (o[key] is None and key != "point"):
@@ -325,6 +338,8 @@ def nearest_point_query(bvh, points, queries, max_dist2=math.inf, *, kernel=None
     if bvh.kind != MG_PRIM_POINTS:
         raise ValueError("nearest_point_query needs a point BVH")
     nq = _f32(queries, 3, "queries").shape[1]
+    if _f32(points, 3, "points").shape[1] != bvh.n:
+        raise ValueError(f"nearest_point_query: points has {points.shape[1]} entries, the BVH {bvh.n}")
     idx = torch.empty(nq, dtype=torch.int32, device=queries.device)
     d2 = torch.empty(nq, device=queries.device)
     _call("mg_nearest_point_query", _ptr(bvh.buf), bvh.nbytes, bvh.n, _ptr(points), _ptr(queries), nq,

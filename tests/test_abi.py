@@ -104,3 +104,27 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_binding_rejects_vertex_counts_other_than_the_build(lib):
+    """The kernels read vertices through the face ids stored at the build, unchecked, so
+    the binding refuses a refit or query with another vertex count, and wrong dtypes,
+    on the host (these raise before anything reaches the device)."""
+    import torch
+    import paper_2606_00444_amd as mg
+    bvh = mg.LBVH(8, mg.MG_PRIM_TRIANGLES, "cpu")
+    bvh.n_verts = 10
+    q = torch.zeros(3, 4)
+    with pytest.raises(ValueError, match="built on 10"):
+        mg.lbvh_refit(bvh, torch.zeros(3, 9))
+    with pytest.raises(ValueError, match="built on 10"):
+        mg.closest_point_query(bvh, torch.zeros(3, 11), q)
+    with pytest.raises(ValueError, match="built on 10"):
+        mg.knn_surface_query(bvh, torch.zeros(3, 9), q)
+    with pytest.raises(TypeError, match="float32"):
+        mg.closest_point_query(bvh, torch.zeros(3, 10, dtype=torch.float64), q)
+    with pytest.raises(ValueError, match=r"\[3\]\[n\]"):
+        mg.lbvh_refit(bvh, torch.zeros(10, 3))
+    pts = mg.LBVH(5, mg.MG_PRIM_POINTS, "cpu")
+    with pytest.raises(ValueError, match="points has 6"):
+        mg.nearest_point_query(pts, torch.zeros(3, 6), q)
