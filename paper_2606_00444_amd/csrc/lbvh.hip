@@ -376,14 +376,6 @@ __global__ __launch_bounds__(kSortThreads) void radix_pass_kernel(
     }
 }
 
-// delta(i, j) of Karras 2012 over keys (code, index); -1 outside [0, n).
-__device__ __forceinline__ int kdelta(const uint32_t *__restrict__ codes, int64_t n, int64_t i, int64_t j) {
-    if (j < 0 || j >= n) return -1;
-    const uint32_t a = codes[i], b = codes[j];
-    if (a != b) return __clz(static_cast<int>(a ^ b));
-    return 32 + __clz(static_cast<int>(static_cast<uint32_t>(i) ^ static_cast<uint32_t>(j)));
-}
-
 // Internal node i (i < n - 1) and leaf i (i < n): Karras's range and split
 // search; children's parent tags; leaf face permutation; counter reset.
 __global__ __launch_bounds__(256) void hierarchy_kernel(const uint32_t *__restrict__ codes,
@@ -420,22 +412,34 @@ __global__ __launch_bounds__(256) void hierarchy_kernel(const uint32_t *__restri
         return;
     }
     if (i >= n - 1) return;
-    const int d = (kdelta(codes, n, i, i + 1) - kdelta(codes, n, i, i - 1)) > 0 ? 1 : -1;
-    const int dmin = kdelta(codes, n, i, i - d);
-    int64_t lmax = 2;
-    while (kdelta(codes, n, i, i + lmax * d) > dmin) lmax <<= 1;
-    int64_t l = 0;
-    for (int64_t t = lmax >> 1; t >= 1; t >>= 1)
-        if (kdelta(codes, n, i, i + (l + t) * d) > dmin) l += t;
-    const int64_t j = i + l * d;
-    const int dnode = kdelta(codes, n, i, j);
-    int64_t s = 0;
-    for (int64_t div = 2;; div <<= 1) {
-        const int64_t t = (l + div - 1) / div;
-        if (kdelta(codes, n, i, i + (s + t) * d) > dnode) s += t;
+    // The searches run in 32-bit indices (counts are below 2^30, so i + lmax d and
+    // 2 l stay below 2^31) with shifts for the halvings.  Each step is a dependent
+    // read of a code (about 0.3 us from L2 for the top nodes), which sets the
+    // kernel's time: the top nodes' threads finish last.
+    const int ni = static_cast<int>(n), ii = static_cast<int>(i);
+    const uint32_t ci = codes[i];
+    auto delta = [&](int jx) -> int {      // delta(i, jx) of Karras 2012; -1 outside [0, n)
+        if (static_cast<uint32_t>(jx) >= static_cast<uint32_t>(ni)) return -1;
+        const uint32_t cj = codes[jx];
+        if (ci != cj) return __clz(static_cast<int>(ci ^ cj));
+        return 32 + __clz(static_cast<int>(static_cast<uint32_t>(ii) ^ static_cast<uint32_t>(jx)));
+    };
+    const int d = (delta(ii + 1) - delta(ii - 1)) > 0 ? 1 : -1;
+    const int dmin = delta(ii - d);
+    int lmax = 2;
+    while (lmax <= ni && delta(ii + lmax * d) > dmin) lmax <<= 1;
+    int l = 0;
+    for (int t = lmax >> 1; t >= 1; t >>= 1)
+        if (delta(ii + (l + t) * d) > dmin) l += t;
+    const int dnode = delta(ii + l * d);
+    int sp = 0;
+    for (int k = 1;; ++k) {               // t = ceil(l / 2^k)
+        const int t = static_cast<int>((static_cast<uint32_t>(l) + (1u << k) - 1u) >> k);
+        if (delta(ii + (sp + t) * d) > dnode) sp += t;
         if (t <= 1) break;
     }
-    const int64_t gamma = i + s * d + (d < 0 ? -1 : 0);
+    const int64_t j = ii + l * d;
+    const int64_t gamma = ii + sp * d + (d < 0 ? -1 : 0);
     const int64_t lo = i < j ? i : j, hi = i < j ? j : i;
     const int32_t tag_l = static_cast<int32_t>(i << 1), tag_r = static_cast<int32_t>((i << 1) | 1);
     if (lo == gamma) leaf_parent[gamma] = tag_l; else node_parent[gamma] = tag_l;
