@@ -28,6 +28,17 @@ __device__ __forceinline__ void atomic_add3(float *g, int64_t n, int64_t i, f3 v
     atomicAdd(g + 2 * n + i, v.z);
 }
 
+// Sum of v over this lane's run of equal keys up to this lane (a segmented
+// inclusive scan; start is the first lane of the run).
+__device__ __forceinline__ float run_sum(float v, int start, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const float y = __shfl_up(v, o);
+        if (lane - o >= start) v += y;
+    }
+    return v;
+}
+
 // Vector-Jacobian product of the re-pose w.r.t. the three vertices, by the
 // chain rule through Sigma = R_g D R_g^T, R_g = R_f R_l, R_f = [t b nh],
 // b = nh x t, t = e1/|e1|, nh = n/|n|, n = e1 x e2, and the barycentric mean.
@@ -35,8 +46,9 @@ __global__ __launch_bounds__(256) void gaussian_backward_kernel(Inputs in, const
                                                                 const float *__restrict__ grot,
                                                                 const float *__restrict__ gcov,
                                                                 float *__restrict__ gverts) {
-    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g >= in.ng) return;
+    const int64_t gi = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool valid = gi < in.ng;
+    const int64_t g = valid ? gi : in.ng - 1;     // every lane runs, so the wave's shuffles see all lanes
     Local L;
     load_local(in, g, L);
     const int64_t n = in.ng;
@@ -86,7 +98,21 @@ __global__ __launch_bounds__(256) void gaussian_backward_kernel(Inputs in, const
     gv0 = gv0 + b0 * gm;
     gv1 = gv1 + L.b1 * gm;
     gv2 = gv2 + L.b2 * gm;
+    // Gaussians are sorted by face, so neighbouring lanes often share a face: each run
+    // of lanes with one face sums its contributions and its last lane adds them
     const int32_t f = in.gface[g];
+    const int lane = threadIdx.x % 64;
+    const int key = valid ? f : -1 - lane;
+    const int prev = __shfl_up(key, 1);
+    const bool head = lane == 0 || prev != key;
+    const uint64_t heads = __ballot(head);
+    const uint64_t le = lanemask_lt() | (1ull << lane);
+    const int start = 63 - __builtin_clzll(heads & le);
+    const bool tail = lane == 63 || ((heads >> (lane + 1)) & 1ull);
+    gv0 = f3{run_sum(gv0.x, start, lane), run_sum(gv0.y, start, lane), run_sum(gv0.z, start, lane)};
+    gv1 = f3{run_sum(gv1.x, start, lane), run_sum(gv1.y, start, lane), run_sum(gv1.z, start, lane)};
+    gv2 = f3{run_sum(gv2.x, start, lane), run_sum(gv2.y, start, lane), run_sum(gv2.z, start, lane)};
+    if (!valid || !tail) return;
     atomic_add3(gverts, in.nv, in.faces[f], gv0);
     atomic_add3(gverts, in.nv, in.faces[in.nf + f], gv1);
     atomic_add3(gverts, in.nv, in.faces[2 * in.nf + f], gv2);
