@@ -45,25 +45,50 @@ __global__ __launch_bounds__(kReduceThreads) void final_mean_kernel(const double
     if (threadIdx.x == 0) out[0] = n > 0 ? s[0] / static_cast<double>(n) : 0.0;
 }
 
+// Sum of v over this lane's run of equal keys up to this lane (a segmented
+// inclusive scan; start is the first lane of the run).
+__device__ __forceinline__ float run_sum(float v, int start, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const float y = __shfl_up(v, o);
+        if (lane - o >= start) v += y;
+    }
+    return v;
+}
+
+// One target per lane.  When neighbouring targets share their closest face (targets
+// in a spatially coherent order, as scans usually are), each run of lanes with one
+// face sums its three vertex contributions and its last lane adds them; targets in
+// random order pay only the shuffles.  Every lane takes part in them.
 __global__ __launch_bounds__(256) void point_mesh_backward_kernel(
     const float *__restrict__ verts, int64_t nv, const int32_t *__restrict__ faces, int64_t nf,
     const float *__restrict__ y, int64_t nq, const int32_t *__restrict__ face, const float *__restrict__ point,
     const float *__restrict__ bary, float scale, const double *__restrict__ g_loss, float *__restrict__ g) {
-    const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (q >= nq) return;
+    const int64_t qi = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t q = qi < nq ? qi : nq - 1;
     const int32_t f = face[q];
-    if (f < 0) return;
+    const bool valid = qi < nq && f >= 0 && f < nf;
     if (g_loss) scale *= static_cast<float>(*g_loss);
     const f3 r = load3(y, nq, q) - load3(point, nq, q);
     const float w1 = bary[q], w2 = bary[nq + q];
     const float w[3] = {1.0f - w1 - w2, w1, w2};
+    const int lane = threadIdx.x % 64;
+    const int key = valid ? f : -1 - lane;
+    const int prev = __shfl_up(key, 1);
+    const uint64_t heads = __ballot(lane == 0 || prev != key);
+    const int start = 63 - __builtin_clzll(heads & (lanemask_lt() | (1ull << lane)));
+    const bool tail = lane == 63 || ((heads >> (lane + 1)) & 1ull);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const int32_t v = faces[k * nf + f];
-        const float c = -2.0f * scale * w[k];
-        atomicAdd(g + v, c * r.x);
-        atomicAdd(g + nv + v, c * r.y);
-        atomicAdd(g + 2 * nv + v, c * r.z);
+        const float c = valid ? -2.0f * scale * w[k] : 0.0f;
+        const float gx = run_sum(c * r.x, start, lane), gy = run_sum(c * r.y, start, lane),
+                    gz = run_sum(c * r.z, start, lane);
+        if (valid && tail) {
+            const int32_t v = faces[k * nf + f];
+            atomicAdd(g + v, gx);
+            atomicAdd(g + nv + v, gy);
+            atomicAdd(g + 2 * nv + v, gz);
+        }
     }
 }
 
