@@ -64,6 +64,61 @@ __global__ __launch_bounds__(256) void sdf_update_kernel(const float *__restrict
     }
 }
 
+// The values of sdf_update_kernel for a compile-time k: every face id and vertex of
+// a node is loaded before any distance is computed (ids outside the mesh read face 0
+// and do not count), so the gathers overlap instead of forming one chain per face,
+// and the winner's sign is taken once, after the minimum.  Node coordinates use
+// 32-bit index arithmetic (grids have fewer than 2^31 nodes).
+template <int K>
+__global__ __launch_bounds__(256) void sdf_update_k_kernel(const float *__restrict__ verts, int64_t nv,
+                                                           const int32_t *__restrict__ faces, int64_t nf,
+                                                           const int32_t *__restrict__ face_k, Grid g, int64_t n,
+                                                           float *__restrict__ sdf, int32_t *__restrict__ face_out) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
+    const uint32_t nx = static_cast<uint32_t>(g.nx), ny = static_cast<uint32_t>(g.ny);
+    for (int64_t v = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; v < n; v += stride) {
+        const uint32_t u = static_cast<uint32_t>(v), i = u % nx, j = (u / nx) % ny, kk = u / (nx * ny);
+        const f3 p = f3{g.lo_x + g.h * static_cast<float>(i), g.lo_y + g.h * static_cast<float>(j),
+                        g.lo_z + g.h * static_cast<float>(kk)};
+        int32_t fid[K];
+        bool ok[K];
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            const int32_t f = face_k[s * n + v];
+            ok[s] = f >= 0 && f < nf;
+            fid[s] = ok[s] ? f : 0;
+        }
+        f3 A[K], B[K], C[K];
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            A[s] = load3(verts, nv, faces[fid[s]]);
+            B[s] = load3(verts, nv, faces[nf + fid[s]]);
+            C[s] = load3(verts, nv, faces[2 * nf + fid[s]]);
+        }
+        float best = INFINITY, bw1 = 0.0f, bw2 = 0.0f;
+        int32_t win = -1;
+        f3 bA = f3{0.0f, 0.0f, 0.0f}, bB = bA, bC = bA;
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            float w1, w2;
+            const float d2 = tri_closest(p, A[s], B[s], C[s], w1, w2);
+            if (ok[s] && d2 < best) {             // ties keep the lowest slot
+                best = d2; win = fid[s];
+                bA = A[s]; bB = B[s]; bC = C[s]; bw1 = w1; bw2 = w2;
+            }
+        }
+        float side = 1.0f;
+        if (win >= 0) {
+            const float w0 = 1.0f - bw1 - bw2;
+            const f3 c = f3{w0 * bA.x + bw1 * bB.x + bw2 * bC.x, w0 * bA.y + bw1 * bB.y + bw2 * bC.y,
+                            w0 * bA.z + bw1 * bB.z + bw2 * bC.z};
+            side = dot(p - c, tri_normal(bA, bB, bC)) >= 0.0f ? 1.0f : -1.0f;
+        }
+        sdf[v] = side * sqrtf(best);
+        if (face_out) face_out[v] = win;
+    }
+}
+
 __global__ __launch_bounds__(256) void sdf_sample_kernel(const float *__restrict__ sdf, Grid g,
                                                          const float *__restrict__ q, int64_t nq,
                                                          float *__restrict__ out) {
@@ -120,8 +175,19 @@ extern "C" mg_status mg_sdf_update(const float *verts, int32_t n_verts, const in
         return MG_ERR_INVALID_ARGUMENT;
     const Grid g{lo_x, lo_y, lo_z, h, nx, ny, nz};
     const int grid = static_cast<int>(std::min<int64_t>(blocks_for(n, 256), 8192));
-    hipLaunchKernelGGL(sdf_update_kernel, dim3(grid), dim3(256), 0, as_stream(stream), verts, (int64_t)n_verts,
-                       faces, (int64_t)n_faces, face_k, k, g, n, sdf, face);
+    hipStream_t st = as_stream(stream);
+    const int64_t nv = n_verts, nf = n_faces;
+    if (n_faces > 0 && k == 1)
+        hipLaunchKernelGGL(sdf_update_k_kernel<1>, dim3(grid), dim3(256), 0, st, verts, nv, faces, nf, face_k, g, n, sdf, face);
+    else if (n_faces > 0 && k == 2)
+        hipLaunchKernelGGL(sdf_update_k_kernel<2>, dim3(grid), dim3(256), 0, st, verts, nv, faces, nf, face_k, g, n, sdf, face);
+    else if (n_faces > 0 && k == 4)
+        hipLaunchKernelGGL(sdf_update_k_kernel<4>, dim3(grid), dim3(256), 0, st, verts, nv, faces, nf, face_k, g, n, sdf, face);
+    else if (n_faces > 0 && k == 8)
+        hipLaunchKernelGGL(sdf_update_k_kernel<8>, dim3(grid), dim3(256), 0, st, verts, nv, faces, nf, face_k, g, n, sdf, face);
+    else
+        hipLaunchKernelGGL(sdf_update_kernel, dim3(grid), dim3(256), 0, st, verts, nv, faces, nf, face_k, k, g, n,
+                           sdf, face);
     return launch_status();
 }
 
