@@ -292,8 +292,10 @@ typedef struct mg_query_options {
 /* ------------------------------------------------------------------------
  * Closest point on a triangle mesh (NearestSurface with barycentric
  * interpolation, Sec. 3.3 Eq. 1-2, read as the single nearest face) with the
- * face normal computed on demand (Sec. 3.4 step 3).  Exact ties of the float32
- * squared distance go to the lowest original face id.  Per query q:
+ * face normal computed on demand (Sec. 3.4 step 3).  A face is the closed
+ * triangle, the hull of its vertices: a face with two equal vertices is the
+ * segment between the distinct ones (and has no normal).  Exact ties of the
+ * float32 squared distance go to the lowest original face id.  Per query q:
  *   face[q]   original face id, -1 if no face has d^2 <= max_dist2
  *   point     [3][nq] closest point (the query itself when face == -1)
  *   bary      [2][nq] (w1, w2): point = (1-w1-w2) v0 + w1 v1 + w2 v2 (0 when none)
