@@ -476,6 +476,52 @@ __global__ __launch_bounds__(256) void hierarchy_kernel(const uint32_t *__restri
     }
 }
 
+// Subtrees largest first.  Phase 1 of the refit gives subtree k to workgroup k
+// (then k + grid, ...), and workgroups start in index order as compute units free
+// up; when more subtrees than resident workgroups exist (LDS allows two per CU at
+// 1024-leaf chunks, one at 2048), the late starters should be the small subtrees
+// (longest-first list scheduling).  One workgroup sorts by (size descending, first
+// leaf ascending), so the order is deterministic; more than kOrderMax subtrees keep
+// their order.  The refit's records do not depend on the order.
+constexpr int kOrderMax = 2048;
+__global__ __launch_bounds__(1024) void order_subtrees_kernel(int32_t *__restrict__ subtrees, int64_t n,
+                                                              const mg_lbvh_header *__restrict__ hdr) {
+    __shared__ uint64_t s_key[kOrderMax];
+    __shared__ int32_t s_val[3][kOrderMax];
+    const int ns = hdr->n_sub;
+    if (ns <= 1 || ns > kOrderMax) return;
+    int P = 1;
+    while (P < ns) P <<= 1;
+    for (int i = threadIdx.x; i < P; i += 1024) {
+        uint64_t key = ~0ull;                     // padding sorts last
+        if (i < ns) {
+            const int32_t r = subtrees[i], f = subtrees[n + i], l = subtrees[2 * n + i];
+            const uint32_t size = static_cast<uint32_t>(l - f + 1) & 0xfffu;   // <= 2048 leaves
+            key = (static_cast<uint64_t>(0xfffu - size) << 42) | (static_cast<uint64_t>(f & 0x3fffffff) << 11) |
+                  static_cast<uint64_t>(i);
+            s_val[0][i] = r; s_val[1][i] = f; s_val[2][i] = l;
+        }
+        s_key[i] = key;
+    }
+    for (int k = 2; k <= P; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            __syncthreads();
+            for (int t = threadIdx.x; t < P; t += 1024) {
+                const int o = t ^ j;
+                if (o <= t) continue;
+                const uint64_t a = s_key[t], b = s_key[o];
+                if ((a > b) == ((t & k) == 0)) { s_key[t] = b; s_key[o] = a; }
+            }
+        }
+    __syncthreads();
+    for (int q = threadIdx.x; q < ns; q += 1024) {
+        const int i = static_cast<int>(s_key[q] & 0x7ffu);
+        subtrees[q] = s_val[0][i];
+        subtrees[n + q] = s_val[1][i];
+        subtrees[2 * n + q] = s_val[2][i];
+    }
+}
+
 // Per top node and slot: the child's top index, or -1 when the child roots a subtree.
 __global__ __launch_bounds__(256) void top_child_kernel(const int32_t *__restrict__ node_aux,
                                                         const int32_t *__restrict__ top_nodes,
@@ -653,6 +699,8 @@ extern "C" mg_status mg_lbvh_build(const float *verts, int32_t n_verts, const in
                        at<int32_t>(bvh, L.off_node_parent), at<int32_t>(bvh, L.off_node_aux),
                        at<int32_t>(bvh, L.off_top_nodes), at<int32_t>(bvh, L.off_subtrees),
                        at<float>(bvh, L.off_nodes), hdr, chunk_log2_for(n));
+    if (chunk_log2_for(n) >= 10)      // subtrees may outnumber the resident refit workgroups
+        hipLaunchKernelGGL(order_subtrees_kernel, dim3(1), dim3(1024), 0, s, at<int32_t>(bvh, L.off_subtrees), n, hdr);
     hipLaunchKernelGGL(top_child_kernel, dim3(static_cast<unsigned>(std::min<int64_t>(blocks_for(n, 256), 64))),
                        dim3(256), 0, s, at<int32_t>(bvh, L.off_node_aux), at<int32_t>(bvh, L.off_top_nodes),
                        at<float>(bvh, L.off_nodes), n, at<int32_t>(bvh, L.off_top_child), hdr);
