@@ -522,7 +522,10 @@ mg_status mg_batch_plan_init(const mg_batch_scene *scenes, int32_t n_scenes, con
 
 /* One run over all scenes x frames: a small reset kernel, then the
  * persistent kernel.  Asynchronous; capturable in a HIP graph.  Runs on the
- * same plan must not overlap. */
+ * same plan must not overlap.  A scene's queries in frame t > 0 start from
+ * their faces of frame t - 1 when those are already computed (the results are
+ * the same either way); the face outputs are written with device-coherent
+ * stores for that. */
 mg_status mg_batch_run(void *plan, size_t plan_bytes, void *stream);
 
 /* Host-only: device address of the plan's int32 error word (0 = fine; a

@@ -40,14 +40,18 @@ struct PlanScene {
     int32_t batch, seed, query_tile;        // this scene's traversal (plan defaults resolved)
     int32_t chunk_log2;
     int32_t sf_base;                        // index of (this scene, frame 0) among all scene-frames
-    int32_t pad;
+    int32_t qd_base;                        // index of (this scene, frame 0, tile 0) among the query-tile counters
     int64_t n_chunks, g_tiles, q_tiles;     // items per frame (n_chunks: subtrees)
     int64_t first[4];                       // first item of this scene in each phase
 };
 
 struct PlanHeader {
     int32_t n_scenes, total_sf;
-    int32_t batch, seed, gauss_tile, query_tile, reserved0;
+    int32_t batch, seed, gauss_tile, query_tile;
+    int32_t total_qt;                       // query-tile counters in use (all scene-frames)
+    int64_t blocks_off;                     // byte offset of the QueryBlock table in the plan
+    int32_t n_blocks;                       // query blocks (scene-frames with queries), frame-major
+    int32_t pad1;
     int32_t status;
     uint32_t queue;
     int32_t pad;
@@ -85,22 +89,48 @@ inline int64_t frame_scratch_words(int32_t T) {
     return 2 * kTopBoxPlanes * static_cast<int64_t>(T) + (T > kBatchTopLds ? kTopStatePlanes * static_cast<int64_t>(T) : 0);
 }
 
-// Plan layout: header, 2 x total_sf dependency counters, then per scene-frame
-// refit scratch.
+// Plan layout: header, 2 x total_sf dependency counters and the query-tile
+// counters (room for the smallest legal tile, 4 queries, since the plan's size
+// does not depend on the options), then per scene-frame refit scratch.
 inline int64_t align256b(int64_t x) { return (x + 255) & ~int64_t(255); }
 
-inline int64_t plan_bytes_for(int64_t total_sf, int64_t scratch_words) {
-    return align256b(static_cast<int64_t>(sizeof(PlanHeader)) + 8 * total_sf) + 4 * scratch_words;
+inline int64_t query_tile_cap(const mg_batch_scene *scenes, int32_t n) {
+    int64_t c = 0;
+    for (int i = 0; i < n; ++i) c += static_cast<int64_t>(scenes[i].n_frames) * ((scenes[i].n_queries + 3) / 4);
+    return c;
 }
 
-// Dependency counters follow the header: done_chunks[total_sf], refit_done[total_sf].
+// The query phase runs frame by frame across the scenes (frame 0 of every scene,
+// then frame 1, ...), so that a query tile's counterpart in the scene's previous
+// frame was taken from the queue a whole frame of work earlier; one block per
+// scene-frame in that order records its first item.
+struct QueryBlock {
+    int64_t first;
+    int32_t scene, frame;
+};
+
+inline int64_t counters_bytes(int64_t total_sf, int64_t qt_cap) {
+    return align256b(static_cast<int64_t>(sizeof(PlanHeader)) + 8 * total_sf + 4 * qt_cap);
+}
+
+inline int64_t blocks_bytes(int64_t total_sf) {
+    return align256b(static_cast<int64_t>(sizeof(QueryBlock)) * total_sf);
+}
+
+inline int64_t plan_bytes_for(int64_t total_sf, int64_t qt_cap, int64_t scratch_words) {
+    return counters_bytes(total_sf, qt_cap) + blocks_bytes(total_sf) + 4 * scratch_words;
+}
+
+// Dependency counters follow the header: done_chunks[total_sf], refit_done[total_sf],
+// query_done[total_qt] (one per scene, frame and query tile).
 __device__ __forceinline__ uint32_t *counters_of(PlanHeader *h) {
     return reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(h) + sizeof(PlanHeader));
 }
 
 __global__ void batch_reset_kernel(PlanHeader *h) {
     uint32_t *c = counters_of(h);
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < 2 * int64_t(h->total_sf);
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+         i < 2 * int64_t(h->total_sf) + h->total_qt;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x)
         c[i] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -185,6 +215,7 @@ __device__ QueryArgs query_args(const PlanScene &P, int64_t t, const RefitArgs &
     a.counters = nullptr;
     a.queue = nullptr;
     a.hint = nullptr;
+    a.coherent = 1;
     return a;
 }
 
@@ -243,11 +274,30 @@ __device__ __noinline__ void item_query(PlanHeader *h, int si, int64_t t, int64_
     extern __shared__ __align__(16) unsigned char smem[];
     const PlanScene &P = h->scenes[si];
     const int sf = P.sf_base + static_cast<int>(t);
+    uint32_t *query_done = counters_of(h) + 2 * int64_t(h->total_sf);
+    const int64_t qd = P.qd_base + t * P.q_tiles + k;
     wait_for(&counters_of(h)[h->total_sf + sf], 1u, &h->status);
-    const QueryArgs q = query_args(P, t, refit_args(P, t, h), P.seed);
+    QueryArgs q = query_args(P, t, refit_args(P, t, h), P.seed);
+    // The queries start from their faces of the scene's previous frame when the same
+    // tile of frame t - 1 (the same queries) is already done; otherwise they start
+    // cold.  Nothing waits for it, and no ordering is needed for correctness: a hint
+    // only lowers the starting bound, and any id is range-checked.  The face ids are
+    // stored and loaded device-coherent, and a tile counts as done only after its
+    // waves' stores have completed, so the hints are that frame's answers without a
+    // write-back of the L2 per tile.
+    if (t > 0) {
+        __shared__ int s_prev_done;
+        if (threadIdx.x == 0)
+            s_prev_done = __hip_atomic_load(&query_done[qd - P.q_tiles], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        __syncthreads();
+        if (s_prev_done) q.hint = P.s.face + (t - 1) * static_cast<int64_t>(P.s.n_queries);
+    }
     const int64_t q0 = k * P.query_tile;
     const int64_t q1 = q0 + P.query_tile < q.nq ? q0 + P.query_tile : q.nq;
     batch_loop<true, M>(q, q0, static_cast<int64_t>(kBatchWaves) * M, q1, *reinterpret_cast<BatchLds<M> *>(smem));
+    __builtin_amdgcn_s_waitcnt(0);          // this wave's stores have completed
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(&query_done[qd], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // At most 128 registers per lane (four waves per SIMD): with the phases
@@ -265,11 +315,27 @@ __global__ __launch_bounds__(kBlock, 4) void batch_persistent_kernel(PlanHeader 
         int phase = 0;
         while (item >= h->phase_end[phase]) ++phase;
         int si = 0;
-        while (si + 1 < ns && item >= h->scenes[si + 1].first[phase]) ++si;
+        int64_t t = 0, k = 0;
+        if (phase < 3) {
+            while (si + 1 < ns && item >= h->scenes[si + 1].first[phase]) ++si;
+            const PlanScene &Q = h->scenes[si];
+            const int64_t local = item - Q.first[phase];
+            const int64_t per = phase == 0 ? Q.n_chunks : phase == 1 ? Q.g_tiles : 1;
+            t = local / per;
+            k = local % per;
+        } else {                            // the query block holding the item: the last with first <= item
+            const QueryBlock *B = reinterpret_cast<const QueryBlock *>(reinterpret_cast<const char *>(h) + h->blocks_off);
+            int lo = 0, hi = h->n_blocks - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) / 2;
+                if (B[mid].first <= item) lo = mid;
+                else hi = mid - 1;
+            }
+            si = B[lo].scene;
+            t = B[lo].frame;
+            k = item - B[lo].first;
+        }
         const PlanScene &P = h->scenes[si];
-        const int64_t local = item - P.first[phase];
-        const int64_t per = phase == 0 ? P.n_chunks : phase == 1 ? P.g_tiles : phase == 2 ? 1 : P.q_tiles;
-        const int64_t t = local / per, k = local % per;
         if (phase == 0) {
             item_refit_sub(h, si, t, k);
         } else if (phase == 1) {
@@ -319,7 +385,8 @@ extern "C" mg_status mg_batch_plan_size(const mg_batch_scene *scenes, int32_t n_
     int64_t words = 0;
     const mg_status st = scratch_words(scenes, n_scenes, words);
     if (st != MG_OK) return st;
-    *plan_bytes = static_cast<size_t>(plan_bytes_for(total_frames(scenes, n_scenes), words));
+    *plan_bytes = static_cast<size_t>(plan_bytes_for(total_frames(scenes, n_scenes), query_tile_cap(scenes, n_scenes),
+                                                     words));
     return MG_OK;
 }
 
@@ -347,8 +414,10 @@ extern "C" mg_status mg_batch_plan_init(const mg_batch_scene *scenes, int32_t n_
     h.gauss_tile = gtile;
     h.query_tile = qtile;
     int64_t sf = 0;
-    uint32_t *scratch = reinterpret_cast<uint32_t *>(static_cast<char *>(plan) +
-                                                     align256b(sizeof(PlanHeader) + 8 * total_frames(scenes, n_scenes)));
+    uint32_t *scratch = reinterpret_cast<uint32_t *>(
+        static_cast<char *>(plan) + counters_bytes(total_frames(scenes, n_scenes), query_tile_cap(scenes, n_scenes)) +
+        blocks_bytes(total_frames(scenes, n_scenes)));
+    int64_t qt = 0;
     for (int i = 0; i < n_scenes; ++i) {
         const mg_batch_scene &s = scenes[i];
         if (bad_count(s.n_verts) || bad_count(s.n_faces) || bad_count(s.n_gauss) || bad_count(s.n_queries) ||
@@ -398,23 +467,45 @@ extern "C" mg_status mg_batch_plan_init(const mg_batch_scene *scenes, int32_t n_
         P.n_chunks = S.n_sub;
         P.g_tiles = (s.n_gauss + gtile - 1) / gtile;
         P.q_tiles = (s.n_queries + P.query_tile - 1) / P.query_tile;
+        P.qd_base = static_cast<int32_t>(qt);
+        qt += static_cast<int64_t>(s.n_frames) * P.q_tiles;
         sf += s.n_frames;
     }
     h.total_sf = static_cast<int32_t>(sf);
+    h.total_qt = static_cast<int32_t>(qt);
+    if (qt > query_tile_cap(scenes, n_scenes)) return MG_ERR_INVALID_ARGUMENT;   // tiles below 4 queries
     int64_t item = 0;
-    for (int phase = 0; phase < 4; ++phase) {
+    for (int phase = 0; phase < 3; ++phase) {
         for (int i = 0; i < n_scenes; ++i) {
             PlanScene &P = h.scenes[i];
             P.first[phase] = item;
-            const int64_t per = phase == 0 ? P.n_chunks : phase == 1 ? P.g_tiles : phase == 2 ? 1 : P.q_tiles;
+            const int64_t per = phase == 0 ? P.n_chunks : phase == 1 ? P.g_tiles : 1;
             item += per * P.s.n_frames;
         }
         h.phase_end[phase] = item;
     }
+    // the query phase, frame-major across the scenes (empty scene-frames have no block)
+    std::vector<QueryBlock> blocks;
+    int32_t max_frames = 0;
+    for (int i = 0; i < n_scenes; ++i) max_frames = std::max(max_frames, scenes[i].n_frames);
+    for (int i = 0; i < n_scenes; ++i) h.scenes[i].first[3] = item;
+    for (int32_t t = 0; t < max_frames; ++t)
+        for (int i = 0; i < n_scenes; ++i) {
+            const PlanScene &P = h.scenes[i];
+            if (t >= P.s.n_frames || P.q_tiles == 0) continue;
+            blocks.push_back(QueryBlock{item, i, t});
+            item += P.q_tiles;
+        }
+    h.phase_end[3] = item;
+    h.n_blocks = static_cast<int32_t>(blocks.size());
+    h.blocks_off = counters_bytes(total_frames(scenes, n_scenes), query_tile_cap(scenes, n_scenes));
     for (int i = n_scenes; i < kMaxScenes; ++i)
         for (int phase = 0; phase < 4; ++phase) h.scenes[i].first[phase] = h.phase_end[3];
     hipStream_t s = as_stream(stream);
     if (hipMemcpyAsync(plan, &h, sizeof(PlanHeader), hipMemcpyHostToDevice, s) != hipSuccess) return MG_ERR_HIP;
+    if (!blocks.empty() && hipMemcpyAsync(static_cast<char *>(plan) + h.blocks_off, blocks.data(),
+                                          sizeof(QueryBlock) * blocks.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+        return MG_ERR_HIP;
     if (hipStreamSynchronize(s) != hipSuccess) return MG_ERR_HIP;
     return MG_OK;
 }

@@ -42,7 +42,16 @@ struct QueryArgs {
     int32_t *status;                    // error word of the BVH header
     uint32_t *queue;                    // batch kernel: dynamic batch counter (zeroed before launch) or nullptr
     const int32_t *hint;                // [nq] original id to start each query from, or nullptr
+    int coherent;                       // face ids stored and hints loaded device-coherent (batched form)
 };
+
+// The face id of a result: with `coherent`, a relaxed device-scope store, which the
+// other XCDs see without a write-back of the L2 (the batched form reads a scene's
+// previous frame as hints while the launch runs).
+__device__ __forceinline__ void store_face(const QueryArgs &a, int64_t q, int32_t id) {
+    if (a.coherent) __hip_atomic_store(a.face + q, id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else a.face[q] = id;
+}
 
 // Query processed in position i (order[i], or i); -1 if the order entry is out of range.
 __device__ __forceinline__ int64_t query_at(const QueryArgs &a, int64_t i) {
@@ -119,7 +128,7 @@ __device__ void write_result(const QueryArgs &a, int64_t q, f3 p, int32_t leaf, 
             float w1, w2;
             const float dd = tri_closest(p, A, B, C, w1, w2);
             const float w0 = 1.0f - w1 - w2;
-            a.face[q] = id;
+            store_face(a, q, id);
             if (a.point)
                 store3(a.point, a.nq, q, f3{w0 * A.x + w1 * B.x + w2 * C.x, w0 * A.y + w1 * B.y + w2 * C.y,
                                             w0 * A.z + w1 * B.z + w2 * C.z});
@@ -127,14 +136,14 @@ __device__ void write_result(const QueryArgs &a, int64_t q, f3 p, int32_t leaf, 
             if (a.dist2) a.dist2[q] = dd;
             if (a.normal) store3(a.normal, a.nq, q, tri_normal(A, B, C));
         } else {
-            a.face[q] = -1;
+            store_face(a, q, -1);
             if (a.point) store3(a.point, a.nq, q, p);
             if (a.bary) { a.bary[q] = 0.0f; a.bary[a.nq + q] = 0.0f; }
             if (a.dist2) a.dist2[q] = INFINITY;
             if (a.normal) store3(a.normal, a.nq, q, f3{0.0f, 0.0f, 0.0f});
         }
     } else {
-        a.face[q] = leaf >= 0 ? id : -1;
+        store_face(a, q, leaf >= 0 ? id : -1);
         if (a.dist2) a.dist2[q] = leaf >= 0 ? d2 : INFINITY;
     }
 }
@@ -170,7 +179,8 @@ __device__ __forceinline__ float prim_dist2(const QueryArgs &a, f3 p, int32_t id
 template <bool kTri>
 __device__ __forceinline__ unsigned long long hint_best(const QueryArgs &a, int64_t q, f3 p, unsigned long long none) {
     if (!a.hint) return none;
-    const int32_t h = a.hint[q];
+    const int32_t h = a.coherent ? __hip_atomic_load(a.hint + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                 : a.hint[q];
     const float d2 = prim_dist2<kTri>(a, p, h);
     const unsigned long long c = pack_best(d2, h);
     return d2 < INFINITY && c < none ? c : none;
