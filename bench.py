@@ -554,13 +554,16 @@ def run_batched(args):
             "opts": {"kernel": "batch", "batch": o["batch"], "seed": o["seed"]}})
 
     def plain_all(_=0):
+        # frames in order, so (like the batched form) a scene's queries in frame t > 0
+        # start from their faces of frame t - 1, the output array they overwrite
         for s, p in zip(scenes, plain):
             for t in range(s["frames"].shape[0]):
                 mg.vertex_buffer_update(s["frames"], t, p["live"])
                 mg.mesh_gaussian_update(p["live"], s["faces"], s["gface"], s["bary"], s["q_local"], s["log_scale"],
                                         out=p["g"])
                 mg.lbvh_refit(p["bvh"], p["live"])
-                mg.closest_point_query(p["bvh"], p["live"], s["queries"], normal=True, out=p["q"], **p["opts"])
+                mg.closest_point_query(p["bvh"], p["live"], s["queries"], normal=True, out=p["q"],
+                                       hint=p["q"]["face"] if t > 0 else None, **p["opts"])
 
     plain_all()
     torch.cuda.synchronize()
