@@ -272,8 +272,12 @@ mg_status mg_lbvh_refit(const float *verts, int32_t n_verts, void *bvh, size_t b
  * the same call (a query reads its hint before writing its result).  warm
  * (mg_chamfer only, which ignores hint): non-zero means nn_ab and nn_ba hold
  * earlier answers on entry (e.g. the previous call's) that start the queries
- * of their directions.  Results do not depend on any of these choices except
- * among exact ties, which all pick the lowest original id. */
+ * of their directions.  waves (BATCH on triangles): the batch kernel's register
+ * allocation; 0 picks five resident waves per SIMD when the batches outnumber
+ * four waves on every SIMD (more than 4,096 batches) and four otherwise, 4 or
+ * 5 forces one; any other value is MG_ERR_INVALID_ARGUMENT.  Results do not
+ * depend on any of these choices except among exact ties, which all pick the
+ * lowest original id. */
 #define MG_QUERY_AUTO  0
 #define MG_QUERY_LANE  1
 #define MG_QUERY_BATCH 2
@@ -287,6 +291,7 @@ typedef struct mg_query_options {
     uint64_t *counters;
     uint32_t *queue;
     const int32_t *hint;
+    int32_t waves;
 } mg_query_options;
 
 /* ------------------------------------------------------------------------

@@ -40,7 +40,7 @@ class LbvhLayout(ctypes.Structure):
 
 class QueryOptions(ctypes.Structure):
     _fields_ = [("kernel", I32), ("batch", I32), ("seed", I32), ("warm", I32), ("order", P),
-                ("counters", P), ("queue", P), ("hint", P)]
+                ("counters", P), ("queue", P), ("hint", P), ("waves", I32)]
 
 
 class BatchScene(ctypes.Structure):

@@ -217,15 +217,18 @@ def lbvh_refit(bvh, verts):
     return bvh
 
 
-def _opts(kernel, batch, seed=False, order=None, counters=None, queue=None, hint=None, warm=False):
+def _opts(kernel, batch, seed=False, order=None, counters=None, queue=None, hint=None, warm=False, waves=0):
     """ctypes options for the traversal ("auto" | "lane" | "batch"); None when automatic.
 
     queue: a device int32 [1] work counter for the batch kernel's dynamic
     batch assignment (zeroed by the call itself), or None for static.
     hint: device int32 [Q] original ids to start the queries from, or None.
-    warm (chamfer): start from the nearest-neighbour arrays' current contents."""
+    warm (chamfer): start from the nearest-neighbour arrays' current contents.
+    waves: the batch kernel's register allocation on triangles (0: by launch size, 4 or 5)."""
     auto = kernel in (None, "auto") and not batch and not seed and order is None and counters is None
-    if auto and queue is None and hint is None and not warm:
+    if waves not in (0, 4, 5):
+        raise ValueError("waves must be 0, 4 or 5")
+    if auto and queue is None and hint is None and not warm and not waves:
         return None
     k = {"auto": MG_QUERY_AUTO, None: MG_QUERY_AUTO, "lane": MG_QUERY_LANE, "batch": MG_QUERY_BATCH}[kernel]
     o = QueryOptions()
@@ -233,6 +236,7 @@ def _opts(kernel, batch, seed=False, order=None, counters=None, queue=None, hint
     o.batch = int(batch or 0)
     o.seed = 1 if auto else int(bool(seed))           # the automatic choice has the seed on
     o.warm = int(bool(warm))
+    o.waves = int(waves)
     if queue is not None:
         if queue.dtype != torch.int32 or queue.numel() < 1:
             raise TypeError("queue must be int32 [1]")
@@ -284,13 +288,14 @@ def _query_out(nq, device, point, bary, dist2, normal):
 
 def closest_point_query(bvh, verts, queries, max_dist2=math.inf, *, point=True, bary=True, dist2=True,
                         normal=False, out=None, kernel=None, batch=0, seed=False, dynamic=False, order=None,
-                        counters=None, hint=None):
+                        counters=None, hint=None, waves=0):
     """Closest point on the mesh of a triangle LBVH for every query [3][Q].
 
     kernel: None/"auto", "lane" or "batch" (batch = queries per wave), dynamic:
     batches taken from a work counter instead of dealt statically; hint: int32
     [Q] face ids to start from (e.g. the previous frame's out["face"], which may
-    be the very array this call overwrites) - see mg_query_options.  out: a dict
+    be the very array this call overwrites) - see mg_query_options; waves: the
+    batch kernel's register allocation (0: by launch size, 4 or 5).  out: a dict
     of output tensors to fill (face, and point, bary, dist2, normal or None each).
     """
     if bvh.kind != MG_PRIM_TRIANGLES:
@@ -301,7 +306,8 @@ def closest_point_query(bvh, verts, queries, max_dist2=math.inf, *, point=True, 
     _call("mg_closest_point_query", _ptr(bvh.buf), bvh.nbytes, bvh.n, _ptr(verts), verts.shape[1],
           _ptr(queries), nq, float(max_dist2), _ptr(o["face"]), _ptr(o.get("point")), _ptr(o.get("bary")),
           _ptr(o.get("dist2")), _ptr(o.get("normal")),
-          _opts(kernel, batch, seed, order, counters, _queue(dynamic, queries.device), _hint(hint, nq)), _stream())
+          _opts(kernel, batch, seed, order, counters, _queue(dynamic, queries.device), _hint(hint, nq),
+                waves=waves), _stream())
     return o
 
 

@@ -91,18 +91,20 @@ def _tune(key, run, orders, candidates, reps, use_cache):
     return res
 
 
-def tune_closest(bvh, verts, queries, *, order=None, normal=False, reps=5, use_cache=True, candidates=None):
+def tune_closest(bvh, verts, queries, *, order=None, normal=False, reps=5, use_cache=True, candidates=None,
+                 waves=0):
     """Best traversal options for mg_closest_point_query on this BVH and query set.
 
     order: an optional processing order to consider besides the given one (e.g.
     query_order(queries)); the result's "order" is "given" or "order".  Returns
     {"kernel", "batch", "seed", "order", "ms", "timings"}; options(res, order)
-    gives the keyword arguments for closest_point_query.
+    gives the keyword arguments for closest_point_query.  waves: the batch
+    kernel's register allocation to time (0: by launch size, as the plain call).
     """
     orders = {"given": None} if order is None else {"given": None, "order": order}
-    key = _key("closest", bvh, queries, order is not None, f"|normal={int(normal)}")
+    key = _key("closest", bvh, queries, order is not None, f"|normal={int(normal)}" + (f"|waves={waves}" if waves else ""))
     out = api.closest_point_query(bvh, verts, queries, normal=normal)
-    run = lambda **kw: api.closest_point_query(bvh, verts, queries, normal=normal, out=out, **kw)
+    run = lambda **kw: api.closest_point_query(bvh, verts, queries, normal=normal, out=out, waves=waves, **kw)
     return _tune(key, run, orders, candidates, reps, use_cache)
 
 
@@ -130,8 +132,8 @@ def tune_batch(plan, reps=3, use_cache=True):
     """Choose the batched launch's options and apply them to plan (a BatchPlan).
 
     Per scene: queries per wave and seed descent, by timing the plain
-    closest-point traversal (the same device code) of the scene's queries on
-    its frame 0.  Plan-wide: the Gaussian and query tile sizes, by timing whole
+    closest-point traversal (the same device code, with the four-wave register
+    allocation of the batched kernel) of the scene's queries on its frame 0.  Plan-wide: the Gaussian and query tile sizes, by timing whole
     runs of the plan.  Returns {"per_scene", "gauss_tile", "query_tile", "ms",
     "timings"} and leaves the plan configured with the best choice.
     """
@@ -140,7 +142,7 @@ def tune_batch(plan, reps=3, use_cache=True):
         V = sc["frames"][0].contiguous()
         bvh = api.lbvh_build(V, sc["faces"])
         r = tune_closest(bvh, V, sc["queries"], normal=True, reps=reps, use_cache=use_cache,
-                         candidates=BATCH_CANDIDATES)
+                         candidates=BATCH_CANDIDATES, waves=4)
         per_scene.append({"batch": r["batch"], "seed": r["seed"]})
     sizes = ",".join(f"{s['faces'].shape[1]}x{s['frames'].shape[0]}x{s['gface'].shape[0]}x{s['queries'].shape[1]}"
                      for s in plan.scenes)

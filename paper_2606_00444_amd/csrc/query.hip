@@ -338,11 +338,14 @@ mg_status launch_batch_variant(const QueryArgs &a, hipStream_t s) {
 // four waves on every SIMD (256 CUs x 4 SIMDs x 4 waves = 4,096 waves): 1M queries
 // in batches of 16 ran 7% faster, while launches that fit in four waves per SIMD
 // ran up to 2% slower with it.
+// waves: 0 by that rule, 4 or 5 forced (the batched launch's tuner times the
+// plain traversal with the four-wave allocation its own kernel has).
 template <bool kTri, int M>
-mg_status launch_batch(const QueryArgs &a, hipStream_t s) {
+mg_status launch_batch(const QueryArgs &a, int waves, hipStream_t s) {
     constexpr int64_t kFourWaveSlots = 256 * 4 * 4;
     if constexpr (kTri)
-        if ((a.nq + M - 1) / M > kFourWaveSlots) return launch_batch_variant<kTri, M, 5>(a, s);
+        if (waves == 5 || (waves == 0 && (a.nq + M - 1) / M > kFourWaveSlots))
+            return launch_batch_variant<kTri, M, 5>(a, s);
     return launch_batch_variant<kTri, M, 1>(a, s);
 }
 
@@ -350,6 +353,7 @@ template <bool kTri>
 mg_status launch_traverse(QueryArgs a, const mg_query_options *opts, hipStream_t s) {
     int kernel, batch;
     resolve(opts, a.nq, kernel, batch, a.seed);
+    const int waves = opts ? opts->waves : 0;
     a.order = opts ? opts->order : nullptr;
     a.counters = opts ? reinterpret_cast<unsigned long long *>(opts->counters) : nullptr;
     a.queue = opts ? opts->queue : nullptr;
@@ -359,12 +363,12 @@ mg_status launch_traverse(QueryArgs a, const mg_query_options *opts, hipStream_t
         return launch_status();
     }
     switch (batch) {
-        case 1: return launch_batch<kTri, 1>(a, s);
-        case 2: return launch_batch<kTri, 2>(a, s);
-        case 4: return launch_batch<kTri, 4>(a, s);
-        case 8: return launch_batch<kTri, 8>(a, s);
-        case 16: return launch_batch<kTri, 16>(a, s);
-        case 32: return launch_batch<kTri, 32>(a, s);
+        case 1: return launch_batch<kTri, 1>(a, waves, s);
+        case 2: return launch_batch<kTri, 2>(a, waves, s);
+        case 4: return launch_batch<kTri, 4>(a, waves, s);
+        case 8: return launch_batch<kTri, 8>(a, waves, s);
+        case 16: return launch_batch<kTri, 16>(a, waves, s);
+        case 32: return launch_batch<kTri, 32>(a, waves, s);
         default: return MG_ERR_INVALID_ARGUMENT;
     }
 }
@@ -372,6 +376,7 @@ mg_status launch_traverse(QueryArgs a, const mg_query_options *opts, hipStream_t
 inline bool bad_options(const mg_query_options *o) {
     if (!o) return false;
     if (o->kernel < MG_QUERY_AUTO || o->kernel > MG_QUERY_BATCH) return true;
+    if (o->waves != 0 && o->waves != 4 && o->waves != 5) return true;
     return !(o->batch == 0 || o->batch == 1 || o->batch == 2 || o->batch == 4 || o->batch == 8 || o->batch == 16 ||
              o->batch == 32);
 }

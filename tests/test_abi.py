@@ -74,6 +74,12 @@ def test_argument_errors_before_any_hip_call(lib):
     bad.kernel, bad.batch = 2, 3          # batch must be 0, 1, 2, 4, 8, 16 or 32
     assert lib.mg_closest_point_query(fake, 1 << 20, 100, fake, 3, fake, 5, ctypes.c_float(1.0), fake, None, None,
                                       None, None, ctypes.byref(bad), None) == 1
+    bad.batch, bad.waves = 16, 3          # waves must be 0, 4 or 5
+    assert lib.mg_closest_point_query(fake, 1 << 20, 100, fake, 3, fake, 5, ctypes.c_float(1.0), fake, None, None,
+                                      None, None, ctypes.byref(bad), None) == 1
+    from paper_2606_00444_amd import api
+    with pytest.raises(ValueError):
+        api._opts("batch", 16, waves=6)
     assert lib.mg_vertex_buffer_update(fake, 4, 10, 4, fake, None) == 1                 # k out of range
     assert lib.mg_adam_step(fake, fake, fake, fake, 10, 0, ctypes.c_float(1e-3), ctypes.c_float(0.9),
                             ctypes.c_float(0.999), ctypes.c_float(1e-8), None) == 1

@@ -209,6 +209,24 @@ def test_c5_large_sampled(device, kernel, batch):
     assert np.isfinite(host(got["dist2"])).all()
 
 
+@pytest.mark.parametrize("batch", [2, 8, 16])
+def test_register_allocations_agree(device, batch):
+    """The batch kernel's four- and five-wave register allocations (forced, and chosen
+    by launch size) give bitwise the same results, which match the oracle."""
+    import paper_2606_00444_amd as mg
+    import torch
+    sc = make_config(2, small=True)
+    V = sc.frames([11])[0]
+    Vd, F, q = dev(V, device), dev(sc.faces, device), dev(sc.queries, device)
+    bvh = mg.lbvh_build(Vd, F)
+    runs = {w: mg.closest_point_query(bvh, Vd, q, normal=True, kernel="batch", batch=batch, seed=True, waves=w)
+            for w in (0, 4, 5)}
+    for w in (4, 5):
+        for k in ("face", "dist2", "point", "bary", "normal"):
+            assert torch.equal(runs[w][k], runs[0][k]), (w, k)
+    check_closest(runs[5], V, sc.faces, sc.queries)
+
+
 @pytest.mark.parametrize("kernel,batch", [("lane", 0), ("batch", 8), ("seeded", 4)])
 def test_query_order_and_counters(device, kernel, batch):
     import paper_2606_00444_amd as mg
