@@ -14,7 +14,6 @@ Dynamic Mesh-Gaussian Reconstructions", arXiv 2606.00444):
              triangle-frame rotation, covariance (Sec. 3.2 dual representation;
              the paper gives no binding formula, so the reading is ours and is
              pinned only by invariants - parity of the formula itself is unpinned).
-             Per-face normals computed on demand (Sec. 3.4 step 3).
 * morton     30-bit Morton codes of face centroids defined in IEEE binary32, and
              the stable sort (acceleration structure built once from the template
              faces, Sec. 3.4 Initialization; LBVH construction after Karras 2012).
@@ -23,7 +22,8 @@ Dynamic Mesh-Gaussian Reconstructions", arXiv 2606.00444):
              built from F_0 are reused for all frames; O(N_v) per frame).
 * closest    closest point on a triangle (Ericson 2005, Voronoi regions) and on a
              mesh: NearestSurface with barycentric interpolation (Sec. 3.3, Eq. 2),
-             read as the single nearest face (k = 1).
+             read as the single nearest face (k = 1), with the winning face's unit
+             normal computed on demand (Sec. 3.4 step 3).
 * losses     mean squared point-to-mesh distance, two-sided Chamfer distance
              (Sec. 4.2 uses CD as a metric without a formula: squared distances,
              means, both directions, no factor 1/2), and their gradients with

@@ -43,12 +43,3 @@ def step(x, v, verts, faces, dt, g, radius, restitution):
     v = np.where(hit, v - (1.0 + restitution) * vn * nh, v)
     return x, v, contact
 
-
-def run(x, v, frames, faces, dt, g, radius, restitution):
-    """Steps over the mesh poses frames [T][3][V]: returns the states [T+1] of x and v."""
-    xs, vs = [np.asarray(x, np.float64)], [np.asarray(v, np.float64)]
-    for V in frames:
-        nx_, nv_, _ = step(xs[-1], vs[-1], V, faces, dt, g, radius, restitution)
-        xs.append(nx_)
-        vs.append(nv_)
-    return np.stack(xs), np.stack(vs)

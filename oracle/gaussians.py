@@ -47,16 +47,6 @@ def triangle_frame(v0, v1, v2):
     return R, nh, deg
 
 
-def face_normals(verts, faces, face_ids=None):
-    """On-demand unit normals of the given faces (all faces if None), zero if degenerate."""
-    V = _aos(verts)
-    F = np.asarray(faces).T
-    if face_ids is not None:
-        F = F[np.asarray(face_ids)]
-    _, nh, _ = triangle_frame(V[F[:, 0]], V[F[:, 1]], V[F[:, 2]])
-    return nh
-
-
 def quat_to_matrix(q):
     """Rotation matrices [N,3,3] of Hamilton quaternions q [N,4] = (w, x, y, z) (unit)."""
     w, x, y, z = q[:, 0], q[:, 1], q[:, 2], q[:, 3]
