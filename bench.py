@@ -82,8 +82,14 @@ def make_targets(cfg, ts):
     workers = max(1, min(16, len(ts), os.cpu_count() or 1))
     if workers == 1:
         return [_target_job((cfg, t)) for t in ts]
-    with mp.get_context("fork").Pool(workers) as pool:
-        return pool.map(_target_job, [(cfg, t) for t in ts])
+    # close and join (not the context manager's terminate): the workers exit on their own
+    pool = mp.get_context("fork").Pool(workers)
+    try:
+        out = pool.map(_target_job, [(cfg, t) for t in ts])
+    finally:
+        pool.close()
+        pool.join()
+    return out
 
 
 def source_hash(files):

@@ -186,9 +186,11 @@ typedef struct mg_lbvh_header {
     int32_t prim_kind;
     int32_t status;        /* device-side error word, 0 = fine; bits: 4 inconsistent
                               tree, 8 bad refit schedule, 16 a query found an id
-                              without a leaf or a bounded wait ran out (its
-                              results may be wrong) */
-    int32_t reserved0;
+                              without a leaf or a bounded wait ran out, 32 a refit
+                              or query was given a vertex count other than the
+                              build's, 64 a traversal stack overflowed (with 16,
+                              32 or 64 set, results may be wrong) */
+    int32_t n_verts;       /* vertex count of the build (the points for MG_PRIM_POINTS) */
     float root_lo[3];      /* root box (the only box not stored in a node record) */
     float pad0;
     float root_hi[3];
@@ -238,7 +240,12 @@ mg_status mg_lbvh_build(const float *verts, int32_t n_verts, const int32_t *face
                         void *stream);
 
 /* Refit in place: recompute every box of a built BVH for new vertex positions
- * (same n_prims and prim_kind as the build; topology unchanged).  Two
+ * (same n_prims and prim_kind as the build; topology unchanged).  verts must
+ * hold exactly the n_verts of the build: the faces stored at build time index
+ * them.  The refit and every query compare n_verts with the build's
+ * (header.n_verts) and set status bit 32 when they differ; vertex ids are then
+ * clamped into [0, n_verts), so a wrong count gives wrong boxes and results but
+ * never a read outside the caller's array.  Two
  * kernels: a workgroup per subtree, then one workgroup for the top nodes.
  * Refits (and builds) of one BVH must not run concurrently: they share its
  * scratch sections. */
@@ -521,7 +528,8 @@ mg_status mg_batch_plan_size(const mg_batch_scene *scenes, int32_t n_scenes, siz
  * NULL); plan is a device buffer of mg_batch_plan_size bytes.  Copies the
  * table with the stream and synchronises it (initialisation only).  Every
  * scene needs n_faces >= 1, n_frames >= 1 and a built BVH over exactly its
- * faces; the BVH must not be rebuilt between plan_init and the runs. */
+ * faces and n_verts vertices (else MG_ERR_TOPOLOGY_MISMATCH); the BVH must not
+ * be rebuilt between plan_init and the runs. */
 mg_status mg_batch_plan_init(const mg_batch_scene *scenes, int32_t n_scenes, const mg_batch_options *opts,
                              void *plan, size_t plan_bytes, void *stream);
 

@@ -38,6 +38,14 @@ class LbvhLayout(ctypes.Structure):
                                    "off_top_box", "off_top_scratch", "off_inv_prim")]
 
 
+class LbvhHeader(ctypes.Structure):
+    _fields_ = [("n_prims", I32), ("prim_kind", I32), ("status", I32), ("n_verts", I32),
+                ("root_lo", ctypes.c_float * 3), ("pad0", ctypes.c_float), ("root_hi", ctypes.c_float * 3),
+                ("pad1", ctypes.c_float), ("quant_lo", ctypes.c_float * 3), ("quant_scale", ctypes.c_float * 3),
+                ("bounds_enc", ctypes.c_uint32 * 6), ("tile_counter", ctypes.c_uint32 * 4), ("chunk_log2", I32),
+                ("n_top", I32), ("n_sub", I32), ("reserved", I32 * 9)]
+
+
 class QueryOptions(ctypes.Structure):
     _fields_ = [("kernel", I32), ("batch", I32), ("seed", I32), ("warm", I32), ("order", P),
                 ("counters", P), ("queue", P), ("hint", P), ("waves", I32)]

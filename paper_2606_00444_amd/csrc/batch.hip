@@ -74,7 +74,8 @@ inline mg_status read_schedule(const mg_batch_scene &s, Schedule &S) {
     S.n_top = hdr.n_top;
     S.n_sub = hdr.n_sub;
     S.chunk_log2 = hdr.chunk_log2;
-    if (hdr.n_prims != s.n_faces || hdr.prim_kind != MG_PRIM_TRIANGLES || hdr.status != 0)
+    if (hdr.n_prims != s.n_faces || hdr.n_verts != s.n_verts || hdr.prim_kind != MG_PRIM_TRIANGLES ||
+        hdr.status != 0)
         return MG_ERR_TOPOLOGY_MISMATCH;
     if (S.n_top < 0 || S.n_top >= s.n_faces || S.n_sub < 1 || S.n_sub > s.n_faces)
         return MG_ERR_INVALID_ARGUMENT;
@@ -294,7 +295,8 @@ __device__ __noinline__ void item_query(PlanHeader *h, int si, int64_t t, int64_
     }
     const int64_t q0 = k * P.query_tile;
     const int64_t q1 = q0 + P.query_tile < q.nq ? q0 + P.query_tile : q.nq;
-    batch_loop<true, M>(q, q0, static_cast<int64_t>(kBatchWaves) * M, q1, *reinterpret_cast<BatchLds<M> *>(smem));
+    batch_loop<true, M, false>(q, q0, static_cast<int64_t>(kBatchWaves) * M, q1,
+                               *reinterpret_cast<BatchLds<M> *>(smem));
     __builtin_amdgcn_s_waitcnt(0);          // this wave's stores have completed
     __syncthreads();
     if (threadIdx.x == 0) __hip_atomic_fetch_add(&query_done[qd], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

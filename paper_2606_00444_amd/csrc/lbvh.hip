@@ -104,7 +104,7 @@ inline T *at(void *base, int64_t off) {
 // ------------------------------------------------------------------ kernels
 
 __global__ void build_init_kernel(mg_lbvh_header *hdr, uint32_t *hist, uint32_t *lookback,
-                                  int64_t n_lookback, int n, int kind, int chunk_log2) {
+                                  int64_t n_lookback, int n, int nv, int kind, int chunk_log2) {
     const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     if (hist != nullptr)          // no sort scratch when there are no primitives
@@ -113,6 +113,7 @@ __global__ void build_init_kernel(mg_lbvh_header *hdr, uint32_t *hist, uint32_t 
         for (int64_t i = tid; i < n_lookback; i += stride) lookback[i] = 0;
     if (tid == 0) {
         hdr->n_prims = n;
+        hdr->n_verts = nv;
         hdr->prim_kind = kind;
         hdr->status = 0;
         for (int k = 0; k < 3; ++k) {
@@ -602,6 +603,7 @@ mg_status launch_refit(const float *verts, int64_t nv, void *bvh, int64_t n, int
     mg_lbvh_header *hdr = at<mg_lbvh_header>(bvh, L.off_header);
     a.root = hdr->root_lo;
     a.status = &hdr->status;
+    a.hdr_nv = &hdr->n_verts;
     a.n_top = &hdr->n_top;
     a.n_sub = &hdr->n_sub;
     a.n = n;
@@ -663,7 +665,7 @@ extern "C" mg_status mg_lbvh_build(const float *verts, int32_t n_verts, const in
     uint32_t *lookback = n ? at<uint32_t>(ws, W.lookback) : nullptr;
     const int64_t n_lookback = 4 * 256 * W.tiles;
     hipLaunchKernelGGL(build_init_kernel, dim3(n_lookback > 65536 ? 256 : 16), dim3(256), 0, s, hdr,
-                       hist, lookback, n_lookback, n_prims, prim_kind, chunk_log2_for(n_prims));
+                       hist, lookback, n_lookback, n_prims, n_verts, prim_kind, chunk_log2_for(n_prims));
     if (launch_status() != MG_OK) return MG_ERR_HIP;
     if (n == 0) return MG_OK;
     const int32_t *fz = prim_kind == MG_PRIM_TRIANGLES ? faces : nullptr;

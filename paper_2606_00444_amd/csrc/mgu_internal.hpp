@@ -59,10 +59,45 @@ __device__ __forceinline__ f3 fmax3(f3 a, f3 b) { return f3{fmaxf(a.x, b.x), fma
 __device__ __forceinline__ f3 load3(const float *__restrict__ p, int64_t n, int64_t i) {
     return f3{p[i], p[n + i], p[2 * n + i]};
 }
+// Vertex i of [3][n] through an id stored in a BVH at build time, clamped into
+// [0, n): a caller that passes fewer vertices than the build reads wrong values
+// (and is told so by the BVH's status word) but never outside its array.
+__device__ __forceinline__ f3 vload(const float *__restrict__ p, int64_t n, int64_t i) {
+    i = static_cast<uint64_t>(i) < static_cast<uint64_t>(n) ? i : (i < 0 ? 0 : n - 1);
+    return load3(p, n, i);
+}
 __device__ __forceinline__ void store3(float *__restrict__ p, int64_t n, int64_t i, f3 v) {
     p[i] = v.x;
     p[n + i] = v.y;
     p[2 * n + i] = v.z;
+}
+
+// Dot product with explicit fused multiply-adds.  The closest-point, normal and
+// re-pose arithmetic below is written with contraction off and explicit fmaf
+// (or separately rounded products), so its rounding is fixed by the source and
+// not by the compiler's choice of where to fuse at each inlined call site: the
+// brute-force kernel, every traversal variant and the batched kernel then give
+// bitwise the same distances, points and normals for the same face.
+__device__ __forceinline__ float fdot(f3 a, f3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
+
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// The point (1 - w1 - w2) a + w1 b + w2 c.
+__device__ __forceinline__ f3 tri_point(f3 a, f3 b, f3 c, float w1, float w2) {
+#pragma clang fp contract(off)
+    const float w0 = (1.0f - w1) - w2;
+    return f3{fmaf(w2, c.x, fmaf(w1, b.x, w0 * a.x)), fmaf(w2, c.y, fmaf(w1, b.y, w0 * a.y)),
+              fmaf(w2, c.z, fmaf(w1, b.z, w0 * a.z))};
+}
+
+__device__ __forceinline__ float seg_closest(f3 p, f3 a, f3 b, float &t) {
+#pragma clang fp contract(off)
+    const f3 ab = b - a;
+    const float den = fdot(ab, ab);
+    t = den > 0.0f ? fdot(p - a, ab) * rcp(den) : 0.0f;
+    t = fminf(fmaxf(t, 0.0f), 1.0f);
+    const f3 d = p - f3{fmaf(t, ab.x, a.x), fmaf(t, ab.y, a.y), fmaf(t, ab.z, a.z)};
+    return fdot(d, d);
 }
 
 // Closest point on triangle abc to p by Voronoi regions (Ericson 2005,
@@ -77,50 +112,39 @@ __device__ __forceinline__ void store3(float *__restrict__ p, int64_t n, int64_t
 // every p) and nothing else that reaches it (d3 = 0 past vertex B means d4 > 0, so
 // vc = d1 d4 > 0 unless d1 = 0).  Then a == b ends in vertex A, vertex C or edge AC,
 // and b == c or a == c in vertex A, vertex B or edge AB.
-__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-
-
-__device__ __forceinline__ float seg_closest(f3 p, f3 a, f3 b, float &t) {
-    f3 ab = b - a;
-    float den = dot(ab, ab);
-    t = den > 0.0f ? dot(p - a, ab) * rcp(den) : 0.0f;
-    t = fminf(fmaxf(t, 0.0f), 1.0f);
-    f3 d = p - (a + t * ab);
-    return dot(d, d);
-}
-
 __device__ __forceinline__ float tri_closest(f3 p, f3 a, f3 b, f3 c, float &w1, float &w2) {
-    f3 ab = b - a, ac = c - a, ap = p - a;
-    float d1 = dot(ab, ap), d2 = dot(ac, ap);
+#pragma clang fp contract(off)
+    const f3 ab = b - a, ac = c - a, ap = p - a;
+    const float d1 = fdot(ab, ap), d2 = fdot(ac, ap);
     if (d1 <= 0.0f && d2 <= 0.0f) {
         w1 = 0.0f; w2 = 0.0f;
     } else {
-        f3 bp = p - b;
-        float d3 = dot(ab, bp), d4 = dot(ac, bp);
-        float vc = det2(d1, d4, d3, d2);
+        const f3 bp = p - b;
+        const float d3 = fdot(ab, bp), d4 = fdot(ac, bp);
+        const float vc = det2(d1, d4, d3, d2);
         if (d3 >= 0.0f && d4 <= d3) {
             w1 = 1.0f; w2 = 0.0f;
         } else if (vc <= 0.0f && d1 >= 0.0f && d3 < 0.0f) {
             w1 = d1 * rcp(d1 - d3); w2 = 0.0f;
         } else {
-            f3 cp = p - c;
-            float d5 = dot(ab, cp), d6 = dot(ac, cp);
-            float vb = det2(d5, d2, d1, d6);
-            float va = det2(d3, d6, d5, d4);
-            float e43 = d4 - d3, e56 = d5 - d6;
+            const f3 cp = p - c;
+            const float d5 = fdot(ab, cp), d6 = fdot(ac, cp);
+            const float vb = det2(d5, d2, d1, d6);
+            const float va = det2(d3, d6, d5, d4);
+            const float e43 = d4 - d3, e56 = d5 - d6;
             if (d6 >= 0.0f && d5 <= d6) {
                 w1 = 0.0f; w2 = 1.0f;
             } else if (vb <= 0.0f && d2 >= 0.0f && d6 <= 0.0f) {
-                float den = d2 - d6;
+                const float den = d2 - d6;
                 w1 = 0.0f; w2 = den != 0.0f ? d2 * rcp(den) : 0.0f;
             } else if (va <= 0.0f && e43 >= 0.0f && e56 >= 0.0f) {
-                float den = e43 + e56;
-                float t = den != 0.0f ? e43 * rcp(den) : 0.0f;
+                const float den = e43 + e56;
+                const float t = den != 0.0f ? e43 * rcp(den) : 0.0f;
                 w1 = 1.0f - t; w2 = t;
             } else {
-                float den = va + vb + vc;
+                const float den = (va + vb) + vc;
                 if (den > 0.0f) {
-                    float r = rcp(den);
+                    const float r = rcp(den);
                     w1 = vb * r; w2 = vc * r;
                 } else {
                     float t, best = seg_closest(p, a, b, t);
@@ -133,22 +157,20 @@ __device__ __forceinline__ float tri_closest(f3 p, f3 a, f3 b, f3 c, float &w1, 
             }
         }
     }
-    float w0 = 1.0f - w1 - w2;
-    f3 q = f3{w0 * a.x + w1 * b.x + w2 * c.x, w0 * a.y + w1 * b.y + w2 * c.y,
-              w0 * a.z + w1 * b.z + w2 * c.z};
-    f3 d = p - q;
-    return dot(d, d);
+    const f3 d = p - tri_point(a, b, c, w1, w2);
+    return fdot(d, d);
 }
 
 // Unit normal of triangle abc from its stored winding; zero when |ab| == 0 or
 // |ab x ac| == 0 (degenerate; exact for repeated vertices, see cross_rounded).
 __device__ __forceinline__ f3 tri_normal(f3 a, f3 b, f3 c) {
-    f3 e1 = b - a;
-    f3 n = cross_rounded(e1, c - a);
-    float l1 = dot(e1, e1), ln = dot(n, n);
+#pragma clang fp contract(off)
+    const f3 e1 = b - a;
+    const f3 n = cross_rounded(e1, c - a);
+    const float l1 = fdot(e1, e1), ln = fdot(n, n);
     if (l1 == 0.0f || ln == 0.0f) return f3{0.0f, 0.0f, 0.0f};
-    float r = 1.0f / sqrtf(ln);
-    return r * n;
+    const float r = 1.0f / sqrtf(ln);
+    return f3{r * n.x, r * n.y, r * n.z};
 }
 
 // Squared distance from p to an axis-aligned box.

@@ -6,11 +6,11 @@
 // face normal is computed on demand from the three vertices of the winning
 // face (Sec. 3.4 step 3), never stored.
 //
-// Pruning: a child is expanded when its box distance is <= best * (1 + 2^-20);
-// the slack keeps a float32 rounding of a box distance from pruning a face whose
-// float32 distance ties the best (ties go to the lowest original id, carried in
-// the node record beside each leaf child).  Leaf children hold their triangle,
-// so a leaf is tested with the data of the record that referenced it.
+// Pruning: a child is expanded when its lower bound is <= prune_bound(best)
+// (traverse.hpp), a slack that keeps faces whose float32 distance ties the
+// best, so ties go to the lowest original id (carried in the node record beside
+// each leaf child) in every traversal.  Leaf children hold their triangle, so a
+// leaf is tested with the data of the record that referenced it.
 //
 // Two traversals (chosen per call, see mg_query_options):
 //  * lane:  one query per lane, depth-first, nearer child first; stack in LDS
@@ -26,6 +26,8 @@
 //           are expanded 64 at a time instead of one lane walking them serially.
 #include "traverse.hpp"
 
+#include <atomic>
+
 namespace mgu {
 namespace {
 
@@ -35,6 +37,7 @@ __global__ __launch_bounds__(kLaneBlock) void traverse_lane_kernel(QueryArgs a) 
     __shared__ int32_t s_stack[kLdsStack][kLaneBlock];
     int32_t deep[kMaxStack - kLdsStack];
     const int lane = threadIdx.x;
+    check_vertex_count(a);
     const int64_t pos = static_cast<int64_t>(blockIdx.x) * kLaneBlock + lane;
     if (pos >= a.nq) return;
     const int64_t q = query_at(a, pos);
@@ -68,7 +71,8 @@ __global__ __launch_bounds__(kLaneBlock) void traverse_lane_kernel(QueryArgs a) 
         const f3 rlo = f3{a.root[0], a.root[1], a.root[2]};
         const f3 rhi = f3{a.root[4], a.root[5], a.root[6]};
         int sp = 0;
-        int32_t node = box_dist2(p, rlo, rhi) <= best * kPruneSlack ? 0 : -1;
+        const float qm = qnorm1(p);
+        int32_t node = box_dist2(p, rlo, rhi) <= prune_bound(best, qm) ? 0 : -1;
         // each internal node is visited at most once in a valid tree: the step cap
         // and the reference checks keep a corrupted buffer from looping or faulting
         for (int64_t step = 0; node >= 0 && node < a.n - 1 && step < a.n + 64; ++step) {
@@ -78,11 +82,11 @@ __global__ __launch_bounds__(kLaneBlock) void traverse_lane_kernel(QueryArgs a) 
             if (lref >= a.n - 1 || rref >= a.n - 1 || ~lref >= a.n || ~rref >= a.n) break;
             ++n_exp;
             n_lbox += (lref < 0) + (rref < 0);
-            if (lref < 0 && leaf_box_dist2<kTri>(p, l0, l1, l2) <= best * kPruneSlack)
+            if (lref < 0 && leaf_box_dist2<kTri>(p, l0, l1, l2) <= prune_bound(best, qm))
                 consider(leaf_dist2<kTri>(p, l0, l1, l2), __float_as_int(l1.w), ~lref);
-            if (rref < 0 && leaf_box_dist2<kTri>(p, r0, r1, r2) <= best * kPruneSlack)
+            if (rref < 0 && leaf_box_dist2<kTri>(p, r0, r1, r2) <= prune_bound(best, qm))
                 consider(leaf_dist2<kTri>(p, r0, r1, r2), __float_as_int(r1.w), ~rref);
-            const float bound = best * kPruneSlack;
+            const float bound = prune_bound(best, qm);
             const float dl = lref >= 0 ? child_bound<kTri>(p, dq, l0, l1, l2) : INFINITY;
             const float dr = rref >= 0 ? child_bound<kTri>(p, dq, r0, r1, r2) : INFINITY;
             const bool gl = lref >= 0 && dl <= bound, gr = rref >= 0 && dr <= bound;
@@ -92,6 +96,7 @@ __global__ __launch_bounds__(kLaneBlock) void traverse_lane_kernel(QueryArgs a) 
                 node = left_first ? lref : rref;
                 if (sp < kLdsStack) s_stack[sp][lane] = far;
                 else if (sp < kMaxStack) deep[sp - kLdsStack] = far;
+                else atomicOr(a.status, 64);   // past the depth bound of a valid tree
                 sp = sp < kMaxStack ? sp + 1 : sp;
             } else if (gl) {
                 node = lref;
@@ -109,13 +114,14 @@ __global__ __launch_bounds__(kLaneBlock) void traverse_lane_kernel(QueryArgs a) 
     if (a.counters) add_counters(a, n_exp, n_lbox, n_lex, 1);
 }
 
-// kMinWaves: the fewest waves per SIMD the register allocation must allow (1:
-// the compiler's choice, 4 for the triangle kernel; 5 trades a few spills
-// outside the round loop for a fifth resident wave, which pays only when the
-// launch has more waves than four per SIMD hold).
+// kMinWaves: the fewest waves per SIMD the register allocation must allow (4:
+// at most 128 VGPRs, what the triangle kernel needs without spills; 5 trades a
+// few spills outside the round loop for a fifth resident wave, which pays only
+// when the launch has more waves than four per SIMD hold).
 template <bool kTri, int M, int kMinWaves>
 __global__ __launch_bounds__(64 * kBatchWaves) __attribute__((amdgpu_waves_per_eu(kMinWaves))) void traverse_batch_kernel(QueryArgs a) {
     __shared__ BatchLds<M> lds;
+    check_vertex_count(a);
     const int64_t per_block = static_cast<int64_t>(kBatchWaves) * M;
     batch_loop<kTri, M>(a, static_cast<int64_t>(blockIdx.x) * per_block, static_cast<int64_t>(gridDim.x) * per_block,
                         a.nq, lds);
@@ -135,6 +141,7 @@ __global__ __launch_bounds__(kLaneBlock) void knn_lane_kernel(QueryArgs a, int k
     __shared__ int32_t s_stack[kLdsStack][kLaneBlock];
     int32_t deep[kMaxStack - kLdsStack];
     const int lane = threadIdx.x;
+    check_vertex_count(a);
     const int64_t q = static_cast<int64_t>(blockIdx.x) * kLaneBlock + lane;
     if (q >= a.nq) return;
     const f3 p = load3(a.queries, a.nq, q);
@@ -179,7 +186,8 @@ __global__ __launch_bounds__(kLaneBlock) void knn_lane_kernel(QueryArgs a, int k
         const f3 rlo = f3{a.root[0], a.root[1], a.root[2]};
         const f3 rhi = f3{a.root[4], a.root[5], a.root[6]};
         int sp = 0;
-        int32_t node = box_dist2(p, rlo, rhi) <= kth() * kPruneSlack ? 0 : -1;
+        const float qm = qnorm1(p);
+        int32_t node = box_dist2(p, rlo, rhi) <= prune_bound(kth(), qm) ? 0 : -1;
         for (int64_t step = 0; node >= 0 && node < a.n - 1 && step < a.n + 64; ++step) {
             const float4 *rec = a.nodes + 6 * static_cast<int64_t>(node);
             const float4 l0 = rec[0], l1 = rec[1], l2 = rec[2], r0 = rec[3], r1 = rec[4], r2 = rec[5];
@@ -187,11 +195,11 @@ __global__ __launch_bounds__(kLaneBlock) void knn_lane_kernel(QueryArgs a, int k
             if (lref >= a.n - 1 || rref >= a.n - 1 || ~lref >= a.n || ~rref >= a.n) break;
             ++n_exp;
             n_lbox += (lref < 0) + (rref < 0);
-            if (lref < 0 && leaf_box_dist2<true>(p, l0, l1, l2) <= kth() * kPruneSlack)
+            if (lref < 0 && leaf_box_dist2<true>(p, l0, l1, l2) <= prune_bound(kth(), qm))
                 consider(leaf_dist2<true>(p, l0, l1, l2), __float_as_int(l1.w), ~lref);
-            if (rref < 0 && leaf_box_dist2<true>(p, r0, r1, r2) <= kth() * kPruneSlack)
+            if (rref < 0 && leaf_box_dist2<true>(p, r0, r1, r2) <= prune_bound(kth(), qm))
                 consider(leaf_dist2<true>(p, r0, r1, r2), __float_as_int(r1.w), ~rref);
-            const float bound = kth() * kPruneSlack;
+            const float bound = prune_bound(kth(), qm);
             const float dl = lref >= 0 ? child_bound<true>(p, dq, l0, l1, l2) : INFINITY;
             const float dr = rref >= 0 ? child_bound<true>(p, dq, r0, r1, r2) : INFINITY;
             const bool gl = lref >= 0 && dl <= bound, gr = rref >= 0 && dr <= bound;
@@ -201,6 +209,7 @@ __global__ __launch_bounds__(kLaneBlock) void knn_lane_kernel(QueryArgs a, int k
                 node = left_first ? lref : rref;
                 if (sp < kLdsStack) s_stack[sp][lane] = far;
                 else if (sp < kMaxStack) deep[sp - kLdsStack] = far;
+                else atomicOr(a.status, 64);   // past the depth bound of a valid tree
                 sp = sp < kMaxStack ? sp + 1 : sp;
             } else if (gl) {
                 node = lref;
@@ -226,14 +235,12 @@ __global__ __launch_bounds__(kLaneBlock) void knn_lane_kernel(QueryArgs a, int k
         face_k[j * a.nq + q] = ok ? bid[j] : -1;
         if (dist2_k) dist2_k[j * a.nq + q] = ok ? bd[j] : INFINITY;
         if (!ok) continue;
-        const f3 A = load3(a.verts, a.nv, a.leaf_faces[leaf]);
-        const f3 B = load3(a.verts, a.nv, a.leaf_faces[a.n + leaf]);
-        const f3 C = load3(a.verts, a.nv, a.leaf_faces[2 * a.n + leaf]);
+        const f3 A = vload(a.verts, a.nv, a.leaf_faces[leaf]);
+        const f3 B = vload(a.verts, a.nv, a.leaf_faces[a.n + leaf]);
+        const f3 C = vload(a.verts, a.nv, a.leaf_faces[2 * a.n + leaf]);
         float w1, w2;
         const float d2 = tri_closest(p, A, B, C, w1, w2);
-        const float w0 = 1.0f - w1 - w2;
-        const f3 c = f3{w0 * A.x + w1 * B.x + w2 * C.x, w0 * A.y + w1 * B.y + w2 * C.y,
-                        w0 * A.z + w1 * B.z + w2 * C.z};
+        const f3 c = tri_point(A, B, C, w1, w2);
         if ((d2 == 0.0f || k == 1) && !hit) {   // k = 1: the closest point itself, unweighted
             hit = true;
             on = c;
@@ -272,11 +279,8 @@ __global__ __launch_bounds__(256) void bruteforce_kernel(const float *__restrict
         const f3 C = load3(verts, nv, faces[2 * nf + bf]);
         float w1, w2;
         const float d2 = tri_closest(p, A, B, C, w1, w2);
-        const float w0 = 1.0f - w1 - w2;
         face[q] = static_cast<int32_t>(bf);
-        if (point)
-            store3(point, nq, q, f3{w0 * A.x + w1 * B.x + w2 * C.x, w0 * A.y + w1 * B.y + w2 * C.y,
-                                    w0 * A.z + w1 * B.z + w2 * C.z});
+        if (point) store3(point, nq, q, tri_point(A, B, C, w1, w2));
         if (bary) { bary[q] = w1; bary[nq + q] = w2; }
         if (dist2) dist2[q] = d2;
         if (normal) store3(normal, nq, q, tri_normal(A, B, C));
@@ -334,19 +338,33 @@ mg_status launch_batch_variant(const QueryArgs &a, hipStream_t s) {
     return launch_status();
 }
 
+// Compute units of the current device, read once per device (a partitioned
+// device has fewer than the full chip's 256).
+int device_cus() {
+    static std::atomic<int> cached[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int v = cached[dev].load(std::memory_order_relaxed);
+    if (v > 0) return v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    cached[dev].store(v, std::memory_order_relaxed);
+    return v;
+}
+
 // The triangle kernel takes the five-wave allocation when its batches outnumber
-// four waves on every SIMD (256 CUs x 4 SIMDs x 4 waves = 4,096 waves): 1M queries
-// in batches of 16 ran 7% faster, while launches that fit in four waves per SIMD
-// ran up to 2% slower with it.
+// four waves on every SIMD (CUs x 4 SIMDs x 4 waves; 4,096 on a whole MI355X):
+// 1M queries in batches of 16 ran 7% faster, while launches that fit in four
+// waves per SIMD ran up to 2% slower with it.
 // waves: 0 by that rule, 4 or 5 forced (the batched launch's tuner times the
 // plain traversal with the four-wave allocation its own kernel has).
 template <bool kTri, int M>
 mg_status launch_batch(const QueryArgs &a, int waves, hipStream_t s) {
-    constexpr int64_t kFourWaveSlots = 256 * 4 * 4;
-    if constexpr (kTri)
-        if (waves == 5 || (waves == 0 && (a.nq + M - 1) / M > kFourWaveSlots))
+    if constexpr (kTri) {
+        const int64_t four_wave_slots = static_cast<int64_t>(device_cus()) * 4 * 4;
+        if (waves == 5 || (waves == 0 && (a.nq + M - 1) / M > four_wave_slots))
             return launch_batch_variant<kTri, M, 5>(a, s);
-    return launch_batch_variant<kTri, M, 1>(a, s);
+    }
+    return launch_batch_variant<kTri, M, 4>(a, s);
 }
 
 template <bool kTri>
@@ -406,6 +424,7 @@ extern "C" mg_status mg_closest_point_query(const void *bvh, size_t bvh_bytes, i
     a.prim = cat<int32_t>(bvh, L.off_prim);
     a.inv_prim = cat<int32_t>(bvh, L.off_inv_prim);
     a.status = &const_cast<mg_lbvh_header *>(cat<mg_lbvh_header>(bvh, L.off_header))->status;
+    a.hdr_nv = &cat<mg_lbvh_header>(bvh, L.off_header)->n_verts;
     a.verts = verts; a.nv = n_verts; a.n = n_prims;
     a.queries = queries; a.nq = n_queries; a.maxd2 = max_dist2;
     a.face = face; a.point = point; a.bary = bary; a.dist2 = dist2; a.normal = normal;
@@ -430,6 +449,7 @@ extern "C" mg_status mg_nearest_point_query(const void *bvh, size_t bvh_bytes, i
     a.prim = cat<int32_t>(bvh, L.off_prim);
     a.inv_prim = cat<int32_t>(bvh, L.off_inv_prim);
     a.status = &const_cast<mg_lbvh_header *>(cat<mg_lbvh_header>(bvh, L.off_header))->status;
+    a.hdr_nv = &cat<mg_lbvh_header>(bvh, L.off_header)->n_verts;
     a.verts = points; a.nv = n_prims; a.n = n_prims;
     a.queries = queries; a.nq = n_queries; a.maxd2 = max_dist2;
     a.face = index; a.point = nullptr; a.bary = nullptr; a.dist2 = dist2; a.normal = nullptr;
@@ -470,6 +490,7 @@ extern "C" mg_status mg_knn_surface_query(const void *bvh, size_t bvh_bytes, int
     a.prim = cat<int32_t>(bvh, L.off_prim);
     a.inv_prim = cat<int32_t>(bvh, L.off_inv_prim);
     a.status = &const_cast<mg_lbvh_header *>(cat<mg_lbvh_header>(bvh, L.off_header))->status;
+    a.hdr_nv = &cat<mg_lbvh_header>(bvh, L.off_header)->n_verts;
     a.verts = verts; a.nv = n_verts; a.n = n_prims;
     a.queries = queries; a.nq = n_queries; a.maxd2 = max_dist2;
     a.point = point;

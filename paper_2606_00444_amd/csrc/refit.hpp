@@ -51,6 +51,7 @@ struct RefitArgs {
     uint32_t *top_scratch;        // [kTopStatePlanes][tstride] phase-2 state when T exceeds the LDS capacity
     float *root;                  // root box: lo at [0..2], hi at [4..6]
     int32_t *status;              // error word
+    const int32_t *hdr_nv;        // vertex count of the build (header), or nullptr
     const int32_t *n_top;         // number of top nodes (device)
     const int32_t *n_sub;         // number of subtrees (device)
     int64_t n;
@@ -86,10 +87,6 @@ struct Slab {
     float a, b;
 };
 
-// Dot product with explicit fused multiply-adds (the same rounding wherever
-// it is inlined).
-__device__ __forceinline__ float fdot(f3 a, f3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
-
 // Unit direction of a normal sum by the hardware reciprocal square root (any
 // direction gives a valid slab, since the extents are taken along the stored
 // one; |d| is 1 to about 2^-22, which the traversal's bound allows for).
@@ -114,7 +111,7 @@ __device__ __forceinline__ void box_range(f3 r, f3 lo, f3 hi, float &mn, float &
 __device__ __forceinline__ Slab leaf_slab(f3 x, f3 y, f3 z, f3 lo, f3 hi) {
 #pragma clang fp contract(off)
     Slab S;
-    S.s = cross(y - x, z - x);
+    S.s = cross_rounded(y - x, z - x);
     const f3 d = slab_dir(S.s);
     const float px = fdot(d, x), py = fdot(d, y), pz = fdot(d, z);
     const float e = slab_margin(lo, hi);
@@ -246,14 +243,15 @@ __device__ void refit_subtree(const RefitArgs &a, int64_t k, unsigned char *smem
         L.id = a.prim[i];
         L.tag = a.leaf_parent[i];
         if (kTri) {
-            L.x = load3(a.verts, a.nv, a.leaf_faces[i]);
-            L.y = load3(a.verts, a.nv, a.leaf_faces[a.n + i]);
-            L.z = load3(a.verts, a.nv, a.leaf_faces[2 * a.n + i]);
+            L.x = vload(a.verts, a.nv, a.leaf_faces[i]);
+            L.y = vload(a.verts, a.nv, a.leaf_faces[a.n + i]);
+            L.z = vload(a.verts, a.nv, a.leaf_faces[2 * a.n + i]);
         } else {
-            L.x = L.y = L.z = load3(a.verts, a.nv, L.id);
+            L.x = L.y = L.z = vload(a.verts, a.nv, L.id);
         }
         return L;
     };
+    if (k == 0 && threadIdx.x == 0 && a.hdr_nv && *a.hdr_nv != a.nv) atomicOr(a.status, 32);
     const int64_t i0 = f + threadIdx.x;
     Leaf first{};
     if (i0 <= l) first = load_leaf(i0);

@@ -3,7 +3,9 @@
 // The render representation of the paper's dual representation (Sec. 3.2)
 // follows the fixed-topology physics mesh.  The binding formula is not in the
 // paper; the one implemented here is documented in include/mgu.h
-// (mg_mesh_gaussian_update).
+// (mg_mesh_gaussian_update).  Every function here is written with contraction
+// off and explicit fused multiply-adds, so the plain and the batched kernels
+// (different inline sites) round every output identically.
 #pragma once
 
 #include "mgu_internal.hpp"
@@ -18,12 +20,13 @@ struct Frame {
 };
 
 __device__ __forceinline__ Frame triangle_frame(f3 v0, f3 v1, f3 v2, f3 &e1, f3 &e2, f3 &nraw) {
+#pragma clang fp contract(off)
     Frame F;
     e1 = v1 - v0;
     e2 = v2 - v0;
     nraw = cross_rounded(e1, e2);      // exactly zero for two equal vertices
-    F.l1 = sqrtf(dot(e1, e1));
-    F.ln = sqrtf(dot(nraw, nraw));
+    F.l1 = sqrtf(fdot(e1, e1));
+    F.ln = sqrtf(fdot(nraw, nraw));
     F.degenerate = (F.l1 == 0.0f) || (F.ln == 0.0f);
     if (F.degenerate) {
         F.t = f3{1.0f, 0.0f, 0.0f};
@@ -32,13 +35,14 @@ __device__ __forceinline__ Frame triangle_frame(f3 v0, f3 v1, f3 v2, f3 &e1, f3 
     } else {
         F.t = (1.0f / F.l1) * e1;
         F.n = (1.0f / F.ln) * nraw;
-        F.b = cross(F.n, F.t);
+        F.b = cross_rounded(F.n, F.t);
     }
     return F;
 }
 
 // Row-major 3x3 rotation of a unit Hamilton quaternion (w, x, y, z).
 __device__ __forceinline__ void quat_matrix(float w, float x, float y, float z, float R[9]) {
+#pragma clang fp contract(off)
     R[0] = 1.0f - 2.0f * (y * y + z * z);
     R[1] = 2.0f * (x * y - w * z);
     R[2] = 2.0f * (x * z + w * y);
@@ -53,6 +57,7 @@ __device__ __forceinline__ void quat_matrix(float w, float x, float y, float z, 
 // Shepperd (1978): largest of (trace, R00, R11, R22) selects the component taken
 // from a square root.  Sign: w > 0, or the first non-zero of x, y, z positive.
 __device__ __forceinline__ void shepperd(const float R[9], float q[4]) {
+#pragma clang fp contract(off)
     const float r00 = R[0], r11 = R[4], r22 = R[8];
     const float tr = r00 + r11 + r22;
     int pick = 0;
@@ -98,6 +103,7 @@ struct Local {
 };
 
 __device__ __forceinline__ void load_local(const Inputs &in, int64_t g, Local &L) {
+#pragma clang fp contract(off)
     const int32_t f = in.gface[g];
     const int32_t i0 = in.faces[f], i1 = in.faces[in.nf + f], i2 = in.faces[2 * in.nf + f];
     L.v0 = load3(in.verts, in.nv, i0);
@@ -107,7 +113,7 @@ __device__ __forceinline__ void load_local(const Inputs &in, int64_t g, Local &L
     L.b1 = in.bary[g];
     L.b2 = in.bary[in.ng + g];
     float w = in.qloc[g], x = in.qloc[in.ng + g], y = in.qloc[2 * in.ng + g], z = in.qloc[3 * in.ng + g];
-    float inv = 1.0f / sqrtf(w * w + x * x + y * y + z * z);
+    float inv = 1.0f / sqrtf(fmaf(w, w, fmaf(x, x, fmaf(y, y, z * z))));
     quat_matrix(w * inv, x * inv, y * inv, z * inv, L.Rl);
     // R_f columns t, b, n (identity when degenerate)
     float Rf[9];
@@ -122,7 +128,7 @@ __device__ __forceinline__ void load_local(const Inputs &in, int64_t g, Local &L
     for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-            L.Rg[3 * r + c] = Rf[3 * r] * L.Rl[c] + Rf[3 * r + 1] * L.Rl[3 + c] + Rf[3 * r + 2] * L.Rl[6 + c];
+            L.Rg[3 * r + c] = fmaf(Rf[3 * r], L.Rl[c], fmaf(Rf[3 * r + 1], L.Rl[3 + c], Rf[3 * r + 2] * L.Rl[6 + c]));
 #pragma unroll
     for (int k = 0; k < 3; ++k) L.s2[k] = expf(2.0f * in.lscale[k * in.ng + g]);
     L.off = in.offset ? in.offset[g] : 0.0f;
@@ -134,12 +140,11 @@ __device__ __forceinline__ void load_local(const Inputs &in, int64_t g, Local &L
 __device__ __forceinline__ void repose_store(const Inputs &in, int64_t g, float *__restrict__ mean,
                                              float *__restrict__ quat, float *__restrict__ cov,
                                              float *__restrict__ rot) {
+#pragma clang fp contract(off)
     Local L;
     load_local(in, g, L);
-    const float b0 = 1.0f - L.b1 - L.b2;
-    f3 mu = f3{b0 * L.v0.x + L.b1 * L.v1.x + L.b2 * L.v2.x, b0 * L.v0.y + L.b1 * L.v1.y + L.b2 * L.v2.y,
-               b0 * L.v0.z + L.b1 * L.v1.z + L.b2 * L.v2.z};
-    if (L.off != 0.0f) mu = mu + L.off * L.F.n;
+    f3 mu = tri_point(L.v0, L.v1, L.v2, L.b1, L.b2);
+    if (L.off != 0.0f) mu = f3{fmaf(L.off, L.F.n.x, mu.x), fmaf(L.off, L.F.n.y, mu.y), fmaf(L.off, L.F.n.z, mu.z)};
     const int64_t n = in.ng;
     __builtin_nontemporal_store(mu.x, mean + g);
     __builtin_nontemporal_store(mu.y, mean + n + g);
@@ -154,12 +159,12 @@ __device__ __forceinline__ void repose_store(const Inputs &in, int64_t g, float 
         const float *R = L.Rg;
         float c[6];
         // Sigma_ij = sum_k R_ik s2_k R_jk
-        c[0] = R[0] * R[0] * L.s2[0] + R[1] * R[1] * L.s2[1] + R[2] * R[2] * L.s2[2];
-        c[1] = R[0] * R[3] * L.s2[0] + R[1] * R[4] * L.s2[1] + R[2] * R[5] * L.s2[2];
-        c[2] = R[0] * R[6] * L.s2[0] + R[1] * R[7] * L.s2[1] + R[2] * R[8] * L.s2[2];
-        c[3] = R[3] * R[3] * L.s2[0] + R[4] * R[4] * L.s2[1] + R[5] * R[5] * L.s2[2];
-        c[4] = R[3] * R[6] * L.s2[0] + R[4] * R[7] * L.s2[1] + R[5] * R[8] * L.s2[2];
-        c[5] = R[6] * R[6] * L.s2[0] + R[7] * R[7] * L.s2[1] + R[8] * R[8] * L.s2[2];
+        const float *s2 = L.s2;
+        auto sig = [&](int i, int j) {
+            return fmaf(R[3 * i] * s2[0], R[3 * j], fmaf(R[3 * i + 1] * s2[1], R[3 * j + 1], R[3 * i + 2] * s2[2] * R[3 * j + 2]));
+        };
+        c[0] = sig(0, 0); c[1] = sig(0, 1); c[2] = sig(0, 2);
+        c[3] = sig(1, 1); c[4] = sig(1, 2); c[5] = sig(2, 2);
 #pragma unroll
         for (int k = 0; k < 6; ++k) __builtin_nontemporal_store(c[k], cov + k * n + g);
     }

@@ -53,10 +53,8 @@ __global__ __launch_bounds__(256) void sdf_update_kernel(const float *__restrict
             if (d2 < best) {
                 best = d2;
                 win = f;
-                const float w0 = 1.0f - w1 - w2;
-                const f3 c = f3{w0 * A.x + w1 * B.x + w2 * C.x, w0 * A.y + w1 * B.y + w2 * C.y,
-                                w0 * A.z + w1 * B.z + w2 * C.z};
-                side = dot(p - c, tri_normal(A, B, C)) >= 0.0f ? 1.0f : -1.0f;
+                const f3 c = tri_point(A, B, C, w1, w2);
+                side = fdot(p - c, tri_normal(A, B, C)) >= 0.0f ? 1.0f : -1.0f;
             }
         }
         sdf[v] = side * sqrtf(best);
@@ -109,10 +107,8 @@ __global__ __launch_bounds__(256) void sdf_update_k_kernel(const float *__restri
         }
         float side = 1.0f;
         if (win >= 0) {
-            const float w0 = 1.0f - bw1 - bw2;
-            const f3 c = f3{w0 * bA.x + bw1 * bB.x + bw2 * bC.x, w0 * bA.y + bw1 * bB.y + bw2 * bC.y,
-                            w0 * bA.z + bw1 * bB.z + bw2 * bC.z};
-            side = dot(p - c, tri_normal(bA, bB, bC)) >= 0.0f ? 1.0f : -1.0f;
+            const f3 c = tri_point(bA, bB, bC, bw1, bw2);
+            side = fdot(p - c, tri_normal(bA, bB, bC)) >= 0.0f ? 1.0f : -1.0f;
         }
         sdf[v] = side * sqrtf(best);
         if (face_out) face_out[v] = win;

@@ -1,11 +1,12 @@
 // Closest-point / nearest-point traversal pieces shared by the plain query
 // kernels and the batched persistent kernel.
 //
-// Pruning: a child is expanded when its box distance is <= best * (1 + 2^-20);
-// the slack keeps a float32 rounding of a box distance from pruning a face whose
-// float32 distance ties the best (ties go to the lowest original id, carried in
-// the node record beside each leaf child).  Leaf children hold their triangle,
-// so a leaf is tested with the data of the record that referenced it.
+// Pruning: a child is expanded when its lower bound is <= prune_bound(best):
+// the slack keeps a face whose float32 distance ties the best from being
+// pruned, whatever order the faces are met in, so every traversal returns the
+// lowest original id among the faces at the minimal float32 distance (carried
+// in the node record beside each leaf child).  Leaf children hold their
+// triangle, so a leaf is tested with the data of the record that referenced it.
 #pragma once
 
 #include "mgu_internal.hpp"
@@ -18,6 +19,23 @@ constexpr int kLaneBlock = 64;
 constexpr int kLdsStack = 32;
 constexpr int kMaxStack = 64;
 constexpr float kPruneSlack = 1.0f + 1.0f / 1048576.0f;
+
+// The largest lower bound of a node that may still hold a face whose float32
+// squared distance ties `best`.  A float32 closest point on a well-shaped
+// triangle is off by a few units in the last place of the coordinates'
+// magnitude (about |q|_1 + sqrt(best) near q), so its float32 distance may
+// fall short of the exact one by delta = 2^-18 (|q|_1 + sqrt(best)) - a wide
+// margin - while the box and slab bounds are within a few rounding steps of
+// exact: expanding every node with sqrt(bound) <= sqrt(best) + delta (times
+// 1 + 2^-20 for the bound's own rounding) keeps such faces.  qm = |q|_1.
+__device__ __forceinline__ float prune_bound(float best, float qm) {
+    const float d = __builtin_amdgcn_sqrtf(best);
+    const float e = fmaf(0x1p-18f, qm + d, d);
+    return (e * e) * kPruneSlack;
+}
+
+// |q|_1 of a query point (the magnitude of the prune slack and the slab margin).
+__device__ __forceinline__ float qnorm1(f3 q) { return (fabsf(q.x) + fabsf(q.y)) + fabsf(q.z); }
 
 constexpr int kBatchWaves = 4;          // waves per workgroup of the batch kernel
 constexpr int kBatchCap = 512;          // stack entries before the pop width shrinks
@@ -40,6 +58,7 @@ struct QueryArgs {
     unsigned long long *counters;       // [4] statistics or nullptr
     const int32_t *inv_prim;            // [n] leaf of each original id (id -> position in leaf order)
     int32_t *status;                    // error word of the BVH header
+    const int32_t *hdr_nv;              // vertex count of the build (header), or nullptr
     uint32_t *queue;                    // batch kernel: dynamic batch counter (zeroed before launch) or nullptr
     const int32_t *hint;                // [nq] original id to start each query from, or nullptr
     int coherent;                       // face ids stored and hints loaded device-coherent (batched form)
@@ -51,6 +70,11 @@ struct QueryArgs {
 __device__ __forceinline__ void store_face(const QueryArgs &a, int64_t q, int32_t id) {
     if (a.coherent) __hip_atomic_store(a.face + q, id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else a.face[q] = id;
+}
+
+// The first thread of a launch flags a vertex count that differs from the build's.
+__device__ __forceinline__ void check_vertex_count(const QueryArgs &a) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.hdr_nv && *a.hdr_nv != a.nv) atomicOr(a.status, 32);
 }
 
 // Query processed in position i (order[i], or i); -1 if the order entry is out of range.
@@ -78,7 +102,7 @@ __device__ __forceinline__ float leaf_dist2(f3 p, float4 f0, float4 f1, float4 f
         return tri_closest(p, xyz(f0), xyz(f1), xyz(f2), w1, w2);
     }
     const f3 d = p - xyz(f0);
-    return dot(d, d);
+    return fdot(d, d);
 }
 
 // Box distance of a leaf child (its triangle's bounds, or the point itself).
@@ -90,14 +114,12 @@ __device__ __forceinline__ float leaf_box_dist2(f3 p, float4 f0, float4 f1, floa
         return box_dist2(p, lo, hi);
     }
     const f3 d = p - xyz(f0);
-    return dot(d, d);
+    return fdot(d, d);
 }
 
 // Margin of a query's slab distances: 2^-20 of its coordinate magnitudes
 // covers the float32 rounding of d.q.
-__device__ __forceinline__ float slab_query_margin(f3 q) {
-    return 0x1p-20f * ((fabsf(q.x) + fabsf(q.y)) + fabsf(q.z));
-}
+__device__ __forceinline__ float slab_query_margin(f3 q) { return 0x1p-20f * qnorm1(q); }
 
 // Lower bound of the squared distance from q to the faces below an internal
 // child slot (c0, c1, c2) = (lo, ref) (hi, a) (d, b): the larger of the box
@@ -122,16 +144,13 @@ template <bool kTri>
 __device__ void write_result(const QueryArgs &a, int64_t q, f3 p, int32_t leaf, int32_t id, float d2) {
     if (kTri) {
         if (leaf >= 0 && leaf < a.n) {
-            const f3 A = load3(a.verts, a.nv, a.leaf_faces[leaf]);
-            const f3 B = load3(a.verts, a.nv, a.leaf_faces[a.n + leaf]);
-            const f3 C = load3(a.verts, a.nv, a.leaf_faces[2 * a.n + leaf]);
+            const f3 A = vload(a.verts, a.nv, a.leaf_faces[leaf]);
+            const f3 B = vload(a.verts, a.nv, a.leaf_faces[a.n + leaf]);
+            const f3 C = vload(a.verts, a.nv, a.leaf_faces[2 * a.n + leaf]);
             float w1, w2;
             const float dd = tri_closest(p, A, B, C, w1, w2);
-            const float w0 = 1.0f - w1 - w2;
             store_face(a, q, id);
-            if (a.point)
-                store3(a.point, a.nq, q, f3{w0 * A.x + w1 * B.x + w2 * C.x, w0 * A.y + w1 * B.y + w2 * C.y,
-                                            w0 * A.z + w1 * B.z + w2 * C.z});
+            if (a.point) store3(a.point, a.nq, q, tri_point(A, B, C, w1, w2));
             if (a.bary) { a.bary[q] = w1; a.bary[a.nq + q] = w2; }
             if (a.dist2) a.dist2[q] = dd;
             if (a.normal) store3(a.normal, a.nq, q, tri_normal(A, B, C));
@@ -168,11 +187,11 @@ __device__ __forceinline__ float prim_dist2(const QueryArgs &a, f3 p, int32_t id
     if (leaf < 0 || leaf >= a.n) return INFINITY;
     if (kTri) {
         float w1, w2;
-        return tri_closest(p, load3(a.verts, a.nv, a.leaf_faces[leaf]), load3(a.verts, a.nv, a.leaf_faces[a.n + leaf]),
-                           load3(a.verts, a.nv, a.leaf_faces[2 * a.n + leaf]), w1, w2);
+        return tri_closest(p, vload(a.verts, a.nv, a.leaf_faces[leaf]), vload(a.verts, a.nv, a.leaf_faces[a.n + leaf]),
+                           vload(a.verts, a.nv, a.leaf_faces[2 * a.n + leaf]), w1, w2);
     }
-    const f3 d = p - load3(a.verts, a.nv, id);
-    return dot(d, d);
+    const f3 d = p - vload(a.verts, a.nv, id);
+    return fdot(d, d);
 }
 
 // The starting best of query q from its hint: (d^2 bits, id), or `none`.
@@ -191,11 +210,11 @@ template <bool kTri>
 __device__ __forceinline__ float single_leaf_dist2(const QueryArgs &a, f3 p) {
     if (kTri) {
         float w1, w2;
-        return tri_closest(p, load3(a.verts, a.nv, a.leaf_faces[0]), load3(a.verts, a.nv, a.leaf_faces[a.n]),
-                           load3(a.verts, a.nv, a.leaf_faces[2 * a.n]), w1, w2);
+        return tri_closest(p, vload(a.verts, a.nv, a.leaf_faces[0]), vload(a.verts, a.nv, a.leaf_faces[a.n]),
+                           vload(a.verts, a.nv, a.leaf_faces[2 * a.n]), w1, w2);
     }
-    const f3 d = p - load3(a.verts, a.nv, a.prim[0]);
-    return dot(d, d);
+    const f3 d = p - vload(a.verts, a.nv, a.prim[0]);
+    return fdot(d, d);
 }
 
 // --------------------------------------------------------------- batch kernel
@@ -256,6 +275,26 @@ __device__ __forceinline__ bool lds_cas(int32_t *p, int expect, int v) {
                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Lane 0's value as a wave-uniform (scalar) one.  The mailbox decisions, the
+// chunk's owner and size, the stack depth and the wait conditions are the same
+// in every lane; reading them through readfirstlane makes the branches on them
+// scalar, so the compiler never treats the regions that use ballots and
+// shuffles as divergent (with the decisions taken per lane through a
+// shuffle, batches after a wave's first returned faces that were not the
+// nearest).
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// The lanes of a wave hand stack entries to each other through LDS (a lane
+// pops what another lane pushed, copied or donated).  The hardware keeps a
+// wave's LDS operations in order, but the compiler only orders each lane's own
+// accesses, and a lane's load of another lane's slot may be moved above the
+// store that fills it; this fence keeps every LDS access of the wave on its
+// side.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Rounds over wave `self`'s stack (sp entries) until it is empty.  Entries
 // belong to the batch of wave `owner`: its query positions and bests.
 template <bool kTri, int M>
@@ -271,14 +310,16 @@ __device__ void run_stack(const QueryArgs &a, BatchLds<M> &L, int self, int owne
     // query expands each internal node at most once, so the round cap only stops
     // a corrupted buffer from looping
     for (int64_t round = 0; sp > 0 && round < static_cast<int64_t>(M + 1) * a.n + 64; ++round) {
+        wave_sync();                          // the previous round's pushes, or the entries handed in
         if (sp >= kDonateMin) {
             int give = 0;
             if (lane == 0 && lds_load(&mail.state) == 0 && lds_cas(&mail.state, 0, 3)) give = 1;
-            if (__shfl(give, 0)) {
+            if (uniform(give)) {
                 const int i = sp - 64 + lane;
                 mail.node[lane] = S.node[i];
                 mail.dist[lane] = S.dist[i];
                 mail.slot[lane] = S.slot[i];
+                wave_sync();
                 sp -= 64;
                 if (lane == 0) {
                     mail.owner = owner;
@@ -304,20 +345,20 @@ __device__ void run_stack(const QueryArgs &a, BatchLds<M> &L, int self, int owne
         sp -= take;
         bool act = pop && node >= 0 && node < a.n - 1;
         unsigned long long best = act ? O.best[slot] : 0ull;
-        act = act && nd <= __uint_as_float(static_cast<uint32_t>(best >> 32)) * kPruneSlack;
+        const f3 qp = act ? f3{O.q[0][slot], O.q[1][slot], O.q[2][slot]} : f3{0.0f, 0.0f, 0.0f};
+        const float qm = qnorm1(qp);
+        act = act && nd <= prune_bound(__uint_as_float(static_cast<uint32_t>(best >> 32)), qm);
         float4 l0, l1, l2, r0, r1, r2;
         int32_t lref = 0, rref = 0;
-        f3 qp = f3{0.0f, 0.0f, 0.0f};
         unsigned long long cand = ~0ull;
         if (act) {
-            qp = f3{O.q[0][slot], O.q[1][slot], O.q[2][slot]};
             const float4 *rec = a.nodes + 6 * static_cast<int64_t>(node);
             l0 = rec[0]; l1 = rec[1]; l2 = rec[2]; r0 = rec[3]; r1 = rec[4]; r2 = rec[5];
             lref = __float_as_int(l0.w);
             rref = __float_as_int(r0.w);
             if (lref >= a.n - 1 || rref >= a.n - 1 || ~lref >= a.n || ~rref >= a.n) act = false;
         }
-        const float pbound = __uint_as_float(static_cast<uint32_t>(best >> 32)) * kPruneSlack;
+        const float pbound = prune_bound(__uint_as_float(static_cast<uint32_t>(best >> 32)), qm);
         const bool tl = act && lref < 0 && leaf_box_dist2<kTri>(qp, l0, l1, l2) <= pbound;
         const bool tr = act && rref < 0 && leaf_box_dist2<kTri>(qp, r0, r1, r2) <= pbound;
         if (a.counters) {
@@ -332,8 +373,8 @@ __device__ void run_stack(const QueryArgs &a, BatchLds<M> &L, int self, int owne
         }
         if (cand != ~0ull) atomicMin(&O.best[slot], cand);
         best = act ? O.best[slot] : 0ull;
-        const float bound = __uint_as_float(static_cast<uint32_t>(best >> 32)) * kPruneSlack;
-        const float dq = slab_query_margin(qp);
+        const float bound = prune_bound(__uint_as_float(static_cast<uint32_t>(best >> 32)), qm);
+        const float dq = 0x1p-20f * qm;
         const float dl = (act && lref >= 0) ? child_bound<kTri>(qp, dq, l0, l1, l2) : INFINITY;
         const float dr = (act && rref >= 0) ? child_bound<kTri>(qp, dq, r0, r1, r2) : INFINITY;
         const bool pl = act && lref >= 0 && dl <= bound;
@@ -360,8 +401,12 @@ __device__ void run_stack(const QueryArgs &a, BatchLds<M> &L, int self, int owne
             S.slot[off] = static_cast<uint8_t>(slot);
         }
         sp += __popcll(bl) + __popcll(br);
-        sp = sp < kBatchAlloc ? sp : kBatchAlloc;
+        if (sp > kBatchAlloc) {              // past the bound of a valid tree
+            if (lane == 0) atomicOr(a.status, 64);
+            sp = kBatchAlloc;
+        }
     }
+    wave_sync();                              // the last round's bests, before any lane reads them
 }
 
 // Takes the mailbox's chunk, if there is one, and runs it to the end.
@@ -371,9 +416,9 @@ __device__ bool help_once(const QueryArgs &a, BatchLds<M> &L, int self, BatchSta
     WaveMail &mail = L.mail;
     int got = 0;
     if (lane == 0 && lds_load(&mail.state) == 1 && lds_cas(&mail.state, 1, 2)) got = 1;
-    if (!__shfl(got, 0)) return false;
+    if (!uniform(got)) return false;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    const int owner = mail.owner, n = mail.count;
+    const int owner = uniform(mail.owner), n = uniform(mail.count);
     if (owner < 0 || owner >= kBatchWaves || n < 0 || n > 64) {
         if (lane == 0) { atomicOr(a.status, 16); lds_store(&mail.state, 0); }
         return true;
@@ -384,6 +429,7 @@ __device__ bool help_once(const QueryArgs &a, BatchLds<M> &L, int self, BatchSta
         S.dist[lane] = mail.dist[lane];
         S.slot[lane] = mail.slot[lane];
     }
+    wave_sync();
     if (lane == 0) lds_store(&mail.state, 0);
     run_stack<kTri, M>(a, L, self, owner, n, stats);
     if (lane == 0) lds_add(&mail.outstanding[owner], -1);
@@ -410,11 +456,18 @@ __device__ void wait_helping(const QueryArgs &a, BatchLds<M> &L, int self, Batch
 // The workgroup's kBatchWaves waves process the query batches [qb, qb + M)
 // below q_end (positions in the processing order): wave w takes qb = start +
 // w M, then steps by stride or, with a queue, M times the batch numbers it
-// takes from the queue.  Every wave of the workgroup calls this.
-template <bool kTri, int M>
+// takes from the queue.  Every wave of the workgroup calls this.  kHelpBetween:
+// a wave that has written a batch's results empties the mailbox before it
+// starts its next batch.  The batched persistent kernel leaves that out: there
+// the compiled form of that loop returned faces that were not the nearest for
+// queries of later batches (about one in ten at 100,000 queries without the
+// seed descent), while every other form of this loop, and the plain kernels
+// with it, matched the all-faces kernel exactly; its waves still help while
+// they wait for their own chunks and at the end.
+template <bool kTri, int M, bool kHelpBetween = true>
 __device__ void batch_loop(const QueryArgs &a, int64_t start, int64_t stride, int64_t q_end, BatchLds<M> &L) {
     const int lane = threadIdx.x % 64;
-    const int self = threadIdx.x / 64;
+    const int self = uniform(static_cast<int>(threadIdx.x / 64));
     const uint64_t lt = lanemask_lt();
     const unsigned long long none = pack_best(a.maxd2, INT_MAX);
     WaveStack<M> &S = L.st[self];
@@ -431,7 +484,7 @@ __device__ void batch_loop(const QueryArgs &a, int64_t start, int64_t stride, in
         if (!a.queue) return qb + stride;
         uint32_t b = 0;
         if (lane == 0) b = atomicAdd(a.queue, 1u);
-        return static_cast<int64_t>(__shfl(b, 0)) * M;
+        return static_cast<int64_t>(static_cast<uint32_t>(uniform(static_cast<int>(b)))) * M;
     };
     for (int64_t qb = a.queue ? next(0) : start + static_cast<int64_t>(self) * M; qb < q_end; qb = next(qb)) {
         const int nb = static_cast<int>(q_end - qb < M ? q_end - qb : M);
@@ -484,7 +537,7 @@ __device__ void batch_loop(const QueryArgs &a, int64_t start, int64_t stride, in
             const f3 rhi = f3{a.root[4], a.root[5], a.root[6]};
             const float rd = own ? box_dist2(p, rlo, rhi) : INFINITY;
             const float rb = (seeded < none ? __uint_as_float(static_cast<uint32_t>(seeded >> 32)) : a.maxd2);
-            const bool push = own && rd <= rb * kPruneSlack;
+            const bool push = own && rd <= prune_bound(rb, qnorm1(p));
             const uint64_t bm = __ballot(push);
             if (push) {
                 const int pos = __popcll(bm & lt);
@@ -496,7 +549,7 @@ __device__ void batch_loop(const QueryArgs &a, int64_t start, int64_t stride, in
         }
         run_stack<kTri, M>(a, L, self, self, sp, stats);
         // chunks given away must be finished before the results are final
-        wait_helping<kTri, M>(a, L, self, stats, [&]() { return lds_load(&mail.outstanding[self]) == 0; });
+        wait_helping<kTri, M>(a, L, self, stats, [&]() { return uniform(lds_load(&mail.outstanding[self])) == 0; });
         if (own) {
             const unsigned long long b = S.best[lane];
             write_result_id<kTri>(a, qid, p, static_cast<int32_t>(b & 0xffffffffull),
@@ -504,11 +557,12 @@ __device__ void batch_loop(const QueryArgs &a, int64_t start, int64_t stride, in
         }
         if (a.counters) stats.nq += __popcll(__ballot(own));
         // work already started in the workgroup goes before a new batch
-        while (help_once<kTri, M>(a, L, self, stats)) {
-        }
+        if (kHelpBetween)
+            while (help_once<kTri, M>(a, L, self, stats)) {
+            }
     }
     if (lane == 0) lds_add(&mail.done, 1);
-    wait_helping<kTri, M>(a, L, self, stats, [&]() { return lds_load(&mail.done) == kBatchWaves; });
+    wait_helping<kTri, M>(a, L, self, stats, [&]() { return uniform(lds_load(&mail.done)) == kBatchWaves; });
     if (a.counters && lane == 0) add_counters(a, stats.exp, stats.lbox, stats.lex, stats.nq);
 }
 

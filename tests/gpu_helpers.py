@@ -143,3 +143,68 @@ def check_slabs(got, verts):
         cur = cur.copy()
         cur[live] = np.where(tag < 0, 0, nxt)
     return checked
+
+
+def check_knn_result(r, V, F, Q, k, eps, max_dist2=float("inf")):
+    """A k-NN weighted projection result r (device dict: face [k][Q], dist2 [k][Q],
+    point [3][Q]) of queries Q on mesh (V, F) against the float64 oracle, exactly
+    where ties leave no choice: the k smallest distances match the oracle's (they are
+    unique even when the faces are not), every device face lies at its reported
+    distance, and the device point is the weighted point of the device's own faces."""
+    from oracle import knn as ok
+    from oracle import closest as oc
+    face, d2, pt = host(r["face"]).astype(np.int64), host(r["dist2"]).astype(np.float64), host(r["point"])
+    L = scale_of(V)
+    ref_f, ref_d2 = ok.knn_faces(V, F, Q, k)
+    kk = ref_f.shape[0]
+    ok_mask = np.isfinite(ref_d2) & (ref_d2 <= max_dist2)
+    dr, dd = np.sqrt(ref_d2), np.sqrt(d2[:kk])
+    valid = face[:kk] >= 0
+    np.testing.assert_array_equal(valid, ok_mask | (valid & (np.abs(dd - dr) <= REL * np.maximum(dr, 0.1 * L))))
+    assert (np.abs(dd - dr)[valid] <= REL * np.maximum(dr, 0.1 * L)[valid]).all()
+    for j in range(kk):
+        m = valid[j]
+        if m.any():
+            rec = oc.closest_on_faces(V, F, Q[:, m], face[j][m])
+            assert (np.abs(np.sqrt(rec["dist2"]) - dd[j][m]) <= REL * np.maximum(dd[j][m], 0.1 * L)).all()
+    full = valid.all(axis=0)
+    want = ok.weighted_point(V, F, Q[:, full], face[:kk][:, full], eps)
+    # The weighted point P = sum w_i c_i / W, w_i = 1 / (d_i + eps), moves by
+    # dP/dd_i = -w_i^2 (c_i - P) / W under an error in d_i; a float32 distance is off
+    # by a few units in the last place of the coordinates' magnitude M, so when one
+    # face is far nearer than the others that rounding is amplified.  The bound adds
+    # 8 eps32 M times that sensitivity to the position rule.
+    recs = [oc.closest_on_faces(V, F, Q[:, full], face[j][full]) for j in range(kk)]
+    dist = np.stack([np.sqrt(r["dist2"]) for r in recs])                       # [k][Q']
+    with np.errstate(divide="ignore"):
+        w = np.where(dist + eps > 0, 1.0 / (dist + eps), 0.0)
+    W = w.sum(axis=0)
+    sens = np.zeros(dist.shape[1])
+    for j, r in enumerate(recs):
+        sens += w[j] ** 2 * np.linalg.norm(r["point"] - want, axis=0)
+    sens = np.where(W > 0, sens / np.where(W > 0, W, 1.0), 0.0)
+    M = float(np.abs(np.asarray(V, dtype=np.float64)).max())
+    # each closest point c_i is itself only as accurate as its triangle allows: the
+    # float32 bound 8 eps32 M / sin^2 of the smallest angle (thin marching-tetrahedra
+    # triangles), weighted by the face's share w_i / W of the combination
+    thin = np.zeros(dist.shape[1])
+    for j in range(kk):
+        thin += w[j] * 8 * 2.0 ** -24 * M / np.maximum(sin_smallest_angle(V, F, face[j][full]), 1e-30) ** 2
+    thin = np.where(W > 0, thin / np.where(W > 0, W, 1.0), 0.0)
+    tol = REL * np.maximum(np.abs(want), 0.1 * L) + 8 * 2.0 ** -24 * M * sens[None] + thin[None]
+    assert (np.abs(pt[:, full] - want) <= tol).all()
+    return face, d2, pt
+
+
+def sin_smallest_angle(V, F, face_ids):
+    """Sine of the smallest interior angle of each given face (0 for a degenerate one)."""
+    V = np.asarray(V, dtype=np.float64)
+    tri = np.asarray(F)[:, np.asarray(face_ids, dtype=np.int64)]
+    P = [V[:, tri[k]] for k in range(3)]
+    out = np.full(tri.shape[1], np.inf)
+    for x, y, z in ((0, 1, 2), (1, 2, 0), (2, 0, 1)):
+        u, v = P[y] - P[x], P[z] - P[x]
+        den = np.linalg.norm(u, axis=0) * np.linalg.norm(v, axis=0)
+        sn = np.where(den > 0, np.linalg.norm(np.cross(u.T, v.T).T, axis=0) / np.where(den > 0, den, 1.0), 0.0)
+        out = np.minimum(out, sn)
+    return out

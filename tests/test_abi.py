@@ -90,7 +90,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     """The ctypes mirrors have the C structs' sizes and field offsets (gcc on the header)."""
     import subprocess
     from paper_2606_00444_amd import _lib
-    structs = {"mg_lbvh_layout": _lib.LbvhLayout, "mg_query_options": _lib.QueryOptions,
+    structs = {"mg_lbvh_layout": _lib.LbvhLayout, "mg_lbvh_header": _lib.LbvhHeader,
+               "mg_query_options": _lib.QueryOptions,
                "mg_batch_scene": _lib.BatchScene, "mg_batch_options": _lib.BatchOptions}
     lines = ['#include <stdio.h>', '#include "mgu.h"', "int main(void) {"]
     for cname, py in structs.items():

@@ -55,17 +55,13 @@ def _compare(mg, scenes, plan, opts):
             got = decode_bvh(bvh)
             for k in ("child", "internal_box", "leaf_box", "root_box"):
                 np.testing.assert_array_equal(got[k], ref[k], err_msg=f"scene {i} frame {t} {k}")
-            # Gaussians: the same device function
+            # Gaussians: the same device function, whose rounding does not depend on
+            # the kernel it is inlined into
             for k in ("mean", "quat", "cov"):
-                np.testing.assert_allclose(host(o[k][t]), host(g[k]), rtol=1e-6, atol=1e-7,
-                                           err_msg=f"scene {i} frame {t} {k}")
-            # queries: the same traversal with the same options
-            fa, fb = host(o["face"][t]), host(q["face"])
-            same = fa == fb
-            assert same.mean() > 0.999, f"scene {i} frame {t}"
-            np.testing.assert_array_equal(host(o["dist2"][t])[same], host(q["dist2"])[same])
-            np.testing.assert_array_equal(host(o["point"][t])[:, same], host(q["point"])[:, same])
-            np.testing.assert_array_equal(host(o["normal"][t])[:, same], host(q["normal"])[:, same])
+                np.testing.assert_array_equal(host(o[k][t]), host(g[k]), err_msg=f"scene {i} frame {t} {k}")
+            # queries: the same traversal with the same options, bitwise
+            for k in ("face", "dist2", "point", "normal"):
+                np.testing.assert_array_equal(host(o[k][t]), host(q[k]), err_msg=f"scene {i} frame {t} {k}")
 
 
 @pytest.mark.parametrize("batch,seed,gtile,qtile", [(4, True, 2048, 256), (1, False, 256, 64), (16, True, 512, 128)])
@@ -155,3 +151,25 @@ def test_batched_graph_replays(device):
                 a, b = host(o[k]).view(np.uint32), host(v).view(np.uint32)
                 bad = np.argwhere(a != b)
                 assert len(bad) == 0, f"scene {i} {k}: {len(bad)} words differ, first {bad[:8].tolist()}"
+
+
+@pytest.mark.parametrize("batch", [4, 16])
+def test_batched_later_batches_full_size(device, batch):
+    """The 50,000-face C3 scene with its 100,000 queries, seed descent off, so that every
+    wave runs several batches per 256-query tile and hands work through the mailbox:
+    every face, distance and point bitwise equal to the all-faces kernel.  (Between-batch
+    helping compiled into this kernel once returned non-nearest faces for about one
+    query in ten here.)"""
+    import paper_2606_00444_amd as mg
+    from paper_2606_00444_amd.batch import BatchPlan
+    scenes = _scenes(device, ids=(5,), frames=1, small=False)
+    s = scenes[0][0]
+    V = s["frames"][0].contiguous()
+    ref = mg.closest_point_bruteforce(V, s["faces"], s["queries"])
+    plan = BatchPlan([s], batch=batch, seed=False, query_tile=256)
+    plan.run()
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    o = plan.out[0]
+    for k in ("face", "dist2", "point"):
+        assert torch.equal(o[k][0], ref[k]), k

@@ -4,10 +4,8 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import need_gpu, dev, host, scale_of
+from gpu_helpers import need_gpu, dev, host, check_knn_result
 from synth import make_config
-from oracle import knn as ok
-from oracle import closest as oc
 
 pytestmark = pytest.mark.gpu
 
@@ -21,27 +19,7 @@ def _check(mg, V, F, Q, k, eps, device, max_dist2=float("inf")):
     Vd, Fd, Qd = dev(V, device), dev(F, device), dev(Q, device)
     bvh = mg.lbvh_build(Vd, Fd)
     r = mg.knn_surface_query(bvh, Vd, Qd, k=k, eps=eps, max_dist2=max_dist2)
-    face, d2, pt = host(r["face"]).astype(np.int64), host(r["dist2"]).astype(np.float64), host(r["point"])
-    L = scale_of(V)
-    ref_f, ref_d2 = ok.knn_faces(V, F, Q, k)
-    kk = ref_f.shape[0]
-    ok_mask = np.isfinite(ref_d2) & (ref_d2 <= max_dist2)
-    # the k smallest distances are unique: compare them
-    dr, dd = np.sqrt(ref_d2), np.sqrt(d2[:kk])
-    valid = face[:kk] >= 0
-    np.testing.assert_array_equal(valid, ok_mask | (valid & (np.abs(dd - dr) <= 1e-5 * np.maximum(dr, 0.1 * L))))
-    assert (np.abs(dd - dr)[valid] <= 1e-5 * np.maximum(dr, 0.1 * L)[valid]).all()
-    # the faces may differ at ties: each device face is at its reported distance
-    for j in range(kk):
-        m = valid[j]
-        if m.any():
-            rec = oc.closest_on_faces(V, F, Q[:, m], face[j][m])
-            assert (np.abs(np.sqrt(rec["dist2"]) - dd[j][m]) <= 1e-5 * np.maximum(dd[j][m], 0.1 * L)).all()
-    # the weighted point from the device's faces
-    full = valid.all(axis=0)
-    want = ok.weighted_point(V, F, Q[:, full], face[:kk][:, full], eps)
-    assert (np.abs(pt[:, full] - want) <= 1e-5 * np.maximum(np.abs(want), 0.1 * L)).all()
-    return face, d2, pt
+    return check_knn_result(r, V, F, Q, k, eps, max_dist2)
 
 
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 8])

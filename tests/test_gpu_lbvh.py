@@ -209,3 +209,41 @@ def test_build_large_template_and_rebuild_target(device):
     tv, tf = sc.target(11)            # 1,000,000 faces / 750,002 vertices
     tb = mg.lbvh_build(dev(tv, device), dev(tf, device))
     _check_build(tb, tv, tf)
+
+
+def test_vertex_count_other_than_the_build_is_flagged(device):
+    """The build records its vertex count in the header; a refit or query given another
+    count through the C ABI sets status bit 32 (vertex ids are clamped into range, so
+    nothing reads outside the caller's array: here the array really holds the build's
+    count and the call claims one vertex fewer)."""
+    import ctypes
+    import paper_2606_00444_amd as mg
+    from paper_2606_00444_amd import _lib
+    lib = _lib.load()
+    sc = make_config(1, small=True)
+    V, F = dev(sc.verts0, device), dev(sc.faces, device)
+    bvh = mg.lbvh_build(V, F)
+    hdr = lambda: _lib.LbvhHeader.from_buffer_copy(bytes(bvh.buf[:ctypes.sizeof(_lib.LbvhHeader)].cpu().numpy()))
+    assert hdr().n_verts == sc.n_verts and hdr().status == 0
+    s = torch.cuda.current_stream().cuda_stream
+    nv = sc.n_verts
+    assert lib.mg_lbvh_refit(ctypes.c_void_p(V.data_ptr()), nv, ctypes.c_void_p(bvh.buf.data_ptr()), bvh.nbytes,
+                             bvh.n, 0, ctypes.c_void_p(s)) == 0
+    torch.cuda.synchronize()
+    assert hdr().status == 0
+    assert lib.mg_lbvh_refit(ctypes.c_void_p(V.data_ptr()), nv - 1, ctypes.c_void_p(bvh.buf.data_ptr()),
+                             bvh.nbytes, bvh.n, 0, ctypes.c_void_p(s)) == 0
+    torch.cuda.synchronize()
+    assert hdr().status & 32
+    # a fresh build clears the word; a query with the wrong count sets it again
+    bvh = mg.lbvh_build(V, F, bvh=bvh)
+    torch.cuda.synchronize()
+    assert hdr().status == 0
+    q = dev(sc.queries, device)
+    out = torch.empty(q.shape[1], dtype=torch.int32, device=device)
+    assert lib.mg_closest_point_query(ctypes.c_void_p(bvh.buf.data_ptr()), bvh.nbytes, bvh.n,
+                                      ctypes.c_void_p(V.data_ptr()), nv - 1, ctypes.c_void_p(q.data_ptr()),
+                                      q.shape[1], ctypes.c_float(float("inf")), ctypes.c_void_p(out.data_ptr()),
+                                      None, None, None, None, None, ctypes.c_void_p(s)) == 0
+    torch.cuda.synchronize()
+    assert hdr().status & 32

@@ -21,11 +21,11 @@ HIPCC = "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else shut
 # kernel-name pattern -> (minimum waves per SIMD, maximum scratch bytes per lane)
 EXPECT = {
     "query.hip": {
-        r"traverse_batch_kernelILb1ELi(2|4|8|16|32)ELi1EE": (4, 0),
+        r"traverse_batch_kernelILb1ELi(2|4|8|16|32)ELi4EE": (4, 0),
         # the five-wave variant for launches beyond four waves per SIMD: its few
         # spills (24 B) sit outside the round loop
         r"traverse_batch_kernelILb1ELi(2|4|8|16|32)ELi5EE": (5, 32),
-        r"traverse_batch_kernelILb0ELi(16|32)ELi1EE": (6, 0),
+        r"traverse_batch_kernelILb0ELi(16|32)ELi4EE": (6, 0),
     },
     "lbvh.hip": {
         r"refit_sub_kernelILb1ELi\d+E": (7, 0),
