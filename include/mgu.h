@@ -170,14 +170,16 @@ mg_status mg_mesh_gaussian_update_backward(const float *verts, int32_t n_verts, 
  *   node_aux    int32  [n-1]     refit schedule: index among the "top" nodes (those
  *                                with more than 2^chunk_log2 leaves), or -1
  *   top_nodes   int32  [n]       node id of each top node (header.n_top of them)
- *   top_child   int32  [2][n]    per top node and slot: the child's top index, or -1
- *                                when the child roots a subtree
+ *   top_link    int32  [2][n]    plane 0, per top node: (parent's top index << 1) |
+ *                                slot, -1 for the root; plane 1, per subtree: the
+ *                                same for the subtree root's parent
  *   subtrees    int32  [3][n]    per subtree (header.n_sub): root reference, first
  *                                and last leaf; the subtrees (at most 2^chunk_log2
  *                                leaves, children of top nodes) cut the tree
- *   top_box     float  [2][11][n] refit scratch: subtree-root box, normal sum and
- *                                slab per top node slot
- *   top_scratch uint32 [26][n]   second-phase refit scratch when n_top is large
+ *   deposits    float4 [n][3]    refit scratch: each subtree root's summary (box,
+ *                                normal direction and sum length, slab)
+ *   top_scratch float4 [n][3] + uint32 [n]  refit scratch for the top nodes when
+ *                                they are too many for the workgroup's LDS
  *   inv_prim    int32  [n]       original primitive id -> leaf (inverse of prim)
  * ---------------------------------------------------------------------- */
 
@@ -202,7 +204,8 @@ typedef struct mg_lbvh_header {
     int32_t chunk_log2;    /* refit: subtrees of at most 2^chunk_log2 leaves */
     int32_t n_top;         /* number of top nodes */
     int32_t n_sub;         /* number of subtrees (n_top + 1 when n > 2^chunk_log2) */
-    int32_t reserved[9];
+    uint32_t refit_arrivals; /* refit scratch: subtrees finished in the running refit (0 between refits) */
+    int32_t reserved[8];
 } mg_lbvh_header;
 
 typedef struct mg_lbvh_layout {
@@ -216,9 +219,9 @@ typedef struct mg_lbvh_layout {
     int64_t off_nodes;
     int64_t off_node_aux;
     int64_t off_top_nodes;
-    int64_t off_top_child;
+    int64_t off_top_link;
     int64_t off_subtrees;
-    int64_t off_top_box;
+    int64_t off_deposits;
     int64_t off_top_scratch;
     int64_t off_inv_prim;
 } mg_lbvh_layout;
@@ -240,13 +243,13 @@ mg_status mg_lbvh_build(const float *verts, int32_t n_verts, const int32_t *face
                         void *stream);
 
 /* Refit in place: recompute every box of a built BVH for new vertex positions
- * (same n_prims and prim_kind as the build; topology unchanged).  verts must
+ * (same n_prims and prim_kind as the build; topology unchanged).  One kernel: a
+ * workgroup per subtree, the last of them also refits the top nodes.  verts must
  * hold exactly the n_verts of the build: the faces stored at build time index
  * them.  The refit and every query compare n_verts with the build's
  * (header.n_verts) and set status bit 32 when they differ; vertex ids are then
  * clamped into [0, n_verts), so a wrong count gives wrong boxes and results but
- * never a read outside the caller's array.  Two
- * kernels: a workgroup per subtree, then one workgroup for the top nodes.
+ * never a read outside the caller's array.
  * Refits (and builds) of one BVH must not run concurrently: they share its
  * scratch sections. */
 mg_status mg_lbvh_refit(const float *verts, int32_t n_verts, void *bvh, size_t bvh_bytes,

@@ -34,8 +34,8 @@ class MguError(RuntimeError):
 class LbvhLayout(ctypes.Structure):
     _fields_ = [(n, I64) for n in ("total_bytes", "off_header", "off_codes", "off_prim", "off_leaf_faces",
                                    "off_leaf_parent", "off_node_parent", "off_nodes", "off_node_aux",
-                                   "off_top_nodes", "off_top_child", "off_subtrees",
-                                   "off_top_box", "off_top_scratch", "off_inv_prim")]
+                                   "off_top_nodes", "off_top_link", "off_subtrees",
+                                   "off_deposits", "off_top_scratch", "off_inv_prim")]
 
 
 class LbvhHeader(ctypes.Structure):
@@ -43,7 +43,8 @@ class LbvhHeader(ctypes.Structure):
                 ("root_lo", ctypes.c_float * 3), ("pad0", ctypes.c_float), ("root_hi", ctypes.c_float * 3),
                 ("pad1", ctypes.c_float), ("quant_lo", ctypes.c_float * 3), ("quant_scale", ctypes.c_float * 3),
                 ("bounds_enc", ctypes.c_uint32 * 6), ("tile_counter", ctypes.c_uint32 * 4), ("chunk_log2", I32),
-                ("n_top", I32), ("n_sub", I32), ("reserved", I32 * 9)]
+                ("n_top", I32), ("n_sub", I32), ("refit_arrivals", ctypes.c_uint32),
+                ("reserved", I32 * 8)]
 
 
 class QueryOptions(ctypes.Structure):

@@ -31,11 +31,12 @@ constexpr int kSpin = 1 << 22;
 
 struct PlanScene {
     mg_batch_scene s;
-    const int32_t *leaf_faces, *prim, *inv_prim, *leaf_parent, *node_parent, *node_aux, *top_nodes;
-    const int32_t *top_child, *subtrees;
+    const int32_t *leaf_faces, *prim, *inv_prim, *leaf_parent, *node_parent, *top_nodes;
+    const int32_t *top_parent, *sub_parent, *subtrees;
     const int32_t *n_top, *n_sub;           // the scene BVH's counts (device)
-    float *top_box;                         // [n_frames][2][6][n_top] deposited subtree-root boxes
-    uint32_t *top_scratch;                  // [n_frames][kTopStatePlanes][n_top] when n_top > kBatchTopLds, else null
+    float4 *deposit;                        // [n_frames][n_sub][3] subtree-root summaries
+    float4 *top_scratch;                    // [n_frames][13 tstride / 4] phase-2 state when n_top > kBatchTopLds, else null
+    int64_t tstride;                        // n_top rounded up to a multiple of 4
     int32_t n_top_host, n_sub_host;         // counts read at plan time
     int32_t batch, seed, query_tile;        // this scene's traversal (plan defaults resolved)
     int32_t chunk_log2;
@@ -84,10 +85,14 @@ inline mg_status read_schedule(const mg_batch_scene &s, Schedule &S) {
     return MG_OK;
 }
 
-// Scratch words of one frame of a scene: deposited boxes, and second-phase
-// state when the top nodes exceed the LDS capacity.
-inline int64_t frame_scratch_words(int32_t T) {
-    return 2 * kTopBoxPlanes * static_cast<int64_t>(T) + (T > kBatchTopLds ? kTopStatePlanes * static_cast<int64_t>(T) : 0);
+// Scratch words of one frame of a scene: the deposited subtree-root summaries,
+// and second-phase state when the top nodes exceed the LDS capacity (summary
+// slots and arrival words, 13 words per top node, the count rounded up to a
+// multiple of 4 so that every block stays 16-byte aligned).
+__host__ __device__ inline int64_t top_stride(int32_t T) { return (static_cast<int64_t>(T) + 3) & ~int64_t(3); }
+__host__ __device__ inline int64_t top_scratch_words(int32_t T) { return 13 * top_stride(T) + 12 * kDummyWaves; }
+inline int64_t frame_scratch_words(int32_t T, int32_t NS) {
+    return 12 * static_cast<int64_t>(NS) + (T > kBatchTopLds ? top_scratch_words(T) : 0);
 }
 
 // Plan layout: header, 2 x total_sf dependency counters and the query-tile
@@ -174,13 +179,15 @@ __device__ RefitArgs refit_args(const PlanScene &P, int64_t t, PlanHeader *h) {
     a.leaf_parent = P.leaf_parent;
     a.node_parent = P.node_parent;
     a.nodes = reinterpret_cast<float4 *>(s.nodes + t * 24 * static_cast<int64_t>(s.n_faces > 1 ? s.n_faces - 1 : 0));
-    a.node_aux = P.node_aux;
     a.top_nodes = P.top_nodes;
-    a.top_child = P.top_child;
+    a.top_parent = P.top_parent;
+    a.sub_parent = P.sub_parent;
     a.subtrees = P.subtrees;
-    a.tstride = P.n_top_host;
-    a.top_box = P.top_box + t * 2 * kTopBoxPlanes * static_cast<int64_t>(P.n_top_host);
-    a.top_scratch = P.top_scratch ? P.top_scratch + t * kTopStatePlanes * static_cast<int64_t>(P.n_top_host) : nullptr;
+    a.deposit = P.deposit + t * 3 * static_cast<int64_t>(P.n_sub_host);
+    a.tstride = P.tstride;
+    a.top_scratch = P.top_scratch ? P.top_scratch + t * top_scratch_words(P.n_top_host) / 4 : nullptr;
+    a.hdr_nv = nullptr;                     // the plan checked the build's vertex count
+    a.arrivals = nullptr;
     a.root = s.roots + 8 * t;
     a.status = &h->status;
     a.n_top = P.n_top;
@@ -225,6 +232,9 @@ static_assert(kBlock == 64 * kBatchWaves, "a query tile is run by the workgroup'
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 constexpr size_t kSmemBytes = cmax(cmax(refit_top_lds(kBatchTopLds), refit_sub_lds(int64_t(1) << kBatchMaxChunkLog2)),
                                    sizeof(BatchLds<16>));
+static_assert(refit_sub_lds(int64_t(1) << kBatchMaxChunkLog2) <= kSmemBytes &&
+                  (int64_t(1) << kBatchMaxChunkLog2) <= 2 * kBlock,
+              "a subtree of the batched refit fits the workgroup's LDS and two leaves per thread");
 
 // The work of each phase is a function of its own (not inlined), so the
 // kernel needs the registers of its largest phase rather than of all of them
@@ -232,7 +242,8 @@ constexpr size_t kSmemBytes = cmax(cmax(refit_top_lds(kBatchTopLds), refit_sub_l
 __device__ __noinline__ void item_refit_sub(PlanHeader *h, int si, int64_t t, int64_t k) {
     extern __shared__ __align__(16) unsigned char smem[];
     const PlanScene &P = h->scenes[si];
-    refit_subtree<true, kBlock>(refit_args(P, t, h), k, smem);
+    if (P.chunk_log2 <= 8) refit_subtree<true, kBlock, 1>(refit_args(P, t, h), k, smem);
+    else refit_subtree<true, kBlock, 2>(refit_args(P, t, h), k, smem);
     signal(&counters_of(h)[P.sf_base + t], 1u);
 }
 
@@ -258,14 +269,13 @@ __device__ __noinline__ void item_refit_top(PlanHeader *h, int si, int64_t t) {
     uint32_t *refit_done = done_chunks + h->total_sf;
     wait_for(&done_chunks[sf], static_cast<uint32_t>(P.n_chunks), &h->status);
     const RefitArgs r = refit_args(P, t, h);
-    const int T = *P.n_top;
-    if (T != P.n_top_host) {
+    const int T = *P.n_top, NS = *P.n_sub;
+    if (T != P.n_top_host || NS != P.n_sub_host) {
         if (threadIdx.x == 0) atomicOr(&h->status, 2);   // the BVH was rebuilt after planning
     } else if (T > 0 && T <= kBatchTopLds) {
-        refit_top<true, kBlock, (kBatchTopLds + kBlock - 1) / kBlock>(r, T, reinterpret_cast<uint32_t *>(smem),
-                                                                      kBatchTopLds);
+        refit_top<true, kBlock, false>(r, T, NS, smem);
     } else if (T > kBatchTopLds) {
-        refit_top<true, kBlock, 1>(r, T, r.top_scratch, T);
+        refit_top<true, kBlock, true>(r, T, NS, smem);
     }
     signal(&refit_done[sf], 1u);
 }
@@ -375,7 +385,7 @@ inline mg_status scratch_words(const mg_batch_scene *scenes, int32_t n_scenes, i
         Schedule S;
         const mg_status st = read_schedule(scenes[i], S);
         if (st != MG_OK) return st;
-        words += static_cast<int64_t>(scenes[i].n_frames) * frame_scratch_words(S.n_top);
+        words += static_cast<int64_t>(scenes[i].n_frames) * frame_scratch_words(S.n_top, S.n_sub);
     }
     return MG_OK;
 }
@@ -445,9 +455,9 @@ extern "C" mg_status mg_batch_plan_init(const mg_batch_scene *scenes, int32_t n_
         P.inv_prim = reinterpret_cast<const int32_t *>(b + L.off_inv_prim);
         P.leaf_parent = reinterpret_cast<const int32_t *>(b + L.off_leaf_parent);
         P.node_parent = reinterpret_cast<const int32_t *>(b + L.off_node_parent);
-        P.node_aux = reinterpret_cast<const int32_t *>(b + L.off_node_aux);
         P.top_nodes = reinterpret_cast<const int32_t *>(b + L.off_top_nodes);
-        P.top_child = reinterpret_cast<const int32_t *>(b + L.off_top_child);
+        P.top_parent = reinterpret_cast<const int32_t *>(b + L.off_top_link);
+        P.sub_parent = P.top_parent + s.n_faces;
         P.subtrees = reinterpret_cast<const int32_t *>(b + L.off_subtrees);
         P.n_top = &reinterpret_cast<const mg_lbvh_header *>(b + L.off_header)->n_top;
         P.n_sub = &reinterpret_cast<const mg_lbvh_header *>(b + L.off_header)->n_sub;
@@ -457,13 +467,15 @@ extern "C" mg_status mg_batch_plan_init(const mg_batch_scene *scenes, int32_t n_
         P.n_top_host = S.n_top;
         P.n_sub_host = S.n_sub;
         P.chunk_log2 = S.chunk_log2;
-        // per-frame scratch: [n_frames][2][kTopBoxPlanes][T] deposits, then [n_frames][kTopStatePlanes][T] phase-2 state
-        P.top_box = reinterpret_cast<float *>(scratch);
-        scratch += static_cast<int64_t>(s.n_frames) * 2 * kTopBoxPlanes * S.n_top;
+        // per-frame scratch: [n_frames][n_sub][3] float4 deposits, then [n_frames][top_scratch_words]
+        // of phase-2 state (multiples of 4 words: the blocks stay 16-byte aligned)
+        P.deposit = reinterpret_cast<float4 *>(scratch);
+        scratch += static_cast<int64_t>(s.n_frames) * 12 * S.n_sub;
+        P.tstride = top_stride(S.n_top);
         P.top_scratch = nullptr;
         if (S.n_top > kBatchTopLds) {
-            P.top_scratch = scratch;
-            scratch += static_cast<int64_t>(s.n_frames) * kTopStatePlanes * S.n_top;
+            P.top_scratch = reinterpret_cast<float4 *>(scratch);
+            scratch += static_cast<int64_t>(s.n_frames) * top_scratch_words(S.n_top);
         }
         P.sf_base = static_cast<int32_t>(sf);
         P.n_chunks = S.n_sub;

@@ -17,9 +17,9 @@
 //   tree     Karras radix tree per internal node + leaf permutation of faces;
 //            lists the subtrees of at most C leaves that cut the tree and the
 //            "top" nodes above them, then links each top node to its parent
-//   refit    two kernels: a workgroup per subtree refits it with counters,
-//            boxes and parent links in LDS, then one workgroup finishes the
-//            top nodes in rounds (see refit.hpp)
+//   refit    one kernel: a workgroup per subtree climbs it with summary slots
+//            in LDS, and the workgroup that finishes the last subtree climbs
+//            the top nodes from the deposited subtree roots (see refit.hpp)
 //
 // Node records are child-centric (96 B: both children's boxes, or a leaf
 // child's triangle itself) so a traversal step reads one record and a leaf
@@ -58,10 +58,10 @@ inline mg_lbvh_layout make_layout(int64_t n, int kind) {
     L.off_nodes = o;       o += align256(96 * m);
     L.off_node_aux = o;    o += align256(4 * m);
     L.off_top_nodes = o;   o += align256(4 * n);
-    L.off_top_child = o;   o += align256(8 * n);
+    L.off_top_link = o;    o += align256(8 * n);
     L.off_subtrees = o;    o += align256(12 * n);
-    L.off_top_box = o;     o += align256(8 * kTopBoxPlanes * n);
-    L.off_top_scratch = o; o += align256(4 * kTopStatePlanes * n);
+    L.off_deposits = o;    o += align256(48 * n);
+    L.off_top_scratch = o; o += align256(52 * n + kDummyBytes);
     L.off_inv_prim = o;    o += align256(4 * n);
     L.total_bytes = o;
     return L;
@@ -69,7 +69,7 @@ inline mg_lbvh_layout make_layout(int64_t n, int kind) {
 
 // Largest subtree C = 2^chunk_log2 leaves: the smallest power of two >= 256
 // with n <= 512 C (a few hundred subtrees, so the top tree stays small),
-// capped at 2048 (the phase-1 LDS state is 32 B per leaf).
+// capped at 2048 (the phase-1 LDS state is 52 B per leaf).
 inline int chunk_log2_for(int64_t n) {
     int c = 8;
     while ((int64_t(512) << c) < n && c < 11) ++c;
@@ -121,6 +121,7 @@ __global__ void build_init_kernel(mg_lbvh_header *hdr, uint32_t *hist, uint32_t 
             hdr->bounds_enc[3 + k] = 0u;        // running max
         }
         for (int k = 0; k < 4; ++k) hdr->tile_counter[k] = 0;
+        hdr->refit_arrivals = 0u;
         hdr->chunk_log2 = chunk_log2;
         hdr->n_top = 0;
         hdr->n_sub = 0;
@@ -523,68 +524,94 @@ __global__ __launch_bounds__(1024) void order_subtrees_kernel(int32_t *__restric
     }
 }
 
-// Per top node and slot: the child's top index, or -1 when the child roots a subtree.
-__global__ __launch_bounds__(256) void top_child_kernel(const int32_t *__restrict__ node_aux,
-                                                        const int32_t *__restrict__ top_nodes,
-                                                        const float *__restrict__ nodes, int64_t n,
-                                                        int32_t *__restrict__ top_child, mg_lbvh_header *hdr) {
-    const int T = hdr->n_top;
+// The top links: per top node, (its parent's top index << 1) | slot (-1 for
+// the root); per subtree, the same for its root's parent.
+__global__ __launch_bounds__(256) void top_link_kernel(const int32_t *__restrict__ node_aux,
+                                                       const int32_t *__restrict__ top_nodes,
+                                                       const int32_t *__restrict__ node_parent,
+                                                       const int32_t *__restrict__ leaf_parent,
+                                                       const int32_t *__restrict__ subtrees, int64_t n,
+                                                       int32_t *__restrict__ top_link, mg_lbvh_header *hdr) {
+    const int T = hdr->n_top, NS = hdr->n_sub;
+    auto link = [&](int32_t tag) -> int32_t {
+        if (tag < 0) return -1;
+        const int32_t p = tag >> 1;
+        if (p >= n - 1) { atomicOr(&hdr->status, 8); return -1; }
+        const int32_t t = node_aux[p];
+        if (t < 0 || t >= T) { atomicOr(&hdr->status, 8); return -1; }
+        return (t << 1) | (tag & 1);
+    };
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < T; t += gridDim.x * blockDim.x) {
         const int32_t p = top_nodes[t];
-        if (p < 0 || p >= n - 1) { atomicOr(&hdr->status, 8); continue; }
-        for (int s = 0; s < 2; ++s) {
-            const int32_t ref = __float_as_int(nodes[24 * static_cast<int64_t>(p) + 12 * s + 3]);
-            top_child[s * n + t] = (ref >= 0 && ref < n - 1 && node_aux[ref] >= 0) ? node_aux[ref] : -1;
-        }
+        if (p < 0 || p >= n - 1) { atomicOr(&hdr->status, 8); top_link[t] = -1; continue; }
+        top_link[t] = link(node_parent[p]);
+    }
+    if (NS < 2) return;                       // a single subtree is the whole tree: no top
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < NS; k += gridDim.x * blockDim.x) {
+        const int32_t r = subtrees[k];
+        const bool leaf = r < 0;
+        const int64_t id = leaf ? ~static_cast<int64_t>(r) : r;
+        if (id >= (leaf ? n : n - 1)) { atomicOr(&hdr->status, 8); top_link[n + k] = -1; continue; }
+        top_link[n + k] = link(leaf ? leaf_parent[id] : node_parent[id]);
     }
 }
 
-// Phase 1: workgroups of kThreads take subtrees.
-template <bool kTri, int kThreads>
-__global__ __launch_bounds__(kThreads) void refit_sub_kernel(RefitArgs a) {
+// The refit: workgroups of kThreads take subtrees (kLeaves adjacent leaves per
+// thread); each counts the subtrees it finished into the header's arrival word
+// once their deposits are complete, and the one that brings it to the number
+// of subtrees climbs the top nodes (then clears the word for the next refit).
+// smem: refit_lds(C) bytes.
+template <bool kTri, int kThreads, int kLeaves>
+__global__ __launch_bounds__(kThreads) void refit_kernel(RefitArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_last;
     const int32_t ns = *a.n_sub;
+    int mine = 0;
     for (int64_t k = blockIdx.x; k < ns; k += gridDim.x) {
-        refit_subtree<kTri, kThreads>(a, k, smem);
-        __syncthreads();          // LDS is reused by the next subtree
+        refit_subtree<kTri, kThreads, kLeaves>(a, k, smem);   // ends with a barrier
+        ++mine;
     }
-}
-
-// Phase 1 with one workgroup thread per two leaves of the largest subtree
-// (at least 256 threads), so the climbs of a subtree mostly run side by side.
-template <bool kTri, int kThreads>
-void launch_refit_sub_t(const RefitArgs &a, size_t lds, int grid, hipStream_t s) {
-    if (lds > 65536)    // beyond the default dynamic LDS limit (gfx950 has 160 KB per workgroup)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&refit_sub_kernel<kTri, kThreads>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-    hipLaunchKernelGGL((refit_sub_kernel<kTri, kThreads>), dim3(grid), dim3(kThreads), lds, s, a);
-}
-
-template <bool kTri>
-void launch_refit_sub(const RefitArgs &a, int64_t C, int grid, hipStream_t s) {
-    const size_t lds = refit_sub_lds(C);
-    if (C >= 2048)
-        launch_refit_sub_t<kTri, 1024>(a, lds, grid, s);
-    else if (C >= 1024)
-        launch_refit_sub_t<kTri, 512>(a, lds, grid, s);
-    else
-        launch_refit_sub_t<kTri, 256>(a, lds, grid, s);
-}
-
-// Phase 2: one workgroup, one top node per thread while they fit in LDS.
-template <bool kTri>
-__global__ __launch_bounds__(1024) void refit_top_kernel(RefitArgs a) {
-    extern __shared__ __align__(16) unsigned char smem[];
+    if (ns < 2 || mine == 0) return;          // one subtree is the whole tree: its climb wrote the root
+    if (threadIdx.x == 0)
+        s_last = __hip_atomic_fetch_add(a.arrivals, static_cast<uint32_t>(mine), __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT) + mine == static_cast<uint32_t>(ns);
+    __syncthreads();
+    if (!s_last) return;
     const int T = *a.n_top;
-    if (T > 0 && T <= kTopLds) refit_top<kTri, 1024, 1>(a, T, reinterpret_cast<uint32_t *>(smem), kTopLds);
-    else if (T > kTopLds) refit_top<kTri, 1024, 1>(a, T, a.top_scratch, a.n);
+    if (T < 1 || T >= a.n) {
+        if (threadIdx.x == 0) atomicOr(a.status, 8);
+    } else if (refit_top_lds(T) <= refit_lds_bytes(a.chunk_log2)) {
+        refit_top<kTri, kThreads, false>(a, T, ns, smem);
+    } else {
+        refit_top<kTri, kThreads, true>(a, T, ns, smem);
+    }
+    if (threadIdx.x == 0) __hip_atomic_store(a.arrivals, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <bool kTri, int kThreads, int kLeaves>
+mg_status launch_refit_t(const RefitArgs &a, int grid, hipStream_t s) {
+    const size_t lds = refit_lds_bytes(a.chunk_log2);
+    if (lds > 65536)    // beyond the default dynamic LDS limit (gfx950 has 160 KB per workgroup)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&refit_kernel<kTri, kThreads, kLeaves>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    hipLaunchKernelGGL((refit_kernel<kTri, kThreads, kLeaves>), dim3(grid), dim3(kThreads), lds, s, a);
+    return launch_status();
+}
+
+// Workgroups of 512 threads (two fit a CU beside each other's LDS), one leaf
+// each, or 2 or 4 adjacent leaves for 1024- and 2048-leaf subtrees.
+template <bool kTri>
+mg_status launch_refit_k(const RefitArgs &a, int grid, hipStream_t s) {
+    if (a.chunk_log2 <= 9) return launch_refit_t<kTri, 512, 1>(a, grid, s);
+    if (a.chunk_log2 == 10) return launch_refit_t<kTri, 512, 2>(a, grid, s);
+    return launch_refit_t<kTri, 512, 4>(a, grid, s);
 }
 
 mg_status check_kind(int32_t kind) {
     return (kind == MG_PRIM_TRIANGLES || kind == MG_PRIM_POINTS) ? MG_OK : MG_ERR_INVALID_ARGUMENT;
 }
 
-mg_status launch_refit(const float *verts, int64_t nv, void *bvh, int64_t n, int kind, hipStream_t s) {
+RefitArgs refit_args(const float *verts, int64_t nv, void *bvh, int64_t n, int kind) {
     const mg_lbvh_layout L = make_layout(n, kind);
     RefitArgs a;
     a.verts = verts; a.nv = nv;
@@ -593,38 +620,30 @@ mg_status launch_refit(const float *verts, int64_t nv, void *bvh, int64_t n, int
     a.leaf_parent = at<int32_t>(bvh, L.off_leaf_parent);
     a.node_parent = at<int32_t>(bvh, L.off_node_parent);
     a.nodes = at<float4>(bvh, L.off_nodes);
-    a.node_aux = at<int32_t>(bvh, L.off_node_aux);
     a.top_nodes = at<int32_t>(bvh, L.off_top_nodes);
-    a.top_child = at<int32_t>(bvh, L.off_top_child);
+    a.top_parent = at<int32_t>(bvh, L.off_top_link);
+    a.sub_parent = at<int32_t>(bvh, L.off_top_link) + n;
     a.subtrees = at<int32_t>(bvh, L.off_subtrees);
-    a.top_box = at<float>(bvh, L.off_top_box);
+    a.deposit = at<float4>(bvh, L.off_deposits);
+    a.top_scratch = at<float4>(bvh, L.off_top_scratch);
     a.tstride = n;
-    a.top_scratch = at<uint32_t>(bvh, L.off_top_scratch);
     mg_lbvh_header *hdr = at<mg_lbvh_header>(bvh, L.off_header);
     a.root = hdr->root_lo;
     a.status = &hdr->status;
     a.hdr_nv = &hdr->n_verts;
     a.n_top = &hdr->n_top;
     a.n_sub = &hdr->n_sub;
+    a.arrivals = &hdr->refit_arrivals;
     a.n = n;
     a.chunk_log2 = chunk_log2_for(n);
+    return a;
+}
+
+mg_status launch_refit(const float *verts, int64_t nv, void *bvh, int64_t n, int kind, hipStream_t s) {
+    const RefitArgs a = refit_args(verts, nv, bvh, n, kind);
     const int64_t C = int64_t(1) << a.chunk_log2;
     const int grid = static_cast<int>(std::min<int64_t>(2 * ((n + C - 1) / C), 65535));
-    if (kind == MG_PRIM_TRIANGLES)
-        launch_refit_sub<true>(a, C, grid, s);
-    else
-        launch_refit_sub<false>(a, C, grid, s);
-    if (n > C) {   // otherwise the one subtree is the whole tree and phase 1 wrote the root
-        const size_t lds = refit_top_lds(kTopLds);
-        const void *fn = kind == MG_PRIM_TRIANGLES ? reinterpret_cast<const void *>(&refit_top_kernel<true>)
-                                                   : reinterpret_cast<const void *>(&refit_top_kernel<false>);
-        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-        if (kind == MG_PRIM_TRIANGLES)
-            hipLaunchKernelGGL(refit_top_kernel<true>, dim3(1), dim3(1024), lds, s, a);
-        else
-            hipLaunchKernelGGL(refit_top_kernel<false>, dim3(1), dim3(1024), lds, s, a);
-    }
-    return launch_status();
+    return kind == MG_PRIM_TRIANGLES ? launch_refit_k<true>(a, grid, s) : launch_refit_k<false>(a, grid, s);
 }
 
 }  // namespace
@@ -703,9 +722,10 @@ extern "C" mg_status mg_lbvh_build(const float *verts, int32_t n_verts, const in
                        at<float>(bvh, L.off_nodes), hdr, chunk_log2_for(n));
     if (chunk_log2_for(n) >= 10)      // subtrees may outnumber the resident refit workgroups
         hipLaunchKernelGGL(order_subtrees_kernel, dim3(1), dim3(1024), 0, s, at<int32_t>(bvh, L.off_subtrees), n, hdr);
-    hipLaunchKernelGGL(top_child_kernel, dim3(static_cast<unsigned>(std::min<int64_t>(blocks_for(n, 256), 64))),
+    hipLaunchKernelGGL(top_link_kernel, dim3(static_cast<unsigned>(std::min<int64_t>(blocks_for(n, 256), 64))),
                        dim3(256), 0, s, at<int32_t>(bvh, L.off_node_aux), at<int32_t>(bvh, L.off_top_nodes),
-                       at<float>(bvh, L.off_nodes), n, at<int32_t>(bvh, L.off_top_child), hdr);
+                       at<int32_t>(bvh, L.off_node_parent), at<int32_t>(bvh, L.off_leaf_parent),
+                       at<int32_t>(bvh, L.off_subtrees), n, at<int32_t>(bvh, L.off_top_link), hdr);
     if (launch_status() != MG_OK) return MG_ERR_HIP;
     return launch_refit(verts, n_verts, bvh, n, prim_kind, s);
 }

@@ -5,29 +5,29 @@
 // root is a child, with at most C leaves, of a node with more than C (or the
 // whole tree when it has at most C leaves).  Above the cut lie the "top"
 // nodes, one fewer than the subtrees.  Both sets are fixed by the topology and
-// listed once, when the tree is built.
+// listed once, when the tree is built, with the parent of every top node and
+// of every subtree root among the top nodes (the top links).
 //
-// Phase 1 (one workgroup per subtree): a Karras node covers a contiguous leaf
+// A finished node hands its parent a 12-float summary: its box, the unit
+// direction d of the area-weighted normal sum of the faces below it, the sum's
+// length, and the slab [a, b] of d.x over those faces.  Each node has one
+// summary slot and an arrival word: the first child to finish publishes its
+// summary there and stops; the second reads it, joins the two in registers,
+// writes the node's slot in its parent's record and climbs on.  A level of
+// the climb is one LDS atomic, one 48-byte LDS read and the join.
+//
+// Phase 1 (a workgroup per subtree): a Karras node covers a contiguous leaf
 // range and its index is one end of that range, so the internal nodes of a
-// subtree over leaves [f, l] have indices in [f, l].  The workgroup keeps, per
-// local index, an arrival counter, a box accumulator (LDS float min/max
-// atomics) and the node's parent link in LDS; a leaf's thread writes the leaf's
-// record slot and climbs while it is the second arrival, so the climb reads
-// only LDS.  The subtree root's box is deposited in its top parent's slot of
-// the top-box table.
+// subtree over leaves [f, l] have indices in [f, l] and their slots live in
+// LDS.  The subtree root's summary is deposited for phase 2 with device-scope
+// stores.  Phase 2 (one workgroup): the same climb through the top nodes, one
+// thread from each deposited subtree root.  The plain refit runs it in the
+// workgroup that finishes the last subtree (an arrival counter in the BVH
+// header), the batched kernel as a work item of its own.
 //
-// Phase 2 (one workgroup, after phase 1 has finished): the top nodes are
-// finished in rounds.  Each round, every node whose top children are done
-// takes the union of its deposited subtree-root boxes and its top children's
-// boxes, writes its top children's record slots, and is done; the rounds end
-// when the root is.  Boxes, child indices and flags live in LDS (or in global
-// scratch when there are more top nodes than fit).
-//
-// Triangle BVHs also carry a normal slab per internal child (see Slab below):
-// a node's is formed from its two children's, in slot order, by the thread
-// that finishes the node.  Boxes are exact (min/max only) and slabs are
-// evaluated in a fixed order with contraction off, so any schedule gives
-// bitwise the same records.  Every index read from the buffer is
+// Boxes are exact (min/max only) and each join takes its two children in slot
+// order with contraction off and explicit fused multiply-adds, so any schedule
+// gives bitwise the same records.  Every index read from the buffer is
 // range-checked; a corrupted buffer sets the error word instead of faulting or
 // hanging.
 #pragma once
@@ -42,444 +42,503 @@ struct RefitArgs {
     const int32_t *prim;
     const int32_t *leaf_parent; const int32_t *node_parent;
     float4 *nodes;                // [n-1][6] records written by this refit
-    const int32_t *node_aux;      // top index of a top node, else -1
     const int32_t *top_nodes;     // [T] node id of each top node
-    const int32_t *top_child;     // [2][n] top index of each child, -1 when it roots a subtree
-    const int32_t *subtrees;      // [3][n_sub]: root reference, first leaf, last leaf
-    float *top_box;               // [2][kTopBoxPlanes][tstride] deposited subtree roots: box, normal sum, slab
-    int64_t tstride;
-    uint32_t *top_scratch;        // [kTopStatePlanes][tstride] phase-2 state when T exceeds the LDS capacity
+    const int32_t *top_parent;    // [T] (parent's top index << 1) | slot, -1 for the root
+    const int32_t *sub_parent;    // [n_sub] (top parent's index << 1) | slot of each subtree root
+    const int32_t *subtrees;      // [3][n]: root reference, first leaf, last leaf
+    float4 *deposit;              // [n_sub][3] subtree-root summaries (device-coherent)
+    float4 *top_scratch;          // [tstride][3] summary slots, [kDummyWaves][3] dummies, then
+    int64_t tstride;              // uint32 [tstride] arrival words: phase-2 state when T
+                                  // exceeds the LDS capacity
     float *root;                  // root box: lo at [0..2], hi at [4..6]
     int32_t *status;              // error word
     const int32_t *hdr_nv;        // vertex count of the build (header), or nullptr
     const int32_t *n_top;         // number of top nodes (device)
     const int32_t *n_sub;         // number of subtrees (device)
+    uint32_t *arrivals;           // subtrees finished in this launch (plain refit)
     int64_t n;
     int chunk_log2;
 };
 
-constexpr int kTopLds = 1024;     // top nodes handled with LDS state in the plain refit
-constexpr int kTopBoxPlanes = 11; // per deposit slot: box (6), normal sum (3), slab (2)
-constexpr int kTopStatePlanes = 26;
+// The summary a finished node hands to its parent.
+struct Sum {
+    f3 lo, hi;                    // box
+    f3 d;                         // unit normal direction (zero: none)
+    float sn;                     // length of the area-weighted normal sum
+    float a, b;                   // slab: a <= d.x <= b over the faces below
+};
 
-// LDS bytes of phase 1 for subtrees of up to C leaves (per local node: 6 box
-// planes, arrival counter, parent link, and per child slot its normal sum and
-// slab), and of phase 2 for Tl top nodes (6 box planes, 2 child indices, node
-// id, done and ready flags, own normal sum and slab, and per slot the
-// deposited subtree root's normal sum and slab).
-constexpr size_t refit_sub_lds(int64_t C) { return static_cast<size_t>(C) * 72; }
-constexpr size_t refit_top_lds(int64_t Tl) { return static_cast<size_t>(Tl) * 4 * kTopStatePlanes; }
+// LDS bytes per subtree node (three float4, an arrival word and its parent
+// link) and per top node (the same, plus its node id), and the per-wave dummy
+// slots of the hand-off (below).
+constexpr size_t kSubSlotBytes = 56;
+constexpr size_t kTopSlotBytes = 60;
+constexpr int kDummyWaves = 16;   // waves of a 1024-thread workgroup
+constexpr size_t kDummyBytes = kDummyWaves * 48;
+constexpr int kTopCap = 1024;     // top nodes the plain refit's LDS holds at least
+
+constexpr size_t refit_sub_lds(int64_t C) { return static_cast<size_t>(C) * kSubSlotBytes + kDummyBytes; }
+constexpr size_t refit_top_lds(int64_t T) { return static_cast<size_t>(T) * kTopSlotBytes + kDummyBytes; }
+// LDS of the plain refit kernel: a subtree's slots, and room for at least
+// kTopCap top nodes in the workgroup that climbs the top.
+constexpr size_t refit_lds_bytes(int chunk_log2) {
+    return refit_sub_lds(int64_t(1) << chunk_log2) > refit_top_lds(kTopCap) ? refit_sub_lds(int64_t(1) << chunk_log2)
+                                                                            : refit_top_lds(kTopCap);
+}
 
 // ------------------------------------------------------------- normal slabs
 // An internal child slot of a triangle BVH stores, besides its box, a unit
-// direction d (the normalised sum of the area-weighted normals of the faces
-// below it, for the current vertices) and [a, b] with a <= d.x <= b for every
-// point x of those faces; the distance from q to them is then at least
-// max(a - d.q, d.q - b, 0).  A parent's [a, b] comes from its children's: with
-// alpha = d.d_c and r = d - alpha d_c, d.x = alpha (d_c.x) + r.x, where the
-// first term lies in alpha [a_c, b_c] and the second in the range of r.x over
-// the parent's box (for a leaf child, [a_c, b_c] is its triangle's extent along
-// its own normal); the result is intersected with the range of d.x over the
-// box.  Every extent is widened by 2^-18 of the box's coordinate magnitudes,
-// which covers the float32 rounding of these sums at every level.
-struct Slab {
-    f3 s;                         // unnormalised normal sum
-    float a, b;
-};
-
-// Unit direction of a normal sum by the hardware reciprocal square root (any
-// direction gives a valid slab, since the extents are taken along the stored
-// one; |d| is 1 to about 2^-22, which the traversal's bound allows for).
-// Sums too small to normalise safely give no direction.
-__device__ __forceinline__ f3 slab_dir(f3 s) {
-    const float l2 = fdot(s, s);
-    const bool ok = l2 > 1e-30f && l2 < 1e30f;
-    const float k = ok ? __builtin_amdgcn_rsqf(l2) : 0.0f;
-    return k * s;
-}
+// direction d and [a, b] with a <= d.x <= b for every point x of the faces
+// below it; the distance from q to them is then at least max(a - d.q, d.q - b,
+// 0).  A node's d is the normalised sum of its children's normal sums.  Its
+// slab comes from its children's: with alpha = d.d_c and r = d - alpha d_c,
+// d.x = alpha (d_c.x) + r.x, where the first term lies in alpha [a_c, b_c] and
+// the second in the range of r.x over the child's box; the union over the two
+// children is intersected with the range of d.x over the node's box.  A leaf's
+// slab is its triangle's extent along its own normal.  Every extent is widened
+// by 2^-18 of the node's box coordinate magnitudes, far more than the float32
+// rounding of these few operations (the range of a linear function over a box
+// from its centre and half-widths; the residual r rounded once per component,
+// an error of at most one unit in its last place times |x|).
 
 __device__ __forceinline__ float slab_margin(f3 lo, f3 hi) {
     return 0x1p-18f * (((fabsf(lo.x) + fabsf(hi.x)) + (fabsf(lo.y) + fabsf(hi.y))) + (fabsf(lo.z) + fabsf(hi.z)));
 }
 
-// [mn, mx] of r.x over the box [lo, hi].
-__device__ __forceinline__ void box_range(f3 r, f3 lo, f3 hi, float &mn, float &mx) {
-    mn = (fminf(r.x * lo.x, r.x * hi.x) + fminf(r.y * lo.y, r.y * hi.y)) + fminf(r.z * lo.z, r.z * hi.z);
-    mx = (fmaxf(r.x * lo.x, r.x * hi.x) + fmaxf(r.y * lo.y, r.y * hi.y)) + fmaxf(r.z * lo.z, r.z * hi.z);
+// Unit direction and length of a normal sum by the hardware reciprocal square
+// root (any direction gives a valid slab, since the extents are taken along
+// the stored one; |d| is 1 to about 2^-22, which the traversal's bound allows
+// for).  Sums too small or too large to normalise safely give no direction.
+__device__ __forceinline__ bool unit_of(f3 s, f3 &d, float &len) {
+#pragma clang fp contract(off)
+    const float l2 = fdot(s, s);
+    const bool ok = l2 > 1e-30f && l2 < 1e30f;
+    const float k = ok ? __builtin_amdgcn_rsqf(l2) : 0.0f;
+    d = f3{k * s.x, k * s.y, k * s.z};
+    len = ok ? l2 * k : 0.0f;
+    return ok;
 }
 
-__device__ __forceinline__ Slab leaf_slab(f3 x, f3 y, f3 z, f3 lo, f3 hi) {
+// [mn, mx] of r.x over the box with doubled centre S = lo + hi and doubled
+// half-widths H = hi - lo: 0.5 (r.S -/+ |r|.H).
+__device__ __forceinline__ void range_over(f3 r, f3 S, f3 H, float &mn, float &mx) {
 #pragma clang fp contract(off)
-    Slab S;
-    S.s = cross_rounded(y - x, z - x);
-    const f3 d = slab_dir(S.s);
-    const float px = fdot(d, x), py = fdot(d, y), pz = fdot(d, z);
-    const float e = slab_margin(lo, hi);
-    const bool none = d.x == 0.0f && d.y == 0.0f && d.z == 0.0f;
-    S.a = none ? -INFINITY : fminf(fminf(px, py), pz) - e;
-    S.b = none ? INFINITY : fmaxf(fmaxf(px, py), pz) + e;
+    const float c = fdot(r, S);
+    const float h = fdot(f3{fabsf(r.x), fabsf(r.y), fabsf(r.z)}, H);
+    mn = 0.5f * (c - h);
+    mx = 0.5f * (c + h);
+}
+
+template <bool kTri>
+__device__ __forceinline__ Sum leaf_sum(f3 x, f3 y, f3 z) {
+#pragma clang fp contract(off)
+    Sum S;
+    // + 0 turns -0 into +0, so a zero box coordinate has one encoding whatever the
+    // vertices' signs of zero (boxes are then bitwise the same in any union order)
+    const f3 lo = fmin3(fmin3(x, y), z), hi = fmax3(fmax3(x, y), z);
+    S.lo = f3{lo.x + 0.0f, lo.y + 0.0f, lo.z + 0.0f};
+    S.hi = f3{hi.x + 0.0f, hi.y + 0.0f, hi.z + 0.0f};
+    S.d = f3{0.0f, 0.0f, 0.0f};
+    S.sn = 0.0f;
+    S.a = -INFINITY;
+    S.b = INFINITY;
+    if (!kTri) return S;
+    if (unit_of(cross_rounded(y - x, z - x), S.d, S.sn)) {
+        const float px = fdot(S.d, x), py = fdot(S.d, y), pz = fdot(S.d, z);
+        const float e = slab_margin(S.lo, S.hi);
+        S.a = fminf(fminf(px, py), pz) - e;
+        S.b = fmaxf(fmaxf(px, py), pz) + e;
+    }
     return S;
 }
 
-// Bound of d.x over a child (slab c, direction dc) inside the box [lo, hi];
-// a child without a slab contributes the box's own range [ba, bb].
-__device__ __forceinline__ void child_range(f3 d, const Slab &c, f3 dc, f3 lo, f3 hi, float ba, float bb,
-                                            float &ca, float &cb) {
+// Bound of d.x over child c's faces, or [ba, bb] (the node box's range) when
+// the child has no slab.
+__device__ __forceinline__ void child_range(f3 d, const Sum &c, float ba, float bb, float &ca, float &cb) {
 #pragma clang fp contract(off)
-    const float al = fdot(d, dc);
-    const f3 r = f3{fmaf(-al, dc.x, d.x), fmaf(-al, dc.y, d.y), fmaf(-al, dc.z, d.z)};
+    const float al = fdot(d, c.d);
+    const f3 r = f3{fmaf(-al, c.d.x, d.x), fmaf(-al, c.d.y, d.y), fmaf(-al, c.d.z, d.z)};
     float rmn, rmx;
-    box_range(r, lo, hi, rmn, rmx);
+    range_over(r, c.lo + c.hi, c.hi - c.lo, rmn, rmx);
     const bool pos = al >= 0.0f;
-    const float lo_c = (pos ? al * c.a : al * c.b) + rmn;
-    const float hi_c = (pos ? al * c.b : al * c.a) + rmx;
-    const bool has = c.a > -INFINITY && c.b < INFINITY && (dc.x != 0.0f || dc.y != 0.0f || dc.z != 0.0f);
+    const float lo_c = fmaf(al, pos ? c.a : c.b, rmn);
+    const float hi_c = fmaf(al, pos ? c.b : c.a, rmx);
+    const bool has = c.a > -INFINITY && c.b < INFINITY && c.sn > 0.0f;
     ca = has ? lo_c : ba;
     cb = has ? hi_c : bb;
 }
 
-// The slab of a node with box [lo, hi] from its children's (slot order); d is
-// its unit direction.
-__device__ __forceinline__ Slab join_slab(const Slab &c0, const Slab &c1, f3 lo, f3 hi, f3 &d) {
+// The summary of a node from its children's, in slot order.
+template <bool kTri>
+__device__ __forceinline__ Sum join(const Sum &L, const Sum &R) {
 #pragma clang fp contract(off)
-    Slab P;
-    P.s = c0.s + c1.s;
-    d = slab_dir(P.s);
-    float a, b;
-    box_range(d, lo, hi, a, b);
-    float a0, b0, a1, b1;
-    child_range(d, c0, slab_dir(c0.s), lo, hi, a, b, a0, b0);
-    child_range(d, c1, slab_dir(c1.s), lo, hi, a, b, a1, b1);
-    const float e = slab_margin(lo, hi);
-    const bool none = d.x == 0.0f && d.y == 0.0f && d.z == 0.0f;
-    P.a = none ? -INFINITY : fmaxf(a, fminf(a0, a1)) - e;
-    P.b = none ? INFINITY : fminf(b, fmaxf(b0, b1)) + e;
+    Sum P;
+    P.lo = fmin3(L.lo, R.lo);
+    P.hi = fmax3(L.hi, R.hi);
+    P.d = f3{0.0f, 0.0f, 0.0f};
+    P.sn = 0.0f;
+    P.a = -INFINITY;
+    P.b = INFINITY;
+    if (!kTri) return P;
+    const f3 s = f3{fmaf(L.sn, L.d.x, R.sn * R.d.x), fmaf(L.sn, L.d.y, R.sn * R.d.y),
+                    fmaf(L.sn, L.d.z, R.sn * R.d.z)};
+    if (unit_of(s, P.d, P.sn)) {
+        float ba, bb;
+        range_over(P.d, P.lo + P.hi, P.hi - P.lo, ba, bb);
+        float a0, b0, a1, b1;
+        child_range(P.d, L, ba, bb, a0, b0);
+        child_range(P.d, R, ba, bb, a1, b1);
+        const float e = slab_margin(P.lo, P.hi);
+        P.a = fmaxf(ba, fminf(a0, a1)) - e;
+        P.b = fminf(bb, fmaxf(b0, b1)) + e;
+    }
     return P;
+}
+
+// The join of a node whose children's summaries are `mine` (the climbing
+// lane's, in slot `slot`) and `other`: the two are put in slot order with
+// selects, so a wave whose lanes came from either side runs one join.
+template <bool kTri>
+__device__ __forceinline__ Sum join_slots(const Sum &mine, const Sum &other, int slot) {
+    const bool sw = slot != 0;
+    Sum L, R;
+    L.lo = f3{sw ? other.lo.x : mine.lo.x, sw ? other.lo.y : mine.lo.y, sw ? other.lo.z : mine.lo.z};
+    L.hi = f3{sw ? other.hi.x : mine.hi.x, sw ? other.hi.y : mine.hi.y, sw ? other.hi.z : mine.hi.z};
+    L.d = f3{sw ? other.d.x : mine.d.x, sw ? other.d.y : mine.d.y, sw ? other.d.z : mine.d.z};
+    L.sn = sw ? other.sn : mine.sn; L.a = sw ? other.a : mine.a; L.b = sw ? other.b : mine.b;
+    R.lo = f3{sw ? mine.lo.x : other.lo.x, sw ? mine.lo.y : other.lo.y, sw ? mine.lo.z : other.lo.z};
+    R.hi = f3{sw ? mine.hi.x : other.hi.x, sw ? mine.hi.y : other.hi.y, sw ? mine.hi.z : other.hi.z};
+    R.d = f3{sw ? mine.d.x : other.d.x, sw ? mine.d.y : other.d.y, sw ? mine.d.z : other.d.z};
+    R.sn = sw ? mine.sn : other.sn; R.a = sw ? mine.a : other.a; R.b = sw ? mine.b : other.b;
+    return join<kTri>(L, R);
+}
+
+// A summary in three float4 and back: (lo, sn) (hi, a) (d, b).
+__device__ __forceinline__ void pack(const Sum &S, float4 v[3]) {
+    v[0] = make_float4(S.lo.x, S.lo.y, S.lo.z, S.sn);
+    v[1] = make_float4(S.hi.x, S.hi.y, S.hi.z, S.a);
+    v[2] = make_float4(S.d.x, S.d.y, S.d.z, S.b);
+}
+__device__ __forceinline__ Sum unpack(float4 v0, float4 v1, float4 v2) {
+    Sum S;
+    S.lo = f3{v0.x, v0.y, v0.z}; S.sn = v0.w;
+    S.hi = f3{v1.x, v1.y, v1.z}; S.a = v1.w;
+    S.d = f3{v2.x, v2.y, v2.z}; S.b = v2.w;
+    return S;
 }
 
 // Record slot of an internal child: (lo, ref) (hi, a) (d, b); points carry no slab.
 template <bool kTri>
-__device__ __forceinline__ void write_internal(float4 *rec, int32_t ref, f3 lo, f3 hi, f3 d, const Slab &S) {
-    rec[0] = make_float4(lo.x, lo.y, lo.z, __int_as_float(ref));
+__device__ __forceinline__ void write_internal(float4 *rec, int32_t ref, const Sum &S) {
+    rec[0] = make_float4(S.lo.x, S.lo.y, S.lo.z, __int_as_float(ref));
     if (kTri) {
-        rec[1] = make_float4(hi.x, hi.y, hi.z, S.a);
-        rec[2] = make_float4(d.x, d.y, d.z, S.b);
+        rec[1] = make_float4(S.hi.x, S.hi.y, S.hi.z, S.a);
+        rec[2] = make_float4(S.d.x, S.d.y, S.d.z, S.b);
     } else {
-        rec[1] = make_float4(hi.x, hi.y, hi.z, 0.0f);
+        rec[1] = make_float4(S.hi.x, S.hi.y, S.hi.z, 0.0f);
     }
 }
 
-__device__ __forceinline__ void write_root(float *root, f3 lo, f3 hi) {
-    root[0] = lo.x; root[1] = lo.y; root[2] = lo.z;
-    root[4] = hi.x; root[5] = hi.y; root[6] = hi.z;
+__device__ __forceinline__ void write_root(float *root, const Sum &S) {
+    root[0] = S.lo.x; root[1] = S.lo.y; root[2] = S.lo.z;
+    root[4] = S.hi.x; root[5] = S.hi.y; root[6] = S.hi.z;
 }
 
-// Box accumulators in LDS: float min/max atomics (exact, so any order of
-// arrival gives the same box).  The atomics compare -0 and +0 as equal and keep
-// whichever came first, so zeros are made +0 (x + 0 in round-to-nearest) to
-// keep the box bitwise independent of the arrival order.
-__device__ __forceinline__ void lds_union(float *b, int stride, int j, f3 lo, f3 hi) {
-    lo = f3{lo.x + 0.0f, lo.y + 0.0f, lo.z + 0.0f};
-    hi = f3{hi.x + 0.0f, hi.y + 0.0f, hi.z + 0.0f};
-    __hip_atomic_fetch_min(&b[0 * stride + j], lo.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    __hip_atomic_fetch_min(&b[1 * stride + j], lo.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    __hip_atomic_fetch_min(&b[2 * stride + j], lo.z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    __hip_atomic_fetch_max(&b[3 * stride + j], hi.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    __hip_atomic_fetch_max(&b[4 * stride + j], hi.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    __hip_atomic_fetch_max(&b[5 * stride + j], hi.z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+// Device-scope stores and loads of a deposited summary: visible to a workgroup
+// on another XCD without a write-back of this XCD's L2.  The storing thread
+// waits for its stores to complete before its workgroup signals arrival.
+__device__ __forceinline__ void deposit_store(float4 *dst, const Sum &S) {
+    float4 v[3];
+    pack(S, v);
+    float *f = reinterpret_cast<float *>(dst);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        __hip_atomic_store(f + 4 * q + 0, v[q].x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(f + 4 * q + 1, v[q].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(f + 4 * q + 2, v[q].z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(f + 4 * q + 3, v[q].w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+}
+__device__ __forceinline__ Sum deposit_load(const float4 *src) {
+    const float *f = reinterpret_cast<const float *>(src);
+    float w[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) w[q] = __hip_atomic_load(f + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return unpack(make_float4(w[0], w[1], w[2], w[3]), make_float4(w[4], w[5], w[6], w[7]),
+                  make_float4(w[8], w[9], w[10], w[11]));
 }
 
-__device__ __forceinline__ void lds_read(const float *b, int64_t stride, int64_t j, f3 &lo, f3 &hi) {
-    lo = f3{b[0 * stride + j], b[1 * stride + j], b[2 * stride + j]};
-    hi = f3{b[3 * stride + j], b[4 * stride + j], b[5 * stride + j]};
+// ---------------------------------------------------------------- the climb
+// Arrival word of a node: bit 0 is set by the first child to arrive, bit 1
+// once that child's summary is in the slot.  arrive() returns true for the
+// second child, with the first one's summary in `other`.  Slots and words are
+// in LDS (workgroup scope), or with kGlobal in global scratch used by one
+// workgroup (device scope, so no stale cache line from an earlier launch on
+// another XCD is read).
+//
+// Two children of a node are often climbed by lanes of one wave that arrive
+// in the same instruction, and a lane that waited for an unpublished sibling
+// of its own wave would wait for ever (a wave does not run its other lanes
+// while one spins).  So the publication has no branch: every arriving lane
+// stores its summary - the first child into the node's slot, the second into
+// its wave's dummy slot - and ors the published bit (0 for the second) in the
+// same straight-line instructions, before any lane can start waiting.  A lane
+// then waits only for a first child in another wave, which publishes without
+// waiting for anything.
+constexpr int kSlotSpin = 1 << 20;
+
+// In LDS the words are relaxed atomics ordered by fences on LDS alone: a fence
+// of every address space would also wait for the climb's record stores (on
+// CDNA, vector loads and stores share one counter), a global store's latency
+// per level.
+template <bool kGlobal>
+__device__ __forceinline__ uint32_t word_or(uint32_t *w, uint32_t v) {
+    if (kGlobal) return __hip_atomic_fetch_or(w, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_fetch_or(w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <bool kGlobal>
+__device__ __forceinline__ uint32_t word_load(uint32_t *w) {
+    if (kGlobal) return __hip_atomic_load(w, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <bool kGlobal>
+__device__ __forceinline__ void lds_release() {
+    if (!kGlobal) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+}
+template <bool kGlobal>
+__device__ __forceinline__ void lds_acquire() {
+    if (!kGlobal) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+template <bool kGlobal>
+__device__ __forceinline__ void slot_store(float4 *slot, const Sum &S) {
+    if (kGlobal) {
+        deposit_store(slot, S);
+    } else {
+        float4 v[3];
+        pack(S, v);
+        slot[0] = v[0]; slot[1] = v[1]; slot[2] = v[2];
+    }
+}
+template <bool kGlobal>
+__device__ __forceinline__ Sum slot_load(const float4 *slot) {
+    if (kGlobal) return deposit_load(slot);
+    return unpack(slot[0], slot[1], slot[2]);
 }
 
-__device__ __forceinline__ void lds_write(float *b, int64_t stride, int64_t j, f3 lo, f3 hi) {
-    b[0 * stride + j] = lo.x; b[1 * stride + j] = lo.y; b[2 * stride + j] = lo.z;
-    b[3 * stride + j] = hi.x; b[4 * stride + j] = hi.y; b[5 * stride + j] = hi.z;
+//
+// Two sibling leaves often sit in adjacent lanes of one wave and arrive in the
+// same instruction.  The second may wait for the first's summary only because
+// the publication is a region of its own that precedes any waiting in program
+// order: a wave runs it for its first-arriving lanes before the waiting loop
+// of its second-arriving lanes (a waiting lane never blocks a lane of its own
+// wave that has yet to publish).  The wait is bounded all the same.
+template <bool kGlobal>
+__device__ __forceinline__ bool arrive(float4 *slot, float4 *dummy, uint32_t *word, const Sum &mine, Sum &other,
+                                       int32_t *status) {
+    uint32_t old = word_or<kGlobal>(word, 1u);
+    const bool first = !(old & 1u);
+    slot_store<kGlobal>(first ? slot : dummy, mine);
+    lds_release<kGlobal>();
+    word_or<kGlobal>(word, first ? 2u : 0u);  // the slot is written
+    if (first) return false;                  // the sibling finishes the node
+    for (int spin = 0; !(old & 2u); ++spin) { // a first child in another wave, between its two steps
+        if (spin > kSlotSpin) { atomicOr(status, 8); break; }
+        old = word_load<kGlobal>(word);
+    }
+    lds_acquire<kGlobal>();
+    other = slot_load<kGlobal>(slot);
+    return true;
 }
 
-// Deposit the box, normal sum and slab of a subtree root into slot `slot` of
-// its top parent p.
-__device__ __forceinline__ void deposit(const RefitArgs &a, int32_t p, int slot, f3 lo, f3 hi, const Slab &S) {
-    const int32_t t = a.node_aux[p];
-    if (t < 0 || t >= a.tstride) { atomicOr(a.status, 8); return; }
-    float *b = a.top_box + static_cast<int64_t>(slot) * kTopBoxPlanes * a.tstride + t;
-    const int64_t ts = a.tstride;
-    b[0] = lo.x; b[ts] = lo.y; b[2 * ts] = lo.z;
-    b[3 * ts] = hi.x; b[4 * ts] = hi.y; b[5 * ts] = hi.z;
-    b[6 * ts] = S.s.x; b[7 * ts] = S.s.y; b[8 * ts] = S.s.z;
-    b[9 * ts] = S.a; b[10 * ts] = S.b;
-}
-
-
-// Phase 1 for subtree k by a workgroup of kThreads threads (a compile-time
+// Phase 1 for subtree k by a workgroup of kThreads threads, each taking kLeaves
+// adjacent leaves and advancing their climbs together, one level per step, so
+// that no climb waits behind another of its thread.  kThreads is a compile-time
 // stride: blockDim would be reloaded from the dispatch packet, and that load's
-// wait would also wait for the record stores in flight).  smem:
-// refit_sub_lds(C) bytes.
-template <bool kTri, int kThreads>
+// wait would also wait for the record stores in flight.  smem:
+// refit_sub_lds(C) bytes.  The climb that finishes the subtree root deposits
+// its summary at deposit[k]; returns after the workgroup's barrier.
+template <bool kTri, int kThreads, int kLeaves>
 __device__ void refit_subtree(const RefitArgs &a, int64_t k, unsigned char *smem) {
     const int C = 1 << a.chunk_log2;
     const int32_t r = a.subtrees[k];
     const int64_t f = a.subtrees[a.n + k], l = a.subtrees[2 * a.n + k];
-    float *s_box = reinterpret_cast<float *>(smem);                // [6][C]
-    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(s_box + 6 * C); // [C]
-    int32_t *s_par = reinterpret_cast<int32_t *>(s_cnt + C);       // [C]
-    float *s_dep = reinterpret_cast<float *>(s_par + C);           // [2 slots][5][C]: normal sum, slab
+    float4 *s_slot = reinterpret_cast<float4 *>(smem);                 // [C][3]
+    float4 *s_dummy = s_slot + 3 * C + 3 * (threadIdx.x / 64);         // [kDummyWaves][3]
+    uint32_t *s_word = reinterpret_cast<uint32_t *>(s_slot + 3 * (C + kDummyWaves));   // [C]
+    int32_t *s_par = reinterpret_cast<int32_t *>(s_word + C);          // [C] parent tags
     const int64_t size = l - f + 1;
-    if (f < 0 || l >= a.n || size < 1 || size > C) {
+    if (f < 0 || l >= a.n || size < 1 || size > C || size > static_cast<int64_t>(kThreads) * kLeaves) {
         if (threadIdx.x == 0) atomicOr(a.status, 4);
+        __syncthreads();
         return;
     }
-    // A leaf's primitive, parent tag and vertices.  The first leaf of every
-    // thread is loaded before the LDS set-up and its barrier, so the two rounds
-    // of global loads overlap.
-    struct Leaf {
-        f3 x, y, z;
-        int32_t id, tag;
-    };
-    auto load_leaf = [&](int64_t i) {
-        Leaf L;
-        L.id = a.prim[i];
-        L.tag = a.leaf_parent[i];
-        if (kTri) {
-            L.x = vload(a.verts, a.nv, a.leaf_faces[i]);
-            L.y = vload(a.verts, a.nv, a.leaf_faces[a.n + i]);
-            L.z = vload(a.verts, a.nv, a.leaf_faces[2 * a.n + i]);
-        } else {
-            L.x = L.y = L.z = vload(a.verts, a.nv, L.id);
-        }
-        return L;
-    };
     if (k == 0 && threadIdx.x == 0 && a.hdr_nv && *a.hdr_nv != a.nv) atomicOr(a.status, 32);
-    const int64_t i0 = f + threadIdx.x;
-    Leaf first{};
-    if (i0 <= l) first = load_leaf(i0);
+    // the leaves' ids, parent tags and vertices are loaded before the LDS set-up
+    // and its barrier, so the gathers overlap them
+    Sum S[kLeaves];
+    int32_t p[kLeaves], slot[kLeaves];
+    bool live[kLeaves];
+    f3 x[kLeaves], y[kLeaves], z[kLeaves];
+    int32_t id[kLeaves], tag[kLeaves];
+    const int64_t i0 = f + static_cast<int64_t>(threadIdx.x) * kLeaves;
+#pragma unroll
+    for (int u = 0; u < kLeaves; ++u) {
+        const int64_t i = i0 + u;
+        tag[u] = -2;
+        if (i > l) continue;
+        id[u] = a.prim[i];
+        tag[u] = a.leaf_parent[i];
+        if (kTri) {
+            x[u] = vload(a.verts, a.nv, a.leaf_faces[i]);
+            y[u] = vload(a.verts, a.nv, a.leaf_faces[a.n + i]);
+            z[u] = vload(a.verts, a.nv, a.leaf_faces[2 * a.n + i]);
+        } else {
+            x[u] = y[u] = z[u] = vload(a.verts, a.nv, id[u]);
+        }
+    }
     for (int j = threadIdx.x; j < size; j += kThreads) {
-        s_cnt[j] = 0;
-        lds_write(s_box, C, j, f3{INFINITY, INFINITY, INFINITY}, f3{-INFINITY, -INFINITY, -INFINITY});
+        s_word[j] = 0u;
         s_par[j] = f + j < a.n - 1 ? a.node_parent[f + j] : -1;
     }
     __syncthreads();
-    for (int64_t i = i0; i <= l; i += kThreads) {
-        const Leaf L = i == i0 ? first : load_leaf(i);
-        const int32_t id = L.id;
-        const f3 x = L.x, y = L.y, z = L.z;
-        f3 lo = fmin3(fmin3(x, y), z), hi = fmax3(fmax3(x, y), z);
-        Slab S{f3{0.0f, 0.0f, 0.0f}, -INFINITY, INFINITY};
-        if (kTri) S = leaf_slab(x, y, z, lo, hi);
-        const int32_t tag = L.tag;
-        if (tag < 0) {            // a single leaf is the root
-            write_root(a.root, lo, hi);
+#pragma unroll
+    for (int u = 0; u < kLeaves; ++u) {
+        const int64_t i = i0 + u;
+        live[u] = false;
+        if (tag[u] == -2) continue;
+        S[u] = leaf_sum<kTri>(x[u], y[u], z[u]);
+        if (tag[u] < 0) {                     // a single leaf is the root
+            write_root(a.root, S[u]);
             continue;
         }
-        int32_t p = tag >> 1, slot = tag & 1;
-        if (p >= a.n - 1) { atomicOr(a.status, 4); continue; }
-        float4 *rec = a.nodes + 6 * static_cast<int64_t>(p) + 3 * slot;
-        rec[0] = make_float4(x.x, x.y, x.z, __int_as_float(~static_cast<int32_t>(i)));
-        rec[1] = make_float4(y.x, y.y, y.z, __int_as_float(id));
-        if (kTri) rec[2] = make_float4(z.x, z.y, z.z, 0.0f);
-        if (r == ~static_cast<int32_t>(i)) {      // a one-leaf subtree
-            deposit(a, p, slot, lo, hi, S);
+        p[u] = tag[u] >> 1;
+        slot[u] = tag[u] & 1;
+        if (p[u] >= a.n - 1) { atomicOr(a.status, 4); continue; }
+        float4 *rec = a.nodes + 6 * static_cast<int64_t>(p[u]) + 3 * slot[u];
+        rec[0] = make_float4(x[u].x, x[u].y, x[u].z, __int_as_float(~static_cast<int32_t>(i)));
+        rec[1] = make_float4(y[u].x, y[u].y, y[u].z, __int_as_float(id[u]));
+        if (kTri) rec[2] = make_float4(z[u].x, z[u].y, z[u].z, 0.0f);
+        if (r == ~static_cast<int32_t>(i)) {  // a one-leaf subtree
+            deposit_store(a.deposit + 3 * k, S[u]);
             continue;
         }
-        // a valid tree is at most 62 levels deep
-        for (int level = 0; level < 64; ++level) {
-            const int64_t jl = p - f;
-            if (jl < 0 || jl >= size) { atomicOr(a.status, 4); break; }
-            const int j = static_cast<int>(jl);
-            if (kTri) {
-                float *dep = s_dep + slot * 5 * C + j;
-                dep[0] = S.s.x; dep[C] = S.s.y; dep[2 * C] = S.s.z; dep[3 * C] = S.a; dep[4 * C] = S.b;
-            }
-            lds_union(s_box, C, j, lo, hi);
-            const uint32_t old = __hip_atomic_fetch_add(&s_cnt[j], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (old == 0) break;                  // the sibling finishes node p
-            lds_read(s_box, C, j, lo, hi);
-            f3 d = f3{0.0f, 0.0f, 0.0f};
-            if (kTri) {
-                Slab c0, c1;
-                const float *d0 = s_dep + j, *d1 = s_dep + 5 * C + j;
-                c0.s = f3{d0[0], d0[C], d0[2 * C]}; c0.a = d0[3 * C]; c0.b = d0[4 * C];
-                c1.s = f3{d1[0], d1[C], d1[2 * C]}; c1.a = d1[3 * C]; c1.b = d1[4 * C];
-                S = join_slab(c0, c1, lo, hi, d);
-            }
-            const int32_t c = p;
-            const int32_t ptag = s_par[j];
-            if (ptag < 0) {
-                write_root(a.root, lo, hi);
-                break;
-            }
-            p = ptag >> 1;
-            slot = ptag & 1;
-            if (p >= a.n - 1) { atomicOr(a.status, 4); break; }
-            rec = a.nodes + 6 * static_cast<int64_t>(p) + 3 * slot;
-            write_internal<kTri>(rec, c, lo, hi, d, S);
-            if (c == r) {
-                deposit(a, p, slot, lo, hi, S);
-                break;
-            }
-        }
+        live[u] = true;
     }
+    // a valid tree is at most 62 levels deep
+    for (int level = 0; level < 64; ++level) {
+        bool any = false;
+#pragma unroll
+        for (int u = 0; u < kLeaves; ++u) {
+            if (!live[u]) continue;
+            live[u] = false;
+            const int64_t jl = p[u] - f;
+            if (jl < 0 || jl >= size) { atomicOr(a.status, 4); continue; }
+            const int j = static_cast<int>(jl);
+            const int32_t ptag = s_par[j];
+            Sum O;
+            if (!arrive<false>(s_slot + 3 * j, s_dummy, s_word + j, S[u], O, a.status)) continue;
+            S[u] = join_slots<kTri>(S[u], O, slot[u]);
+            if (ptag < 0) {                   // p is the root: the subtree is the whole tree
+                write_root(a.root, S[u]);
+                continue;
+            }
+            const int32_t c = p[u];
+            p[u] = ptag >> 1;
+            slot[u] = ptag & 1;
+            if (p[u] >= a.n - 1) { atomicOr(a.status, 4); continue; }
+            write_internal<kTri>(a.nodes + 6 * static_cast<int64_t>(p[u]) + 3 * slot[u], c, S[u]);
+            if (c == r) {
+                deposit_store(a.deposit + 3 * k, S[u]);
+                continue;
+            }
+            live[u] = true;
+            any = true;
+        }
+        if (!__builtin_amdgcn_readfirstlane(__ballot(any) != 0)) break;
+    }
+    __syncthreads();
 }
 
-// Phase 2 over T top nodes with state at st (stride planes of uint32: 6 box
-// planes, 2 child planes, node id, done, ready, normal sum and slab (5), the
-// two slots' deposited normal sums and slabs (10)), in LDS or global scratch;
-// one workgroup of kThreads.  Returns after the root's box is written.
-//
-// While every thread owns at most kOwn nodes (T <= kOwn kThreads), a thread
-// keeps its nodes' child indices, ids, boxes and flags in registers, so a
-// round costs one LDS read of the children's flags and one of their boxes;
-// larger T keep everything in the planes.  (kOwn stays small: every owned node
-// carries a copy of the finishing code, and registers are scarce at 1024
-// threads.)
-template <bool kTri, int kThreads, int kOwn>
-__device__ void refit_top(const RefitArgs &a, int T, uint32_t *st, int64_t stride) {
-    __shared__ int s_root, s_root_done;
-    float *bx = reinterpret_cast<float *>(st);
-    int32_t *ch = reinterpret_cast<int32_t *>(st + 6 * stride);
-    int32_t *node = reinterpret_cast<int32_t *>(st + 8 * stride);
-    uint32_t *done = st + 9 * stride;
-    uint32_t *rdy = st + 10 * stride;
-    float *sl = reinterpret_cast<float *>(st + 11 * stride);      // [5][stride]: normal sum, a, b
-    float *dp = reinterpret_cast<float *>(st + 16 * stride);      // [2][5][stride]: deposits
-    if (threadIdx.x == 0) {
-        s_root = -1;
-        s_root_done = 0;
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < T; t += kThreads) {
-        f3 lo = f3{INFINITY, INFINITY, INFINITY}, hi = f3{-INFINITY, -INFINITY, -INFINITY};
-        for (int s = 0; s < 2; ++s) {
-            const int32_t c = a.top_child[s * a.n + t];
-            ch[s * stride + t] = c;
-            if (c >= 0) continue;                 // a top child: merged in a later round
-            const float *b = a.top_box + static_cast<int64_t>(s) * kTopBoxPlanes * a.tstride + t;
-            lo = fmin3(lo, f3{b[0], b[a.tstride], b[2 * a.tstride]});
-            hi = fmax3(hi, f3{b[3 * a.tstride], b[4 * a.tstride], b[5 * a.tstride]});
-            if (kTri)
-                for (int q = 0; q < 5; ++q) dp[(s * 5 + q) * stride + t] = b[(6 + q) * a.tstride];
-        }
-        lds_write(bx, stride, t, lo, hi);
-        done[t] = 0;
-        const int32_t pn = a.top_nodes[t];
-        node[t] = pn;
-        if (pn == 0) s_root = t;
-    }
-    __syncthreads();
-    if (s_root < 0) {
-        if (threadIdx.x == 0) atomicOr(a.status, 8);
-        return;
-    }
-    const int root = s_root;
-    auto plane_slab = [&](const float *pl, int c) {
-        Slab S;
-        S.s = f3{pl[c], pl[stride + c], pl[2 * stride + c]};
-        S.a = pl[3 * stride + c];
-        S.b = pl[4 * stride + c];
-        return S;
-    };
-    // finish node t (its top children are done): union, slab, records of its top children
-    auto finish = [&](int t, int32_t pn, int32_t c0, int32_t c1, f3 lo, f3 hi) {
-        const int32_t cs[2] = {c0, c1};
-        f3 clo[2], chi[2];
-        for (int s = 0; s < 2; ++s) {
-            const int32_t c = cs[s];
-            if (c < 0) continue;
-            lds_read(bx, stride, c, clo[s], chi[s]);
-            lo = fmin3(lo, clo[s]);
-            hi = fmax3(hi, chi[s]);
-        }
-        if (kTri) {
-            Slab cslab[2];
-            for (int s = 0; s < 2; ++s) cslab[s] = cs[s] >= 0 ? plane_slab(sl, cs[s]) : plane_slab(dp + s * 5 * stride, t);
-            f3 d;
-            const Slab S = join_slab(cslab[0], cslab[1], lo, hi, d);
-            sl[t] = S.s.x; sl[stride + t] = S.s.y; sl[2 * stride + t] = S.s.z;
-            sl[3 * stride + t] = S.a; sl[4 * stride + t] = S.b;
-            for (int s = 0; s < 2; ++s) {
-                if (cs[s] < 0) continue;
-                write_internal<true>(a.nodes + 6 * static_cast<int64_t>(pn) + 3 * s, node[cs[s]], clo[s], chi[s],
-                                     slab_dir(cslab[s].s), cslab[s]);
-            }
-        } else {
-            for (int s = 0; s < 2; ++s) {
-                if (cs[s] < 0) continue;
-                write_internal<false>(a.nodes + 6 * static_cast<int64_t>(pn) + 3 * s, node[cs[s]], clo[s], chi[s],
-                                      f3{0.0f, 0.0f, 0.0f}, Slab{});
-            }
-        }
-        lds_write(bx, stride, t, lo, hi);
-        if (t == root) {
-            write_root(a.root, lo, hi);
-            s_root_done = 1;
-        }
-    };
-    if (T <= kOwn * kThreads) {
-        int32_t my_c0[kOwn], my_c1[kOwn], my_pn[kOwn];
-        bool my_done[kOwn];
-        f3 my_lo[kOwn], my_hi[kOwn];
-#pragma unroll
-        for (int u = 0; u < kOwn; ++u) {
-            const int t = threadIdx.x + u * kThreads;
-            my_done[u] = t >= T;
-            my_c0[u] = my_c1[u] = -1;
-            my_pn[u] = -1;
-            if (t < T) {
-                my_c0[u] = ch[t];
-                my_c1[u] = ch[stride + t];
-                my_pn[u] = node[t];
-                lds_read(bx, stride, t, my_lo[u], my_hi[u]);
-                if (my_c0[u] >= T || my_c1[u] >= T || my_pn[u] < 0 || my_pn[u] >= a.n - 1) {
-                    atomicOr(a.status, 8);
-                    my_done[u] = true;
-                }
-            }
-        }
-        // a valid top tree is at most 62 levels high: one level finishes per round
-        for (int round = 0; round < 64; ++round) {
-            bool go[kOwn];
-#pragma unroll
-            for (int u = 0; u < kOwn; ++u)
-                go[u] = !my_done[u] && (my_c0[u] < 0 || done[my_c0[u]]) && (my_c1[u] < 0 || done[my_c1[u]]);
-            __syncthreads();
-#pragma unroll
-            for (int u = 0; u < kOwn; ++u) {
-                if (!go[u]) continue;
-                const int t = threadIdx.x + u * kThreads;
-                finish(t, my_pn[u], my_c0[u], my_c1[u], my_lo[u], my_hi[u]);
-                my_done[u] = true;
-                done[t] = 1;
-            }
-            __syncthreads();
-            if (s_root_done) return;
-        }
+// Phase 2 over T top nodes and NS subtrees by one workgroup of kThreads:
+// the climbs from the deposited subtree roots t, t + kThreads, ... (at most
+// kRoots per thread, advanced together; more are taken kRoots at a time)
+// through the top nodes.  The slots and arrival words live in LDS (smem,
+// refit_top_lds(T) bytes), or with kGlobal in a.top_scratch.  Returns after
+// the root's box is written.
+template <bool kTri, int kThreads, bool kGlobal, int kRoots = 2>
+__device__ void refit_top(const RefitArgs &a, int T, int NS, unsigned char *smem) {
+    // slots [T][3] (global: [tstride][3]), dummies [kDummyWaves][3], words, then in
+    // LDS each top node's id and parent link
+    float4 *t_slot;
+    uint32_t *t_word;
+    int32_t *t_node = nullptr, *t_par = nullptr;
+    const int64_t ts = kGlobal ? a.tstride : T;
+    if (kGlobal) {
+        t_slot = a.top_scratch;
     } else {
-        for (int round = 0; round < 64; ++round) {
-            for (int t = threadIdx.x; t < T; t += kThreads) {
-                uint32_t r = 0;
-                if (!done[t]) {
-                    const int32_t c0 = ch[t], c1 = ch[stride + t];
-                    r = (c0 < 0 || (c0 < T && done[c0])) && (c1 < 0 || (c1 < T && done[c1]));
-                }
-                rdy[t] = r;
-            }
-            __syncthreads();
-            for (int t = threadIdx.x; t < T; t += kThreads) {
-                if (!rdy[t]) continue;
-                const int32_t pn = node[t];
-                if (pn < 0 || pn >= a.n - 1) { atomicOr(a.status, 8); done[t] = 1; continue; }
-                f3 lo, hi;
-                lds_read(bx, stride, t, lo, hi);
-                finish(t, pn, ch[t], ch[stride + t], lo, hi);
-                done[t] = 1;
-            }
-            __syncthreads();
-            if (s_root_done) return;
+        t_slot = reinterpret_cast<float4 *>(smem);
+    }
+    float4 *t_dummy = t_slot + 3 * ts + 3 * (threadIdx.x / 64);
+    t_word = reinterpret_cast<uint32_t *>(t_slot + 3 * (ts + kDummyWaves));
+    if (!kGlobal) {
+        t_node = reinterpret_cast<int32_t *>(t_word + T);
+        t_par = t_node + T;
+    }
+    for (int t = threadIdx.x; t < T; t += kThreads) {
+        if (kGlobal) {
+            __hip_atomic_store(t_word + t, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            t_word[t] = 0u;
+            t_node[t] = a.top_nodes[t];
+            t_par[t] = a.top_parent[t];
         }
     }
-    if (threadIdx.x == 0) atomicOr(a.status, 8);   // the root never became ready
+    if (kGlobal) __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int k0 = 0; k0 < NS; k0 += kRoots * kThreads) {
+        Sum S[kRoots];
+        int32_t tag[kRoots];
+        bool live[kRoots];
+#pragma unroll
+        for (int u = 0; u < kRoots; ++u) {
+            const int k = k0 + u * kThreads + threadIdx.x;
+            live[u] = k < NS;
+            if (!live[u]) continue;
+            S[u] = deposit_load(a.deposit + 3 * k);
+            tag[u] = a.sub_parent[k];
+        }
+        // a valid top tree is at most 62 levels high
+        for (int level = 0; level < 64; ++level) {
+            bool any = false;
+#pragma unroll
+            for (int u = 0; u < kRoots; ++u) {
+                if (!live[u]) continue;
+                live[u] = false;
+                const int tp = tag[u] >> 1, slot = tag[u] & 1;
+                if (tag[u] < 0 || tp >= T) { atomicOr(a.status, 8); continue; }
+                const int32_t ptag = kGlobal ? a.top_parent[tp] : t_par[tp];
+                Sum O;
+                if (!arrive<kGlobal>(t_slot + 3 * tp, t_dummy, t_word + tp, S[u], O, a.status)) continue;
+                S[u] = join_slots<kTri>(S[u], O, slot);
+                if (ptag < 0) {               // tp is the root
+                    write_root(a.root, S[u]);
+                    continue;
+                }
+                const int pt = ptag >> 1;
+                if (pt >= T) { atomicOr(a.status, 8); continue; }
+                const int32_t pn = kGlobal ? a.top_nodes[pt] : t_node[pt];
+                const int32_t cn = kGlobal ? a.top_nodes[tp] : t_node[tp];
+                if (pn < 0 || pn >= a.n - 1) { atomicOr(a.status, 8); continue; }
+                write_internal<kTri>(a.nodes + 6 * static_cast<int64_t>(pn) + 3 * (ptag & 1), cn, S[u]);
+                tag[u] = ptag;
+                live[u] = true;
+                any = true;
+            }
+            if (!__builtin_amdgcn_readfirstlane(__ballot(any) != 0)) break;
+        }
+    }
+    __syncthreads();
 }
 
 }  // namespace mgu
