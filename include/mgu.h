@@ -242,6 +242,21 @@ mg_status mg_lbvh_build(const float *verts, int32_t n_verts, const int32_t *face
                         int32_t prim_kind, void *bvh, size_t bvh_bytes, void *ws, size_t ws_bytes,
                         void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): mg_lbvh_build with the sort
+ * workspace taken from a static device array that the library holds on each
+ * device until the process ends (about 17 MiB), instead of a caller buffer.
+ * n_prims at most MG_LBVH_STATIC_MAX_PRIMS (2^20), else MG_ERR_INVALID_ARGUMENT;
+ * the other arguments and the result are as for mg_lbvh_build.  The call
+ * allocates nothing; the first call on a device looks up that device's copy of
+ * the array.  All calls on one device share the array: calls that may overlap in
+ * time on one device (different streams without ordering) race and build wrong
+ * trees, so order them on one stream. */
+#define MG_LBVH_STATIC_MAX_PRIMS (1 << 20)
+mg_status mg_lbvh_build_static(const float *verts, int32_t n_verts, const int32_t *faces,
+                               int32_t n_prims, int32_t prim_kind, void *bvh, size_t bvh_bytes,
+                               void *stream);
+
 /* Refit in place: recompute every box of a built BVH for new vertex positions
  * (same n_prims and prim_kind as the build; topology unchanged).  One kernel: a
  * workgroup per subtree, the last of them also refits the top nodes.  verts must

@@ -16,7 +16,7 @@ from ._lib import MG_PRIM_POINTS, MG_PRIM_TRIANGLES, MG_QUERY_AUTO, MG_QUERY_BAT
 
 __all__ = [
     "frame_index", "vertex_buffer_update", "fill", "blend", "mesh_gaussian_update", "mesh_gaussian_update_backward",
-    "LBVH", "query_order", "lbvh_bytes", "lbvh_workspace_bytes", "lbvh_build", "lbvh_refit", "closest_point_query", "closest_point_bruteforce",
+    "LBVH", "query_order", "lbvh_bytes", "lbvh_workspace_bytes", "lbvh_build", "lbvh_build_static", "lbvh_refit", "closest_point_query", "closest_point_bruteforce",
     "nearest_point_query", "knn_surface_query", "mean", "chamfer", "point_mesh_backward", "chamfer_backward", "adam_step",
     "validate_indices", "validate_finite", "version", "check_device",
 ]
@@ -197,6 +197,21 @@ def lbvh_build(verts, faces=None, *, bvh=None):
         bvh = LBVH(n, kind, verts.device)
     _call("mg_lbvh_build", _ptr(verts), verts.shape[1], _ptr(faces), n, kind, _ptr(bvh.buf), bvh.nbytes,
           _ptr(bvh.ws), bvh.ws.numel(), _stream())
+    bvh.n_verts = verts.shape[1]
+    return bvh
+
+
+def lbvh_build_static(verts, faces, bvh):
+    """mg_lbvh_build_static: build into the existing bvh (an LBVH of the right size and
+    kind) with the library's static sort scratch instead of bvh.ws; at most 2^20
+    primitives.  Calls overlapping in time on one device race on that scratch."""
+    _f32(verts, 3, "verts")
+    kind = MG_PRIM_POINTS if faces is None else MG_PRIM_TRIANGLES
+    n = verts.shape[1] if faces is None else _i32(faces, "faces").shape[1]
+    if bvh.n != n or bvh.kind != kind:
+        raise ValueError("bvh was sized for another primitive count or kind")
+    _call("mg_lbvh_build_static", _ptr(verts), verts.shape[1], _ptr(faces), n, kind, _ptr(bvh.buf), bvh.nbytes,
+          _stream())
     bvh.n_verts = verts.shape[1]
     return bvh
 

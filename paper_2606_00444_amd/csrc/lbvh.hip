@@ -24,6 +24,8 @@
 // Node records are child-centric (96 B: both children's boxes, or a leaf
 // child's triangle itself) so a traversal step reads one record and a leaf
 // test needs no further gathers.
+#include <mutex>
+
 #include "refit.hpp"
 
 namespace mgu {
@@ -663,9 +665,12 @@ extern "C" mg_status mg_lbvh_workspace_size(int32_t n_prims, int32_t prim_kind, 
     return MG_OK;
 }
 
-extern "C" mg_status mg_lbvh_build(const float *verts, int32_t n_verts, const int32_t *faces,
-                                   int32_t n_prims, int32_t prim_kind, void *bvh, size_t bvh_bytes,
-                                   void *ws, size_t ws_bytes, void *stream) {
+namespace mgu {
+namespace {
+
+mg_status build_into(const float *verts, int32_t n_verts, const int32_t *faces, int32_t n_prims,
+                     int32_t prim_kind, void *bvh, size_t bvh_bytes, void *ws, size_t ws_bytes,
+                     void *stream) {
     if (bad_count(n_verts) || bad_count(n_prims) || check_kind(prim_kind) != MG_OK)
         return MG_ERR_INVALID_ARGUMENT;
     if (prim_kind == MG_PRIM_TRIANGLES && n_prims > 0 && (!faces || n_verts == 0))
@@ -728,6 +733,65 @@ extern "C" mg_status mg_lbvh_build(const float *verts, int32_t n_verts, const in
                        at<int32_t>(bvh, L.off_subtrees), n, at<int32_t>(bvh, L.off_top_link), hdr);
     if (launch_status() != MG_OK) return MG_ERR_HIP;
     return launch_refit(verts, n_verts, bvh, n, prim_kind, s);
+}
+
+}  // namespace
+}  // namespace mgu
+
+extern "C" mg_status mg_lbvh_build(const float *verts, int32_t n_verts, const int32_t *faces,
+                                   int32_t n_prims, int32_t prim_kind, void *bvh, size_t bvh_bytes,
+                                   void *ws, size_t ws_bytes, void *stream) {
+    return build_into(verts, n_verts, faces, n_prims, prim_kind, bvh, bvh_bytes, ws, ws_bytes, stream);
+}
+
+// ------------------------------------------------ build without a caller workspace
+//
+// The sort scratch of mg_lbvh_build_static lives in this array, one copy per
+// device for the life of the process.  In host code `scratch` only names the
+// symbol: kernels get the device address that hipGetSymbolAddress returns for
+// the current device.  Sized for the largest build accepted: four key/value
+// planes of 2^20 entries, the four digit histograms, and look-back words for at
+// most 256 tiles per pass (sort_items_for keeps the tile count at or below 256
+// up to 2^20 keys).
+namespace {
+constexpr int64_t kStaticMaxPrims = MG_LBVH_STATIC_MAX_PRIMS;
+constexpr int64_t kStaticWsBytes = 4 * (4 * kStaticMaxPrims) + 4 * 4 * 256 + 4 * 4 * 256 * 256;
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticWsBytes];
+
+namespace {
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on the current device, looked up on the first
+// call there.
+mg_status scratch_address(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return MG_ERR_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return MG_ERR_UNSUPPORTED_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MG_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MG_OK;
+}
+}  // namespace
+
+extern "C" mg_status mg_lbvh_build_static(const float *verts, int32_t n_verts, const int32_t *faces,
+                                          int32_t n_prims, int32_t prim_kind, void *bvh, size_t bvh_bytes,
+                                          void *stream) {
+    if (n_prims < 0 || n_prims > kStaticMaxPrims) return MG_ERR_INVALID_ARGUMENT;
+    if (make_ws(n_prims).total > kStaticWsBytes) return MG_ERR_INVALID_ARGUMENT;
+    void *ws = nullptr;
+    const mg_status st = scratch_address(&ws);
+    if (st != MG_OK) return st;
+    return build_into(verts, n_verts, faces, n_prims, prim_kind, bvh, bvh_bytes, ws,
+                      static_cast<size_t>(kStaticWsBytes), stream);
 }
 
 extern "C" mg_status mg_lbvh_refit(const float *verts, int32_t n_verts, void *bvh, size_t bvh_bytes,
