@@ -12,13 +12,15 @@ Inputs are synthetic, seeded and device-resident before timing.  Warm-up steps
 run eagerly; the K timed steps are captured once into a HIP graph and replayed
 (so host launch overhead is not measured), bracketed by synchronisations.
 
-Workload track times temporal correspondence tracking (one step = one frame),
+Workload c1 times the small icosphere case the same way without the
+comparison path (no varying-topology target), plus its 60 frames as one
+persistent launch; track times temporal correspondence tracking (one step = one frame),
 c3 times the batched form instead (one step = one persistent launch
 over all scenes x frames, against the plain per-frame path on the same GPU),
 and c4 the differentiable form (one step = one Adam step of the template
 projection loss, forward + backward + update).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c4|c5|track|sdf|contact]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c2|c3|c4|c5|track|sdf|contact]
 Prints one JSON line.
 """
 
@@ -37,10 +39,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP32_VECTOR_PEAK_TFLOPS = 157.3
-# The small configuration (icosphere, 5,120 faces, no varying-topology target) is a
-# parity-test case (tests/), not a bench line.
+# Dense fp32 vector peak without packed instructions (the build turns them off):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops per FMA x 2.4 GHz.
+FP32_VECTOR_NONPACKED_TFLOPS = 78.6
+QUERY_COMPULSORY_BYTES = 40.0      # query point in, closest point, id and distance out
+# c2 is the default line; c1 (the small icosphere case, no varying-topology target)
+# and the others are optional lines.
 WORKLOADS = {
+    "c1": (1, "icosphere 2,562 V / 5,120 F, 30,720 Gaussians, 10,000 queries, 60 frames of sinusoidal "
+              "vertex displacement"),
     "c2": (2, "UV-sphere template 20,002 V / 40,000 F, 100,000 Gaussians, 50,000 particles, "
               "200 frames, marching-tetrahedra targets ~46-53k F"),
     "c3": (3, "batched: 6 UV-sphere scenes of 5k/10k/20k/30k/40k/50k F, 20k-300k Gaussians, "
@@ -59,14 +66,14 @@ WORKLOADS = {
 }
 METRIC = "frames/s and closest-point queries/s, refit vs rebuild; achieved HBM GB/s"
 # (timed steps, warm-up steps) per workload: each default run times about a second of GPU work
-# Algorithmic float32 operations of the closest-point traversal per counted unit:
+# Algorithmic float32 operations (an FMA counts two) of the closest-point traversal per counted unit:
 # a node expansion bounds its two internal children (box distance 17 and
 # normal-slab distance 12 each, plus the query's slab margin 6), a leaf bound
 # test takes the triangle's bounds and their box distance (29), an exact test
 # is the closest point on a triangle (80).
 OPS_EXPANSION, OPS_LEAF_BOUND, OPS_EXACT = 64.0, 29.0, 80.0
 
-DEFAULT_STEPS = {"c2": (200, 10), "c3": (10, 2), "c4": (200, 10), "c5": (20, 3), "track": (199, 0), "sdf": (200, 10), "contact": (200, 10)}
+DEFAULT_STEPS = {"c1": (60, 5), "c2": (200, 10), "c3": (10, 2), "c4": (200, 10), "c5": (20, 3), "track": (199, 0), "sdf": (200, 10), "contact": (200, 10)}
 
 
 def _target_job(args):
@@ -105,66 +112,104 @@ KERNEL_SOURCES = {
     "gaussian_update": [_CSRC + f for f in ("gaussian.hip", "repose.hpp", "mgu_internal.hpp")],
     "refit": [_CSRC + f for f in ("lbvh.hip", "refit.hpp", "mgu_internal.hpp")],
     "collide": [_CSRC + f for f in ("query.hip", "traverse.hpp", "mgu_internal.hpp")],
+    "batch": [_CSRC + f for f in ("batch.hip", "traverse.hpp", "refit.hpp", "repose.hpp", "mgu_internal.hpp")],
 }
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it still matches the source."""
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of kernel in workload from the committed rocprofv3 counter
+    summary (profiles/traffic.json, keyed by workload then kernel), if it was taken
+    on the current source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path)).get(kernel)
-    except (OSError, ValueError):
+        rec = json.load(open(path)).get(workload, {}).get(kernel)
+    except (OSError, ValueError, AttributeError):
         return None
     if not rec or rec.get("source_hash") != source_hash(KERNEL_SOURCES.get(kernel, [])):
         return None
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(sc, frames_np, targets_np, n_sample, min_seconds=10.0):
-    """The float64 oracle on a bounded sample of frames 1, 2, ... (until min_seconds of
-    wall time have run, at least one frame), as frames/s."""
+def measured_counters(workload, kernel):
+    """Per-dispatch counter figures (VALU busy, occupancy, ...) of kernel in workload
+    from profiles/counters.json, if taken on the current source; else None."""
+    path = os.path.join(ROOT, "profiles", "counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(workload, {}).get(kernel)
+    except (OSError, ValueError, AttributeError):
+        return None
+    if not rec or rec.get("source_hash") != source_hash(KERNEL_SOURCES.get(kernel, [])):
+        return None
+    return {k: v for k, v in rec.items() if k != "source_hash"}
+
+
+def cpu_baseline(sc, frames_np, targets_np, n_sample, n_single, reps=5):
+    """The float64 oracle on the phases of a step, frames 1..reps, as frames/s.
+
+    Per frame: the re-pose of every Gaussian, the refit of the template tree and
+    the rebuild of the frame's target (numpy, one thread), and the three query
+    sets (plain-C brute force, OpenMP) on n_sample random queries per set with
+    every host core, and on n_single with one thread, each scaled to the full set.
+    A frame's all-core time is the numpy phases plus the all-core query time, its
+    single-thread time the numpy phases plus the one-thread query time; the
+    values are medians over the reps frames."""
     from oracle import gaussians as og, lbvh as ol, closest as oc, frame as ofr
     t_all = time.perf_counter()
     ref = ol.build(sc.verts0, sc.faces)          # the rest-pose tree, built once at initialisation
     rng = np.random.default_rng(0)
-    timings = {k: 0.0 for k in ("update", "refit", "rebuild", "collide", "collide_target", "project")}
-    n_frames, last = 0, min(len(frames_np), len(targets_np)) - 1
-    t_loop = time.perf_counter()
-    while n_frames == 0 or (time.perf_counter() - t_loop < min_seconds and n_frames < last):
-        f = 1 + n_frames
-        V = frames_np[f]
-        tv, tf = targets_np[f]
+    cores = omp_threads()
+    reps = max(1, min(reps, len(frames_np) - 1, len(targets_np) - 1))
+    host = {k: [] for k in ("update", "refit", "rebuild")}
+    qall = {k: [] for k in ("collide", "collide_target", "project")}
+    q1 = {k: [] for k in qall}
+
+    def queries(mv, mf, q, n, threads):
+        idx = rng.choice(q.shape[1], min(n, q.shape[1]), replace=False)
+        oc.set_threads(threads)
         t = time.perf_counter()
-        live = ofr.vertex_buffer_update(frames_np, f)
-        og.repose(live, sc.faces, sc.binding)
-        timings["update"] += time.perf_counter() - t
-        t = time.perf_counter()
-        ol.refit(ref["tree"], ol.leaf_boxes(V, sc.faces, ref["perm"]))
-        timings["refit"] += time.perf_counter() - t
-        t = time.perf_counter()
-        ol.build(tv, tf)
-        timings["rebuild"] += time.perf_counter() - t
-        qs = [(V, sc.faces, sc.queries), (tv, tf, sc.queries), (tv, tf, sc.verts0)]
-        for name, (mv, mf, q) in zip(("collide", "collide_target", "project"), qs):
-            idx = rng.choice(q.shape[1], min(n_sample, q.shape[1]), replace=False)
+        oc.closest_point_mesh(mv, mf, q[:, idx])
+        return (time.perf_counter() - t) * q.shape[1] / idx.size
+
+    try:
+        for f in range(1, reps + 1):
+            V = frames_np[f]
+            tv, tf = targets_np[f]
             t = time.perf_counter()
-            oc.closest_point_mesh(mv, mf, q[:, idx])
-            timings[name] += (time.perf_counter() - t) * q.shape[1] / idx.size
-        n_frames += 1
-    per_frame = sum(timings.values()) / n_frames
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+            live = ofr.vertex_buffer_update(frames_np, f)
+            og.repose(live, sc.faces, sc.binding)
+            host["update"].append(time.perf_counter() - t)
+            t = time.perf_counter()
+            ol.refit(ref["tree"], ol.leaf_boxes(V, sc.faces, ref["perm"]))
+            host["refit"].append(time.perf_counter() - t)
+            t = time.perf_counter()
+            ol.build(tv, tf)
+            host["rebuild"].append(time.perf_counter() - t)
+            qs = {"collide": (V, sc.faces, sc.queries), "collide_target": (tv, tf, sc.queries),
+                  "project": (tv, tf, sc.verts0)}
+            for name, (mv, mf, q) in qs.items():
+                qall[name].append(queries(mv, mf, q, n_sample, cores))
+                q1[name].append(queries(mv, mf, q, n_single, 1))
+    finally:
+        oc.set_threads(cores)
+    host_s = np.sum([host[k] for k in host], axis=0)
+    all_core = host_s + np.sum([qall[k] for k in qall], axis=0)
+    single = host_s + np.sum([q1[k] for k in q1], axis=0)
+    med = lambda d: {k: round(float(np.median(v)), 4) for k, v in d.items()}
     return {
-        "value": 1.0 / per_frame, "unit": "frames/s", "cores": threads, "kind": "oracle",
-        "sample": ((f"{n_frames} whole frames (1-{n_frames})" if n_frames > 1 else "one whole frame")
-                   + f": float64 numpy re-pose of all {sc.n_gauss} "
-                   f"Gaussians, refit and rebuild (single thread); brute-force plain-C closest points on "
-                   + ("every query of each set" if all(n_sample >= q.shape[1] for _, _, q in qs)
-                      else f"{n_sample} random queries per query set, scaled to the full query counts")
-                   + f" (OpenMP, {threads} threads)"),
-        "frames": n_frames,
-        "seconds_per_frame": {k: round(v / n_frames, 4) for k, v in timings.items()},
+        "value": 1.0 / float(np.median(all_core)), "unit": "frames/s", "cores": cores, "kind": "oracle",
+        "sample": (f"median of {reps} frames (1-{reps}): float64 numpy re-pose of all {sc.n_gauss} Gaussians, "
+                   f"template refit and target rebuild (one thread); plain-C brute-force closest points on "
+                   f"{n_sample} random queries per query set with {cores} OpenMP threads, scaled to the full "
+                   f"sets ({sc.queries.shape[1]} particles twice, {sc.n_verts} template vertices)"),
+        "single_thread": {"value": 1.0 / float(np.median(single)), "unit": "frames/s", "cores": 1,
+                          "sample": f"the same frames and host phases; {n_single} random queries per set on one "
+                                    f"thread, scaled"},
+        "seconds_per_frame_median": dict(med(host), **{k + "_all_cores": v for k, v in med(qall).items()},
+                                         **{k + "_one_thread": v for k, v in med(q1).items()}),
         "wall_s": round(time.perf_counter() - t_all, 2),
     }
 
@@ -283,8 +328,8 @@ def run_contact(args):
         "kernels_ms": {k: round(v, 5) for k, v in ph.items()},
         "queries_per_s": round(P * 1000.0 / ms_per_step, 1),
         "roofline": {"bound": "alu", "kernel": "traverse_batch_kernel (sphere centres onto the template)",
-                     "achieved": round(achieved, 4), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5), "traffic": None,
+                     "achieved": round(achieved, 4), "peak": FP32_VECTOR_NONPACKED_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP32_VECTOR_NONPACKED_TFLOPS, 5), "traffic": None,
                      "alg_ops_per_launch": int(ops), "avg_launch_ms": round(ph["closest"], 5)},
         "wall_s": round(wall, 4), "setup_s": round(setup_s, 2),
     }
@@ -466,8 +511,8 @@ def run_track(args):
         achieved = ops / (ph["query"] * 1e-3) / 1e12
         kname = "knn_lane_kernel" if args.knn > 1 else "traverse_batch_kernel"
         roofline = {"bound": "alu", "kernel": f"{kname} (tracked points onto the frame's mesh)",
-                    "achieved": round(achieved, 4), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5), "traffic": None,
+                    "achieved": round(achieved, 4), "peak": FP32_VECTOR_NONPACKED_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / FP32_VECTOR_NONPACKED_TFLOPS, 5), "traffic": None,
                     "alg_ops_per_launch": int(ops), "avg_launch_ms": round(ph["query"], 5)}
     else:
         tf_mean = float(np.mean([f.shape[1] for _, f in targets_np]))
@@ -605,7 +650,7 @@ def run_batched(args):
                       "query_tile": tune["query_tile"]},
         "roofline": {"bound": "hbm", "kernel": "batch_persistent_kernel", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic("batch"), "alg_bytes_per_launch": int(alg),
+                     "traffic": measured_traffic("c3", "batch"), "alg_bytes_per_launch": int(alg),
                      "avg_launch_ms": round(ms_per_step, 5)},
         "wall_s": round(wall, 4), "setup_s": round(setup_s, 2),
     }
@@ -732,8 +777,8 @@ def run_refine(args):
                       "leaf_bound_tests_per_query": round(n_lbox / n_q, 1),
                       "exact_leaf_tests_per_query": round(n_lex / n_q, 1)},
         "roofline": {"bound": "alu", "kernel": "traverse_batch_kernel (targets onto the template)",
-                     "achieved": round(achieved, 4), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5), "traffic": None,
+                     "achieved": round(achieved, 4), "peak": FP32_VECTOR_NONPACKED_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP32_VECTOR_NONPACKED_TFLOPS, 5), "traffic": None,
                      "alg_ops_per_launch": int(ops), "avg_launch_ms": round(ph["closest"], 5)},
         "wall_s": round(wall, 4), "setup_s": round(setup_s, 2),
     }
@@ -756,6 +801,188 @@ def cpu_baseline_refine(sc, Y):
                        f"targets and both nearest-neighbour maps (OpenMP, {th} threads), float64 numpy re-pose, "
                        f"gradients and Adam (single thread)"),
             "wall_s": round(sec, 2)}
+
+
+def kernel_roofline(workload, kernel, ms, alg_bytes, coll_ops, n_queries):
+    """The roofline object of the step's dominant kernel (the phase of one kernel with
+    the longest average launch).  HBM-bound kernels: algorithmic bytes per launch over
+    the launch time against 8 TB/s.  The collision traversal is bound by VALU issue and
+    latency (the tree stays in L2/MALL; a query's compulsory traffic is 40 B): its
+    algorithmic fp32 operations (an FMA counts two) per launch over the launch time,
+    against the non-packed fp32 peak, with the compulsory-byte fraction beside it."""
+    if kernel == "collide":
+        achieved = coll_ops / (ms * 1e-3) / 1e12
+        comp = QUERY_COMPULSORY_BYTES * n_queries
+        r = {"bound": "alu", "kernel": "traverse_batch_kernel (collision queries)", "achieved": round(achieved, 4),
+             "peak": FP32_VECTOR_NONPACKED_TFLOPS, "unit": "TFLOP/s",
+             "frac": round(achieved / FP32_VECTOR_NONPACKED_TFLOPS, 5),
+             "traffic": measured_traffic(workload, kernel), "alg_flops_per_launch": int(coll_ops),
+             "avg_launch_ms": round(ms, 5),
+             "compulsory_bytes_per_launch": int(comp),
+             "hbm_frac_of_compulsory_bytes": round(comp / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)}
+    else:
+        achieved = alg_bytes[kernel] / (ms * 1e-3) / 1e9
+        r = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(workload, kernel),
+             "alg_bytes_per_launch": int(alg_bytes[kernel]), "avg_launch_ms": round(ms, 5)}
+    c = measured_counters(workload, kernel)
+    if c:
+        r["counters"] = c
+    return r
+
+
+def run_c1(args):
+    """c1: the icosphere's frames through copy, re-pose, refit and collision queries,
+    one frame per step; beside it the same 60 frames as one persistent launch."""
+    from synth import make_config
+    t0 = time.perf_counter()
+    sc = make_config(1)
+    T = sc.n_frames
+    frames_np = sc.frames(range(T))
+    setup_s = time.perf_counter() - t0
+
+    import torch
+    import paper_2606_00444_amd as mg
+    from paper_2606_00444_amd import autotune
+    from paper_2606_00444_amd.batch import BatchPlan
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    mg.check_device()
+    D = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    frames, F, V0, particles = D(frames_np), D(sc.faces), D(sc.verts0), D(sc.queries)
+    b = {k: D(v) for k, v in sc.binding.items()}
+    G, Q, NV, NF = sc.n_gauss, sc.queries.shape[1], sc.n_verts, sc.n_faces
+    live = torch.empty(3, NV, device=dev)
+    gout = {"mean": torch.empty(3, G, device=dev), "quat": torch.empty(4, G, device=dev),
+            "cov": torch.empty(6, G, device=dev)}
+    col = {"face": torch.full((Q,), -1, dtype=torch.int32, device=dev), "point": torch.empty(3, Q, device=dev),
+           "bary": torch.empty(2, Q, device=dev), "dist2": torch.empty(Q, device=dev),
+           "normal": torch.empty(3, Q, device=dev)}
+    bvh = mg.lbvh_build(V0, F)
+    order_p = mg.query_order(particles)
+    mg.vertex_buffer_update(frames, 0, live)
+    mg.lbvh_refit(bvh, live)
+    o_col = autotune.options(autotune.tune_closest(bvh, live, particles, order=order_p, normal=True), order_p)
+    none_hint = torch.full((Q,), -1, dtype=torch.int32, device=dev)
+
+    def phase_update():
+        mg.mesh_gaussian_update(live, F, b["face"], b["bary"], b["q_local"], b["log_scale"], out=gout)
+
+    def phase_collide(hint=None):
+        mg.closest_point_query(bvh, live, particles, normal=True, out=col, hint=col["face"] if hint is None else hint,
+                               **o_col)
+
+    def step(i):
+        mg.vertex_buffer_update(frames, i % T, live)
+        phase_update()
+        mg.lbvh_refit(bvh, live)
+        phase_collide()
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    if args.eager:
+        run = lambda: [step(i) for i in range(args.steps)]
+    else:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for i in range(args.warmup, args.warmup + args.steps):
+                step(i)
+        g.replay()
+        torch.cuda.synchronize()
+        run = g.replay
+    ms_per_step, wall = timed_region(run, args.steps, torch)
+
+    reps = 100
+    ph = {"vertex_copy": graph_ms(lambda r: mg.vertex_buffer_update(frames, r % T, live), reps, torch),
+          "gaussian_update": graph_ms(lambda r: phase_update(), reps, torch),
+          "refit": graph_ms(lambda r: mg.lbvh_refit(bvh, live), reps, torch)}
+    ph["frame_update"] = graph_ms(lambda r: (mg.vertex_buffer_update(frames, r % T, live), phase_update(),
+                                             mg.lbvh_refit(bvh, live)), reps, torch)
+    hint = col["face"].clone()
+    ph["collide"] = graph_ms(lambda r: phase_collide(hint=hint), reps, torch)
+    cnt = torch.zeros(4, dtype=torch.int64, device=dev)
+    mg.closest_point_query(bvh, live, particles, normal=True, out=col, counters=cnt, hint=hint, **o_col)
+    torch.cuda.synchronize()
+    n_exp, n_lbox, n_lex, _ = (int(x) for x in cnt.cpu())
+    coll_ops = OPS_EXPANSION * n_exp + OPS_LEAF_BOUND * n_lbox + OPS_EXACT * n_lex
+    alg_bytes = {
+        "vertex_copy": 24.0 * NV,
+        "gaussian_update": 92.0 * G + 12.0 * NF + 12.0 * NV,
+        "refit": 12.0 * NV + 12.0 * NF + 48.0 * NF,
+        "frame_update": 24.0 * NV + (92.0 * G + 12.0 * NF + 12.0 * NV) + (12.0 * NV + 12.0 * NF + 48.0 * NF),
+        "collide": 52.0 * Q,
+    }
+    kernels = {}
+    for k, ms in ph.items():
+        gbs = alg_bytes[k] / (ms * 1e-3) / 1e9
+        kernels[k] = {"ms": round(ms, 5), "alg_bytes": int(alg_bytes[k]), "GB_s": round(gbs, 1),
+                      "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    single = {k: ph[k] for k in ("gaussian_update", "refit", "collide")}
+    dom = max(single, key=single.get)
+
+    # the same 60 frames as one persistent launch (re-pose, refit, queries per frame)
+    scene = {"frames": frames, "faces": F, "gface": b["face"], "bary": b["bary"], "q_local": b["q_local"],
+             "log_scale": b["log_scale"], "queries": particles}
+    plan = BatchPlan([scene])
+    autotune.tune_batch(plan)
+    plan.run()
+    torch.cuda.synchronize()
+    if plan.status() != 0:
+        raise RuntimeError(f"batched run reported status {plan.status()}")
+    batch_ms = graph_ms(lambda r: plan.run(), 20, torch)
+    b_alg = T * (12.0 * NV + 92.0 * G + 12.0 * NF + 48.0 * NF + 52.0 * Q)
+    out = {
+        "metric": METRIC, "value": round(1000.0 / ms_per_step, 2), "unit": "frames/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"c1: {WORKLOADS['c1'][1]}", "frames": T, "vertices": NV, "faces": NF,
+                   "gaussians": G, "queries": Q, "timing": "eager" if args.eager else "hip-graph"},
+        "frame_update": dict(kernels["frame_update"], what="vertex copy, Gaussian re-pose, refit"),
+        "queries_per_s": round(Q * 1000.0 / ms_per_step, 1),
+        "traversal": {"node_expansions_per_query": round(n_exp / Q, 1),
+                      "leaf_bound_tests_per_query": round(n_lbox / Q, 1),
+                      "exact_leaf_tests_per_query": round(n_lex / Q, 1)},
+        "batched": {"what": f"all {T} frames in one persistent launch", "ms_per_launch": round(batch_ms, 5),
+                    "frames_per_s": round(T / (batch_ms * 1e-3), 1), "alg_bytes": int(b_alg),
+                    "hbm_frac": round(b_alg / (batch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "kernels": kernels,
+        "roofline": kernel_roofline("c1", dom, ph[dom], alg_bytes, coll_ops, Q),
+        "wall_s": round(wall, 4), "setup_s": round(setup_s, 2),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_c1(sc, frames_np)
+    print(json.dumps(out))
+
+
+def cpu_baseline_c1(sc, frames_np, reps=5):
+    """The float64 oracle on frames 1..reps of c1 (re-pose, refit, every query), all
+    host cores and one thread for the queries; medians over the frames."""
+    from oracle import gaussians as og, lbvh as ol, closest as oc, frame as ofr
+    t_all = time.perf_counter()
+    ref = ol.build(sc.verts0, sc.faces)
+    cores = omp_threads()
+    tot = {"all": [], "one": []}
+    try:
+        for f in range(1, reps + 1):
+            t = time.perf_counter()
+            live = ofr.vertex_buffer_update(frames_np, f)
+            og.repose(live, sc.faces, sc.binding)
+            ol.refit(ref["tree"], ol.leaf_boxes(frames_np[f], sc.faces, ref["perm"]))
+            host_s = time.perf_counter() - t
+            for key, th in (("all", cores), ("one", 1)):
+                oc.set_threads(th)
+                t = time.perf_counter()
+                oc.closest_point_mesh(frames_np[f], sc.faces, sc.queries)
+                tot[key].append(host_s + time.perf_counter() - t)
+    finally:
+        oc.set_threads(cores)
+    return {"value": 1.0 / float(np.median(tot["all"])), "unit": "frames/s", "cores": cores, "kind": "oracle",
+            "sample": f"median of {reps} whole frames (1-{reps}): float64 numpy re-pose and refit (one thread), "
+                      f"plain-C brute-force closest points of all {sc.queries.shape[1]} queries ({cores} threads)",
+            "single_thread": {"value": 1.0 / float(np.median(tot["one"])), "unit": "frames/s", "cores": 1,
+                              "sample": "the same frames with the queries on one thread"},
+            "wall_s": round(time.perf_counter() - t_all, 2)}
 
 
 def copy_calibration(mb, reps):
@@ -805,6 +1032,8 @@ def main():
     if args.steps < 1 or args.warmup < 0:
         print("--steps must be >= 1 and --warmup >= 0", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "c1":
+        return run_c1(args)
     if args.workload == "c3":
         return run_batched(args)
     if args.workload == "c4":
@@ -1047,6 +1276,37 @@ def main():
     # the target BVHs share one buffer: time their queries on one freshly built target
     phase_rebuild(0)
     ph["target_queries"] = timed(lambda r: phase_target_queries(0), reps)
+    # The paper's comparison on like terms: the same deformed template per frame, its
+    # tree refit or rebuilt from scratch, and the same collision queries without
+    # previous-frame hints on either tree.
+    tmpl_rb = mg.LBVH(NF, mg.MG_PRIM_TRIANGLES, dev)
+    like = {}
+    for f in sample_frames(T):
+        phase_copy(f)
+        phase_refit()
+        mg.lbvh_build(live, F, bvh=tmpl_rb)
+        r_ms = timed(lambda r: phase_refit(), reps)
+        b_ms = timed(lambda r: mg.lbvh_build(live, F, bvh=tmpl_rb), reps)
+        qr = timed(lambda r: phase_collide(hint=none_hint), max(10, reps // 6))
+        qb = timed(lambda r: mg.closest_point_query(tmpl_rb, live, particles, normal=True, out=col_t, **o_col),
+                   max(10, reps // 6))
+        for k, v in (("refit", r_ms), ("rebuild", b_ms), ("collide_refit_tree", qr), ("collide_rebuilt_tree", qb)):
+            like.setdefault(k, []).append(v)
+    like = {k: float(np.mean(v)) for k, v in like.items()}
+    fu_ms = ph["vertex_copy"] + ph["gaussian_update"]
+    refit_vs_rebuild = {
+        "what": "same deformed template per frame (6 frames across the sequence): copy + re-pose, then the tree "
+                "refit or rebuilt, then the collision queries without hints; kernel averages from HIP graphs",
+        "refit_ms": round(like["refit"], 5), "rebuild_ms": round(like["rebuild"], 5),
+        "collide_refit_tree_ms": round(like["collide_refit_tree"], 5),
+        "collide_rebuilt_tree_ms": round(like["collide_rebuilt_tree"], 5),
+        "refit_frame_ms": round(fu_ms + like["refit"] + like["collide_refit_tree"], 5),
+        "rebuild_frame_ms": round(fu_ms + like["rebuild"] + like["collide_rebuilt_tree"], 5),
+    }
+    refit_vs_rebuild["tree_speedup"] = round(like["rebuild"] / like["refit"], 3)
+    refit_vs_rebuild["frame_speedup"] = round(refit_vs_rebuild["rebuild_frame_ms"] / refit_vs_rebuild["refit_frame_ms"], 3)
+    phase_copy(0)
+    phase_refit()
     tf_mean = float(np.mean([f.shape[1] for _, f in targets_np]))
     tv_mean = float(np.mean([v.shape[1] for v, _ in targets_np]))
     alg_bytes = {
@@ -1082,17 +1342,7 @@ def main():
     coll_ops = OPS_EXPANSION * n_exp + OPS_LEAF_BOUND * n_lbox + OPS_EXACT * n_lex
     single = {k: ph[k] for k in ("gaussian_update", "refit", "collide")}   # the kernels of one phase
     dom = max(single, key=single.get)
-    if dom == "collide":
-        achieved = coll_ops / (ph[dom] * 1e-3) / 1e12
-        roofline = {"bound": "alu", "kernel": "traverse_batch_kernel (collision queries)", "achieved": round(achieved, 4),
-                    "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5),
-                    "traffic": measured_traffic(dom), "alg_ops_per_launch": int(coll_ops),
-                    "avg_launch_ms": round(ph[dom], 5), "hbm_frac_of_compulsory_bytes": kernels["collide"]["hbm_frac"]}
-    else:
-        achieved = alg_bytes[dom] / (ph[dom] * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
-                    "alg_bytes_per_launch": int(alg_bytes[dom]), "avg_launch_ms": round(ph[dom], 5)}
+    roofline = kernel_roofline(args.workload, dom, ph[dom], alg_bytes, coll_ops, Q)
     q_per_frame = 2 * Q + NV
     fps = 1000.0 / ms_per_step
     out = {
@@ -1104,9 +1354,13 @@ def main():
                    "gaussians": G, "particles": Q, "template_vertices_projected": NV,
                    "target_faces_mean": round(tf_mean), "timing": "eager" if args.eager else "hip-graph",
                    "streams": args.streams},
-        "refit_path": {"ms_per_frame": round(refit_path_ms, 5), "frames_per_s": round(1000.0 / refit_path_ms, 1)},
+        "refit_path": {"ms_per_frame": round(refit_path_ms, 5), "frames_per_s": round(1000.0 / refit_path_ms, 1),
+                       "what": "frame update + collision queries from the previous frame's faces"},
         "frame_update": dict(kernels["frame_update"], what="vertex copy, Gaussian re-pose, refit"),
-        "rebuild_path": {"ms_per_frame": round(rebuild_path_ms, 5), "frames_per_s": round(1000.0 / rebuild_path_ms, 1)},
+        "rebuild_path": {"ms_per_frame": round(rebuild_path_ms, 5), "frames_per_s": round(1000.0 / rebuild_path_ms, 1),
+                         "what": "varying-topology target: rebuild, collision queries and template projection "
+                                 "onto it (no hints exist across topologies)"},
+        "refit_vs_rebuild": refit_vs_rebuild,
         "queries_per_s": round(q_per_frame * fps, 1),
         "collide_queries_per_s": round(Q / (ph["collide"] * 1e-3), 1),
         "traversal": trav,
@@ -1119,12 +1373,12 @@ def main():
         "wall_s": round(wall, 4), "setup_s": round(setup_s, 2),
     }
     if not args.no_cpu_baseline:
-        # C2: whole frames (every query of every set, about 3 s each on the host's
-        # cores) until 10 s have run; C5: one frame, 8,000 queries per set, scaled
-        # (a whole frame would take hours)
-        full = max(sc.queries.shape[1], sc.n_verts)
-        out["cpu_baseline"] = cpu_baseline(sc, frames_np, targets_np,
-                                           args.cpu_sample or (full if args.workload == "c2" else 8000))
+        # about 2 s per frame on 16 host cores at C2 (a quarter of each query set), and
+        # 1,000 queries per set on one thread; C5 samples 4,000 and 250 queries per set
+        # (its host phases alone take seconds per frame)
+        n_all = args.cpu_sample or (12_500 if args.workload == "c2" else 4_000)
+        out["cpu_baseline"] = cpu_baseline(sc, frames_np, make_targets(cfg, range(6)) if n_used < 6 else targets_np,
+                                           n_all, max(50, n_all // (12 if args.workload == "c2" else 16)))
     print(json.dumps(out))
 
 

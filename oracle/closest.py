@@ -49,8 +49,15 @@ def _clib():
         lib.oracle_closest_point_mesh.restype = ctypes.c_int
         lib.oracle_nearest_points.argtypes = [P, I, P, I, P, P]
         lib.oracle_nearest_points.restype = None
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_threads.restype = None
         _lib = lib
     return _lib
+
+
+def set_threads(n):
+    """OpenMP threads of the plain-C brute force (a timing knob; results do not change)."""
+    _clib().oracle_set_threads(int(n))
 
 
 def _ptr(a):

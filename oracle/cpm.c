@@ -17,6 +17,9 @@
  */
 #include <math.h>
 #include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct { double x, y, z; } d3;
 
@@ -151,4 +154,15 @@ void oracle_nearest_points(const double *src, int64_t n, const double *dst, int6
         idx[i] = bi;
         dist2[i] = best;
     }
+}
+
+/* Thread count of the OpenMP loops above (for timing the checker on one core or
+ * on all of them; the results do not depend on it).  n <= 0 is ignored. */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }

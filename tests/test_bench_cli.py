@@ -23,3 +23,16 @@ def test_unknown_workload_is_rejected():
     r = _run("--workload", "c9")
     assert r.returncode != 0
     assert "invalid choice" in r.stderr
+
+
+def test_cpu_baseline_reports_all_core_and_single_thread():
+    import numpy as np
+    import bench
+    from synth import make_config
+    sc = make_config(2, small=True)
+    frames = sc.frames(range(6))
+    targets = [sc.target(t) for t in range(6)]
+    r = bench.cpu_baseline(sc, frames, targets, 300, 40, reps=2)
+    assert r["kind"] == "oracle" and r["unit"] == "frames/s" and r["cores"] >= 1
+    assert r["value"] > 0 and r["single_thread"]["value"] > 0 and r["single_thread"]["cores"] == 1
+    assert np.isfinite(list(r["seconds_per_frame_median"].values())).all()
