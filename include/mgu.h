@@ -169,10 +169,13 @@ mg_status mg_mesh_gaussian_update_backward(const float *verts, int32_t n_verts, 
  *                                refit rewrites all of it.
  *   node_aux    int32  [n-1]     refit schedule: index among the "top" nodes (those
  *                                with more than 2^chunk_log2 leaves), or -1
+ *   child       int32  [2][n-1]  child references of each internal node, as in the
+ *                                records (>= 0 internal node, < 0 leaf ~i)
  *   top_nodes   int32  [n]       node id of each top node (header.n_top of them)
- *   top_link    int32  [2][n]    plane 0, per top node: (parent's top index << 1) |
- *                                slot, -1 for the root; plane 1, per subtree: the
- *                                same for the subtree root's parent
+ *   top_child   int32  [4][n]    plane s < 2, per top node: its child in slot s,
+ *                                as that child's top index, or ~k for the root of
+ *                                subtree k; plane 2 + s: that child's node id when
+ *                                it is a top node (0 otherwise)
  *   subtrees    int32  [3][n]    per subtree (header.n_sub): root reference, first
  *                                and last leaf; the subtrees (at most 2^chunk_log2
  *                                leaves, children of top nodes) cut the tree
@@ -218,8 +221,9 @@ typedef struct mg_lbvh_layout {
     int64_t off_node_parent;
     int64_t off_nodes;
     int64_t off_node_aux;
+    int64_t off_child;
     int64_t off_top_nodes;
-    int64_t off_top_link;
+    int64_t off_top_child;
     int64_t off_subtrees;
     int64_t off_deposits;
     int64_t off_top_scratch;

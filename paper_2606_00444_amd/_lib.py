@@ -33,8 +33,8 @@ class MguError(RuntimeError):
 
 class LbvhLayout(ctypes.Structure):
     _fields_ = [(n, I64) for n in ("total_bytes", "off_header", "off_codes", "off_prim", "off_leaf_faces",
-                                   "off_leaf_parent", "off_node_parent", "off_nodes", "off_node_aux",
-                                   "off_top_nodes", "off_top_link", "off_subtrees",
+                                   "off_leaf_parent", "off_node_parent", "off_nodes", "off_node_aux", "off_child",
+                                   "off_top_nodes", "off_top_child", "off_subtrees",
                                    "off_deposits", "off_top_scratch", "off_inv_prim")]
 
 

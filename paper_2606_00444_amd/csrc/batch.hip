@@ -31,8 +31,9 @@ constexpr int kSpin = 1 << 22;
 
 struct PlanScene {
     mg_batch_scene s;
-    const int32_t *leaf_faces, *prim, *inv_prim, *leaf_parent, *node_parent, *top_nodes;
-    const int32_t *top_parent, *sub_parent, *subtrees;
+    const int32_t *leaf_faces, *prim, *inv_prim, *leaf_parent, *node_parent, *node_aux, *top_nodes;
+    const int32_t *top_child, *subtrees;
+    const int32_t *child;                   // the BVH's child references [2][n-1]
     const int32_t *n_top, *n_sub;           // the scene BVH's counts (device)
     float4 *deposit;                        // [n_frames][n_sub][3] subtree-root summaries
     float4 *top_scratch;                    // [n_frames][13 tstride / 4] phase-2 state when n_top > kBatchTopLds, else null
@@ -90,7 +91,7 @@ inline mg_status read_schedule(const mg_batch_scene &s, Schedule &S) {
 // slots and arrival words, 13 words per top node, the count rounded up to a
 // multiple of 4 so that every block stays 16-byte aligned).
 __host__ __device__ inline int64_t top_stride(int32_t T) { return (static_cast<int64_t>(T) + 3) & ~int64_t(3); }
-__host__ __device__ inline int64_t top_scratch_words(int32_t T) { return 13 * top_stride(T) + 12 * kDummyWaves; }
+__host__ __device__ inline int64_t top_scratch_words(int32_t T) { return 13 * top_stride(T); }
 inline int64_t frame_scratch_words(int32_t T, int32_t NS) {
     return 12 * static_cast<int64_t>(NS) + (T > kBatchTopLds ? top_scratch_words(T) : 0);
 }
@@ -180,8 +181,9 @@ __device__ RefitArgs refit_args(const PlanScene &P, int64_t t, PlanHeader *h) {
     a.node_parent = P.node_parent;
     a.nodes = reinterpret_cast<float4 *>(s.nodes + t * 24 * static_cast<int64_t>(s.n_faces > 1 ? s.n_faces - 1 : 0));
     a.top_nodes = P.top_nodes;
-    a.top_parent = P.top_parent;
-    a.sub_parent = P.sub_parent;
+    a.child = P.child;
+    a.node_aux = P.node_aux;
+    a.top_child = P.top_child;
     a.subtrees = P.subtrees;
     a.deposit = P.deposit + t * 3 * static_cast<int64_t>(P.n_sub_host);
     a.tstride = P.tstride;
@@ -273,9 +275,9 @@ __device__ __noinline__ void item_refit_top(PlanHeader *h, int si, int64_t t) {
     if (T != P.n_top_host || NS != P.n_sub_host) {
         if (threadIdx.x == 0) atomicOr(&h->status, 2);   // the BVH was rebuilt after planning
     } else if (T > 0 && T <= kBatchTopLds) {
-        refit_top<true, kBlock, false>(r, T, NS, smem);
+        refit_top<true, kBlock, false, (kBatchTopLds + kBlock - 1) / kBlock>(r, T, NS, smem);
     } else if (T > kBatchTopLds) {
-        refit_top<true, kBlock, true>(r, T, NS, smem);
+        refit_top<true, kBlock, true, 1>(r, T, NS, smem);
     }
     signal(&refit_done[sf], 1u);
 }
@@ -456,8 +458,9 @@ extern "C" mg_status mg_batch_plan_init(const mg_batch_scene *scenes, int32_t n_
         P.leaf_parent = reinterpret_cast<const int32_t *>(b + L.off_leaf_parent);
         P.node_parent = reinterpret_cast<const int32_t *>(b + L.off_node_parent);
         P.top_nodes = reinterpret_cast<const int32_t *>(b + L.off_top_nodes);
-        P.top_parent = reinterpret_cast<const int32_t *>(b + L.off_top_link);
-        P.sub_parent = P.top_parent + s.n_faces;
+        P.node_aux = reinterpret_cast<const int32_t *>(b + L.off_node_aux);
+        P.top_child = reinterpret_cast<const int32_t *>(b + L.off_top_child);
+        P.child = reinterpret_cast<const int32_t *>(b + L.off_child);
         P.subtrees = reinterpret_cast<const int32_t *>(b + L.off_subtrees);
         P.n_top = &reinterpret_cast<const mg_lbvh_header *>(b + L.off_header)->n_top;
         P.n_sub = &reinterpret_cast<const mg_lbvh_header *>(b + L.off_header)->n_sub;

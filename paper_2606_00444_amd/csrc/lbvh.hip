@@ -16,10 +16,11 @@
 //            digit bits), global digit offsets by decoupled look-back
 //   tree     Karras radix tree per internal node + leaf permutation of faces;
 //            lists the subtrees of at most C leaves that cut the tree and the
-//            "top" nodes above them, then links each top node to its parent
-//   refit    one kernel: a workgroup per subtree climbs it with summary slots
-//            in LDS, and the workgroup that finishes the last subtree climbs
-//            the top nodes from the deposited subtree roots (see refit.hpp)
+//            "top" nodes above them, then lists each top node's two children
+//   refit    one kernel: a workgroup per subtree refits it level by level
+//            with summary slots in LDS, and the workgroup that finishes the
+//            last subtree refits the top nodes from the deposited subtree
+//            roots (see refit.hpp)
 //
 // Node records are child-centric (96 B: both children's boxes, or a leaf
 // child's triangle itself) so a traversal step reads one record and a leaf
@@ -59,11 +60,12 @@ inline mg_lbvh_layout make_layout(int64_t n, int kind) {
     L.off_node_parent = o; o += align256(4 * m);
     L.off_nodes = o;       o += align256(96 * m);
     L.off_node_aux = o;    o += align256(4 * m);
+    L.off_child = o;       o += align256(8 * m);
     L.off_top_nodes = o;   o += align256(4 * n);
-    L.off_top_link = o;    o += align256(8 * n);
+    L.off_top_child = o;   o += align256(16 * n);
     L.off_subtrees = o;    o += align256(12 * n);
     L.off_deposits = o;    o += align256(48 * n);
-    L.off_top_scratch = o; o += align256(52 * n + kDummyBytes);
+    L.off_top_scratch = o; o += align256(52 * n);
     L.off_inv_prim = o;    o += align256(4 * n);
     L.total_bytes = o;
     return L;
@@ -390,6 +392,7 @@ __global__ __launch_bounds__(256) void hierarchy_kernel(const uint32_t *__restri
                                                         int32_t *__restrict__ leaf_parent,
                                                         int32_t *__restrict__ node_parent,
                                                         int32_t *__restrict__ node_aux,
+                                                        int32_t *__restrict__ child,
                                                         int32_t *__restrict__ top_nodes,
                                                         int32_t *__restrict__ subtrees,
                                                         float *__restrict__ nodes,
@@ -451,8 +454,12 @@ __global__ __launch_bounds__(256) void hierarchy_kernel(const uint32_t *__restri
     if (i == 0) node_parent[0] = -1;
     // child references live in the records' first .w word of each slot; the refit
     // rewrites the same values, so they are valid before any box exists
-    nodes[24 * i + 3] = __int_as_float(static_cast<int32_t>(lo == gamma ? ~gamma : gamma));
-    nodes[24 * i + 15] = __int_as_float(static_cast<int32_t>(hi == gamma + 1 ? ~(gamma + 1) : gamma + 1));
+    const int32_t c0 = static_cast<int32_t>(lo == gamma ? ~gamma : gamma);
+    const int32_t c1 = static_cast<int32_t>(hi == gamma + 1 ? ~(gamma + 1) : gamma + 1);
+    nodes[24 * i + 3] = __int_as_float(c0);
+    nodes[24 * i + 15] = __int_as_float(c1);
+    child[i] = c0;
+    child[n - 1 + i] = c1;
     // the cut: a node with more than C leaves is a top node, and each of its
     // children with at most C leaves roots a subtree (list order is irrelevant)
     const int64_t C = int64_t(1) << chunk_log2;
@@ -526,87 +533,95 @@ __global__ __launch_bounds__(1024) void order_subtrees_kernel(int32_t *__restric
     }
 }
 
-// The top links: per top node, (its parent's top index << 1) | slot (-1 for
-// the root); per subtree, the same for its root's parent.
-__global__ __launch_bounds__(256) void top_link_kernel(const int32_t *__restrict__ node_aux,
-                                                       const int32_t *__restrict__ top_nodes,
-                                                       const int32_t *__restrict__ node_parent,
-                                                       const int32_t *__restrict__ leaf_parent,
-                                                       const int32_t *__restrict__ subtrees, int64_t n,
-                                                       int32_t *__restrict__ top_link, mg_lbvh_header *hdr) {
+// The top children: per top node and slot, the child's top index, or ~k when
+// the child is the root of subtree k (every top node has two children of
+// these kinds), and in planes 2 and 3 a top child's node id (0 for a subtree).
+__global__ __launch_bounds__(256) void top_child_kernel(const int32_t *__restrict__ node_aux,
+                                                        const int32_t *__restrict__ top_nodes,
+                                                        const int32_t *__restrict__ node_parent,
+                                                        const int32_t *__restrict__ leaf_parent,
+                                                        const int32_t *__restrict__ subtrees, int64_t n,
+                                                        int32_t *__restrict__ top_child, mg_lbvh_header *hdr) {
     const int T = hdr->n_top, NS = hdr->n_sub;
-    auto link = [&](int32_t tag) -> int32_t {
-        if (tag < 0) return -1;
+    if (NS < 2) return;                       // a single subtree is the whole tree: no top
+    // the parent tag of a top node or subtree root names its slot in a top node
+    auto put = [&](int32_t tag, int32_t v, int32_t node) {
+        if (tag < 0) return;                  // the root
         const int32_t p = tag >> 1;
-        if (p >= n - 1) { atomicOr(&hdr->status, 8); return -1; }
+        if (p >= n - 1) { atomicOr(&hdr->status, 8); return; }
         const int32_t t = node_aux[p];
-        if (t < 0 || t >= T) { atomicOr(&hdr->status, 8); return -1; }
-        return (t << 1) | (tag & 1);
+        if (t < 0 || t >= T) { atomicOr(&hdr->status, 8); return; }
+        top_child[(tag & 1) * n + t] = v;
+        top_child[(2 + (tag & 1)) * n + t] = node;
     };
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < T; t += gridDim.x * blockDim.x) {
         const int32_t p = top_nodes[t];
-        if (p < 0 || p >= n - 1) { atomicOr(&hdr->status, 8); top_link[t] = -1; continue; }
-        top_link[t] = link(node_parent[p]);
+        if (p < 0 || p >= n - 1) { atomicOr(&hdr->status, 8); continue; }
+        put(node_parent[p], t, p);
     }
-    if (NS < 2) return;                       // a single subtree is the whole tree: no top
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < NS; k += gridDim.x * blockDim.x) {
         const int32_t r = subtrees[k];
         const bool leaf = r < 0;
         const int64_t id = leaf ? ~static_cast<int64_t>(r) : r;
-        if (id >= (leaf ? n : n - 1)) { atomicOr(&hdr->status, 8); top_link[n + k] = -1; continue; }
-        top_link[n + k] = link(leaf ? leaf_parent[id] : node_parent[id]);
+        if (id >= (leaf ? n : n - 1)) { atomicOr(&hdr->status, 8); continue; }
+        put(leaf ? leaf_parent[id] : node_parent[id], ~k, 0);
     }
 }
 
-// The refit: workgroups of kThreads take subtrees (kLeaves adjacent leaves per
-// thread); each counts the subtrees it finished into the header's arrival word
-// once their deposits are complete, and the one that brings it to the number
-// of subtrees climbs the top nodes (then clears the word for the next refit).
-// smem: refit_lds(C) bytes.
-template <bool kTri, int kThreads, int kLeaves>
-__global__ __launch_bounds__(kThreads) void refit_kernel(RefitArgs a) {
+// The refit: workgroups of kThreads take subtrees (kPer nodes per thread);
+// each counts the subtrees it finished into the header's arrival word once
+// their deposits are complete, and the one that brings it to the number of
+// subtrees refits the top nodes (then clears the word for the next refit).
+// smem: refit_lds_bytes(chunk_log2) bytes.
+template <bool kTri, int kThreads, int kPer, int kMinWaves>
+__global__ __launch_bounds__(kThreads, kMinWaves) void refit_kernel(RefitArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_last;
     const int32_t ns = *a.n_sub;
     int mine = 0;
     for (int64_t k = blockIdx.x; k < ns; k += gridDim.x) {
-        refit_subtree<kTri, kThreads, kLeaves>(a, k, smem);   // ends with a barrier
+        refit_subtree<kTri, kThreads, kPer>(a, k, smem);     // ends with a barrier
         ++mine;
     }
-    if (ns < 2 || mine == 0) return;          // one subtree is the whole tree: its climb wrote the root
+    if (ns < 2 || mine == 0) return;          // one subtree is the whole tree: its root is written
     if (threadIdx.x == 0)
         s_last = __hip_atomic_fetch_add(a.arrivals, static_cast<uint32_t>(mine), __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT) + mine == static_cast<uint32_t>(ns);
     __syncthreads();
     if (!s_last) return;
     const int T = *a.n_top;
+    static_assert(kTopCap % kThreads == 0, "the top nodes kept in LDS are dealt evenly");
     if (T < 1 || T >= a.n) {
         if (threadIdx.x == 0) atomicOr(a.status, 8);
-    } else if (refit_top_lds(T) <= refit_lds_bytes(a.chunk_log2)) {
-        refit_top<kTri, kThreads, false>(a, T, ns, smem);
+    } else if (T <= kTopCap) {
+        refit_top<kTri, kThreads, false, kTopCap / kThreads>(a, T, ns, smem);
     } else {
-        refit_top<kTri, kThreads, true>(a, T, ns, smem);
+        refit_top<kTri, kThreads, true, 1>(a, T, ns, smem);
     }
     if (threadIdx.x == 0) __hip_atomic_store(a.arrivals, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <bool kTri, int kThreads, int kLeaves>
+template <bool kTri, int kThreads, int kPer, int kMinWaves>
 mg_status launch_refit_t(const RefitArgs &a, int grid, hipStream_t s) {
     const size_t lds = refit_lds_bytes(a.chunk_log2);
     if (lds > 65536)    // beyond the default dynamic LDS limit (gfx950 has 160 KB per workgroup)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&refit_kernel<kTri, kThreads, kLeaves>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&refit_kernel<kTri, kThreads, kPer, kMinWaves>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-    hipLaunchKernelGGL((refit_kernel<kTri, kThreads, kLeaves>), dim3(grid), dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL((refit_kernel<kTri, kThreads, kPer, kMinWaves>), dim3(grid), dim3(kThreads), lds, s, a);
     return launch_status();
 }
 
-// Workgroups of 512 threads (two fit a CU beside each other's LDS), one leaf
-// each, or 2 or 4 adjacent leaves for 1024- and 2048-leaf subtrees.
+// A thread per internal node of a subtree of up to 256 or 512 leaves, and 2
+// or 4 nodes per thread in 512-thread workgroups for 1024- and 2048-leaf
+// subtrees.  Up to 1024 leaves three workgroups fit a CU beside each other
+// (about 50 KB of LDS each, six waves per SIMD for 512 threads), so a tree
+// of 500,000 faces has nearly all its subtrees resident at once.
 template <bool kTri>
 mg_status launch_refit_k(const RefitArgs &a, int grid, hipStream_t s) {
-    if (a.chunk_log2 <= 9) return launch_refit_t<kTri, 512, 1>(a, grid, s);
-    if (a.chunk_log2 == 10) return launch_refit_t<kTri, 512, 2>(a, grid, s);
-    return launch_refit_t<kTri, 512, 4>(a, grid, s);
+    if (a.chunk_log2 <= 8) return launch_refit_t<kTri, 256, 1, 3>(a, grid, s);
+    if (a.chunk_log2 == 9) return launch_refit_t<kTri, 512, 1, 6>(a, grid, s);
+    if (a.chunk_log2 == 10) return launch_refit_t<kTri, 512, 2, 6>(a, grid, s);
+    return launch_refit_t<kTri, 512, 4, 2>(a, grid, s);
 }
 
 mg_status check_kind(int32_t kind) {
@@ -622,9 +637,10 @@ RefitArgs refit_args(const float *verts, int64_t nv, void *bvh, int64_t n, int k
     a.leaf_parent = at<int32_t>(bvh, L.off_leaf_parent);
     a.node_parent = at<int32_t>(bvh, L.off_node_parent);
     a.nodes = at<float4>(bvh, L.off_nodes);
+    a.child = at<int32_t>(bvh, L.off_child);
+    a.node_aux = at<int32_t>(bvh, L.off_node_aux);
     a.top_nodes = at<int32_t>(bvh, L.off_top_nodes);
-    a.top_parent = at<int32_t>(bvh, L.off_top_link);
-    a.sub_parent = at<int32_t>(bvh, L.off_top_link) + n;
+    a.top_child = at<int32_t>(bvh, L.off_top_child);
     a.subtrees = at<int32_t>(bvh, L.off_subtrees);
     a.deposit = at<float4>(bvh, L.off_deposits);
     a.top_scratch = at<float4>(bvh, L.off_top_scratch);
@@ -723,14 +739,14 @@ mg_status build_into(const float *verts, int32_t n_verts, const int32_t *faces, 
                        at<int32_t>(bvh, L.off_inv_prim), n, fz,
                        fz ? at<int32_t>(bvh, L.off_leaf_faces) : nullptr, at<int32_t>(bvh, L.off_leaf_parent),
                        at<int32_t>(bvh, L.off_node_parent), at<int32_t>(bvh, L.off_node_aux),
-                       at<int32_t>(bvh, L.off_top_nodes), at<int32_t>(bvh, L.off_subtrees),
+                       at<int32_t>(bvh, L.off_child), at<int32_t>(bvh, L.off_top_nodes), at<int32_t>(bvh, L.off_subtrees),
                        at<float>(bvh, L.off_nodes), hdr, chunk_log2_for(n));
     if (chunk_log2_for(n) >= 10)      // subtrees may outnumber the resident refit workgroups
         hipLaunchKernelGGL(order_subtrees_kernel, dim3(1), dim3(1024), 0, s, at<int32_t>(bvh, L.off_subtrees), n, hdr);
-    hipLaunchKernelGGL(top_link_kernel, dim3(static_cast<unsigned>(std::min<int64_t>(blocks_for(n, 256), 64))),
+    hipLaunchKernelGGL(top_child_kernel, dim3(static_cast<unsigned>(std::min<int64_t>(blocks_for(n, 256), 64))),
                        dim3(256), 0, s, at<int32_t>(bvh, L.off_node_aux), at<int32_t>(bvh, L.off_top_nodes),
                        at<int32_t>(bvh, L.off_node_parent), at<int32_t>(bvh, L.off_leaf_parent),
-                       at<int32_t>(bvh, L.off_subtrees), n, at<int32_t>(bvh, L.off_top_link), hdr);
+                       at<int32_t>(bvh, L.off_subtrees), n, at<int32_t>(bvh, L.off_top_child), hdr);
     if (launch_status() != MG_OK) return MG_ERR_HIP;
     return launch_refit(verts, n_verts, bvh, n, prim_kind, s);
 }

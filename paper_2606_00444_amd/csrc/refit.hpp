@@ -5,25 +5,32 @@
 // root is a child, with at most C leaves, of a node with more than C (or the
 // whole tree when it has at most C leaves).  Above the cut lie the "top"
 // nodes, one fewer than the subtrees.  Both sets are fixed by the topology and
-// listed once, when the tree is built, with the parent of every top node and
-// of every subtree root among the top nodes (the top links).
+// listed once, when the tree is built, with the two children of every top node
+// (a top node or a subtree).
 //
 // A finished node hands its parent a 12-float summary: its box, the unit
 // direction d of the area-weighted normal sum of the faces below it, the sum's
-// length, and the slab [a, b] of d.x over those faces.  Each node has one
-// summary slot and an arrival word: the first child to finish publishes its
-// summary there and stops; the second reads it, joins the two in registers,
-// writes the node's slot in its parent's record and climbs on.  A level of
-// the climb is one LDS atomic, one 48-byte LDS read and the join.
+// length, and the slab [a, b] of d.x over those faces.
+//
+// The schedule is level-synchronous.  Each thread owns fixed internal nodes;
+// at set-up it gathers the primitives of its nodes' leaf children, writes them
+// into the nodes' records and keeps their summaries in registers.  Then, step
+// by step, every node whose internal children are finished joins its two
+// children's summaries (from registers or LDS slots), writes its record and
+// its own slot and marks itself done; a workgroup barrier ends each step.  A
+// node of height h finishes in step h - 1, so a subtree takes as many steps as
+// it is high, with no atomics and no waiting beyond the barriers.
 //
 // Phase 1 (a workgroup per subtree): a Karras node covers a contiguous leaf
 // range and its index is one end of that range, so the internal nodes of a
-// subtree over leaves [f, l] have indices in [f, l] and their slots live in
-// LDS.  The subtree root's summary is deposited for phase 2 with device-scope
-// stores.  Phase 2 (one workgroup): the same climb through the top nodes, one
-// thread from each deposited subtree root.  The plain refit runs it in the
-// workgroup that finishes the last subtree (an arrival counter in the BVH
-// header), the batched kernel as a work item of its own.
+// subtree over leaves [f, l] have indices in [f, l] (the one other index in
+// that range, if any, is a top node) and their slots live in LDS.  The
+// subtree root's summary goes into its parent's record and, with device-scope
+// stores, to a deposit for phase 2.  Phase 2 (one workgroup) runs the same
+// steps over the top nodes, whose subtree children's summaries are the
+// deposits.  The plain refit runs it in the workgroup that finishes the last
+// subtree (an arrival counter in the BVH header), the batched kernel as a work
+// item of its own.
 //
 // Boxes are exact (min/max only) and each join takes its two children in slot
 // order with contraction off and explicit fused multiply-adds, so any schedule
@@ -42,14 +49,15 @@ struct RefitArgs {
     const int32_t *prim;
     const int32_t *leaf_parent; const int32_t *node_parent;
     float4 *nodes;                // [n-1][6] records written by this refit
+    const int32_t *child;         // [2][n-1] child references of the internal nodes
+    const int32_t *node_aux;      // [n-1] top index of a top node, -1 below the cut
     const int32_t *top_nodes;     // [T] node id of each top node
-    const int32_t *top_parent;    // [T] (parent's top index << 1) | slot, -1 for the root
-    const int32_t *sub_parent;    // [n_sub] (top parent's index << 1) | slot of each subtree root
+    const int32_t *top_child;     // [4][n]: per top node and slot, the child's top index,
+                                  // or ~k for subtree k; then a top child's node id
     const int32_t *subtrees;      // [3][n]: root reference, first leaf, last leaf
     float4 *deposit;              // [n_sub][3] subtree-root summaries (device-coherent)
-    float4 *top_scratch;          // [tstride][3] summary slots, [kDummyWaves][3] dummies, then
-    int64_t tstride;              // uint32 [tstride] arrival words: phase-2 state when T
-                                  // exceeds the LDS capacity
+    float4 *top_scratch;          // [tstride][3] summary slots, then uint32 [tstride]
+    int64_t tstride;              // done words: phase-2 state when T exceeds the LDS capacity
     float *root;                  // root box: lo at [0..2], hi at [4..6]
     int32_t *status;              // error word
     const int32_t *hdr_nv;        // vertex count of the build (header), or nullptr
@@ -68,19 +76,14 @@ struct Sum {
     float a, b;                   // slab: a <= d.x <= b over the faces below
 };
 
-// LDS bytes per subtree node (three float4, an arrival word and its parent
-// link) and per top node (the same, plus its node id), and the per-wave dummy
-// slots of the hand-off (below).
-constexpr size_t kSubSlotBytes = 56;
-constexpr size_t kTopSlotBytes = 60;
-constexpr int kDummyWaves = 16;   // waves of a 1024-thread workgroup
-constexpr size_t kDummyBytes = kDummyWaves * 48;
-constexpr int kTopCap = 1024;     // top nodes the plain refit's LDS holds at least
+// LDS of the two phases: a 48-byte summary slot and a done byte per node, and
+// the step loop's finish word.
+constexpr int kTopCap = 1024;     // top nodes the plain refit keeps in LDS (more: global scratch)
 
-constexpr size_t refit_sub_lds(int64_t C) { return static_cast<size_t>(C) * kSubSlotBytes + kDummyBytes; }
-constexpr size_t refit_top_lds(int64_t T) { return static_cast<size_t>(T) * kTopSlotBytes + kDummyBytes; }
-// LDS of the plain refit kernel: a subtree's slots, and room for at least
-// kTopCap top nodes in the workgroup that climbs the top.
+constexpr size_t refit_sub_lds(int64_t C) { return static_cast<size_t>(C) * 49 + 16; }
+constexpr size_t refit_top_lds(int64_t T) { return static_cast<size_t>(T) * 49 + 16; }
+// LDS of the plain refit kernel: a subtree's slots, and room for kTopCap top
+// nodes in the workgroup that refits the top.
 constexpr size_t refit_lds_bytes(int chunk_log2) {
     return refit_sub_lds(int64_t(1) << chunk_log2) > refit_top_lds(kTopCap) ? refit_sub_lds(int64_t(1) << chunk_log2)
                                                                             : refit_top_lds(kTopCap);
@@ -195,24 +198,6 @@ __device__ __forceinline__ Sum join(const Sum &L, const Sum &R) {
     return P;
 }
 
-// The join of a node whose children's summaries are `mine` (the climbing
-// lane's, in slot `slot`) and `other`: the two are put in slot order with
-// selects, so a wave whose lanes came from either side runs one join.
-template <bool kTri>
-__device__ __forceinline__ Sum join_slots(const Sum &mine, const Sum &other, int slot) {
-    const bool sw = slot != 0;
-    Sum L, R;
-    L.lo = f3{sw ? other.lo.x : mine.lo.x, sw ? other.lo.y : mine.lo.y, sw ? other.lo.z : mine.lo.z};
-    L.hi = f3{sw ? other.hi.x : mine.hi.x, sw ? other.hi.y : mine.hi.y, sw ? other.hi.z : mine.hi.z};
-    L.d = f3{sw ? other.d.x : mine.d.x, sw ? other.d.y : mine.d.y, sw ? other.d.z : mine.d.z};
-    L.sn = sw ? other.sn : mine.sn; L.a = sw ? other.a : mine.a; L.b = sw ? other.b : mine.b;
-    R.lo = f3{sw ? mine.lo.x : other.lo.x, sw ? mine.lo.y : other.lo.y, sw ? mine.lo.z : other.lo.z};
-    R.hi = f3{sw ? mine.hi.x : other.hi.x, sw ? mine.hi.y : other.hi.y, sw ? mine.hi.z : other.hi.z};
-    R.d = f3{sw ? mine.d.x : other.d.x, sw ? mine.d.y : other.d.y, sw ? mine.d.z : other.d.z};
-    R.sn = sw ? mine.sn : other.sn; R.a = sw ? mine.a : other.a; R.b = sw ? mine.b : other.b;
-    return join<kTri>(L, R);
-}
-
 // A summary in three float4 and back: (lo, sn) (hi, a) (d, b).
 __device__ __forceinline__ void pack(const Sum &S, float4 v[3]) {
     v[0] = make_float4(S.lo.x, S.lo.y, S.lo.z, S.sn);
@@ -244,301 +229,406 @@ __device__ __forceinline__ void write_root(float *root, const Sum &S) {
     root[4] = S.hi.x; root[5] = S.hi.y; root[6] = S.hi.z;
 }
 
-// Device-scope stores and loads of a deposited summary: visible to a workgroup
-// on another XCD without a write-back of this XCD's L2.  The storing thread
-// waits for its stores to complete before its workgroup signals arrival.
+// Device-scope stores and loads of a deposited summary (six 64-bit words, the
+// float pairs of its three float4 (lo, sn) (hi, a) (d, b)): visible to a
+// workgroup on another XCD without a write-back of this XCD's L2.  The storing
+// thread waits for its stores to complete before its workgroup signals arrival.
+__device__ __forceinline__ uint64_t pack2(float x, float y) {
+    return static_cast<uint64_t>(__float_as_uint(x)) | (static_cast<uint64_t>(__float_as_uint(y)) << 32);
+}
+__device__ __forceinline__ float lo32(uint64_t w) { return __uint_as_float(static_cast<uint32_t>(w)); }
+__device__ __forceinline__ float hi32(uint64_t w) { return __uint_as_float(static_cast<uint32_t>(w >> 32)); }
+
 __device__ __forceinline__ void deposit_store(float4 *dst, const Sum &S) {
     float4 v[3];
     pack(S, v);
-    float *f = reinterpret_cast<float *>(dst);
+    uint64_t *w = reinterpret_cast<uint64_t *>(dst);
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        __hip_atomic_store(f + 4 * q + 0, v[q].x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(f + 4 * q + 1, v[q].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(f + 4 * q + 2, v[q].z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(f + 4 * q + 3, v[q].w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(w + 2 * q, pack2(v[q].x, v[q].y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(w + 2 * q + 1, pack2(v[q].z, v[q].w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __builtin_amdgcn_s_waitcnt(0);
 }
-__device__ __forceinline__ Sum deposit_load(const float4 *src) {
-    const float *f = reinterpret_cast<const float *>(src);
-    float w[12];
+__device__ __forceinline__ void deposit_load_words(const float4 *src, uint64_t w[6]) {
+    const uint64_t *p = reinterpret_cast<const uint64_t *>(src);
 #pragma unroll
-    for (int q = 0; q < 12; ++q) w[q] = __hip_atomic_load(f + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return unpack(make_float4(w[0], w[1], w[2], w[3]), make_float4(w[4], w[5], w[6], w[7]),
-                  make_float4(w[8], w[9], w[10], w[11]));
+    for (int q = 0; q < 6; ++q) w[q] = __hip_atomic_load(p + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ Sum sum_of_words(const uint64_t w[6]) {
+    return unpack(make_float4(lo32(w[0]), hi32(w[0]), lo32(w[1]), hi32(w[1])),
+                  make_float4(lo32(w[2]), hi32(w[2]), lo32(w[3]), hi32(w[3])),
+                  make_float4(lo32(w[4]), hi32(w[4]), lo32(w[5]), hi32(w[5])));
+}
+__device__ __forceinline__ Sum deposit_load(const float4 *src) {
+    uint64_t w[6];
+    deposit_load_words(src, w);
+    return sum_of_words(w);
 }
 
-// ---------------------------------------------------------------- the climb
-// Arrival word of a node: bit 0 is set by the first child to arrive, bit 1
-// once that child's summary is in the slot.  arrive() returns true for the
-// second child, with the first one's summary in `other`.  Slots and words are
-// in LDS (workgroup scope), or with kGlobal in global scratch used by one
-// workgroup (device scope, so no stale cache line from an earlier launch on
-// another XCD is read).
-//
-// Two children of a node are often climbed by lanes of one wave that arrive
-// in the same instruction, and a lane that waited for an unpublished sibling
-// of its own wave would wait for ever (a wave does not run its other lanes
-// while one spins).  So the publication has no branch: every arriving lane
-// stores its summary - the first child into the node's slot, the second into
-// its wave's dummy slot - and ors the published bit (0 for the second) in the
-// same straight-line instructions, before any lane can start waiting.  A lane
-// then waits only for a first child in another wave, which publishes without
-// waiting for anything.
-constexpr int kSlotSpin = 1 << 20;
+// ---------------------------------------------------------------- the steps
+// Step loop bookkeeping.  A node's mark starts at kNotDone; finished in step s
+// it becomes s + 1, and a parent in step s takes a child whose mark is at most
+// s (a leaf or subtree child counts as 0): every slot is read only in a step
+// after the one that wrote it, so the
+// barrier between the steps orders all slot accesses and no slot needs a
+// fence of its own.  The LDS barrier fences LDS alone: a fence of every
+// address space would also wait for the record stores in flight (on CDNA,
+// vector loads and stores share one counter).
+constexpr int kMaxSteps = 64;     // a valid tree is at most 62 levels high
+constexpr uint8_t kNotDone = 0xff;
 
-// In LDS the words are relaxed atomics ordered by fences on LDS alone: a fence
-// of every address space would also wait for the climb's record stores (on
-// CDNA, vector loads and stores share one counter), a global store's latency
-// per level.
-template <bool kGlobal>
-__device__ __forceinline__ uint32_t word_or(uint32_t *w, uint32_t v) {
-    if (kGlobal) return __hip_atomic_fetch_or(w, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    return __hip_atomic_fetch_or(w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+__device__ __forceinline__ void lds_step_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
-template <bool kGlobal>
-__device__ __forceinline__ uint32_t word_load(uint32_t *w) {
-    if (kGlobal) return __hip_atomic_load(w, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+
+__device__ __forceinline__ void lds_slot_store(float4 *slot, const Sum &S) {
+    float4 v[3];
+    pack(S, v);
+    slot[0] = v[0]; slot[1] = v[1]; slot[2] = v[2];
 }
-template <bool kGlobal>
-__device__ __forceinline__ void lds_release() {
-    if (!kGlobal) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+__device__ __forceinline__ Sum lds_slot_load(const float4 *slot) { return unpack(slot[0], slot[1], slot[2]); }
+
+// The record of a leaf child: (v0, ~leaf) (v1, id) (v2, 0), or for a point
+// (p, ~leaf) (p, id).
+template <bool kTri>
+__device__ __forceinline__ void write_leaf(float4 *rec, int64_t leaf, int32_t id, f3 x, f3 y, f3 z) {
+    rec[0] = make_float4(x.x, x.y, x.z, __int_as_float(~static_cast<int32_t>(leaf)));
+    rec[1] = make_float4(y.x, y.y, y.z, __int_as_float(id));
+    if (kTri) rec[2] = make_float4(z.x, z.y, z.z, 0.0f);
 }
-template <bool kGlobal>
-__device__ __forceinline__ void lds_acquire() {
-    if (!kGlobal) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-template <bool kGlobal>
-__device__ __forceinline__ void slot_store(float4 *slot, const Sum &S) {
-    if (kGlobal) {
-        deposit_store(slot, S);
+
+// Gathers leaf li's primitive (its face's vertices, or the point) and its id.
+template <bool kTri>
+__device__ __forceinline__ void load_leaf(const RefitArgs &a, int64_t li, int32_t &id, f3 &x, f3 &y, f3 &z) {
+    id = a.prim[li];
+    if (kTri) {
+        x = vload(a.verts, a.nv, a.leaf_faces[li]);
+        y = vload(a.verts, a.nv, a.leaf_faces[a.n + li]);
+        z = vload(a.verts, a.nv, a.leaf_faces[2 * a.n + li]);
     } else {
-        float4 v[3];
-        pack(S, v);
-        slot[0] = v[0]; slot[1] = v[1]; slot[2] = v[2];
+        x = y = z = vload(a.verts, a.nv, id);
     }
 }
-template <bool kGlobal>
-__device__ __forceinline__ Sum slot_load(const float4 *slot) {
-    if (kGlobal) return deposit_load(slot);
-    return unpack(slot[0], slot[1], slot[2]);
+
+// Child reference of slot s of internal node i (>= 0 internal node, < 0 leaf ~i).
+__device__ __forceinline__ int32_t child_ref(const RefitArgs &a, int64_t i, int s) {
+    return a.child[s * (a.n - 1) + i];
 }
 
-//
-// Two sibling leaves often sit in adjacent lanes of one wave and arrive in the
-// same instruction.  The second may wait for the first's summary only because
-// the publication is a region of its own that precedes any waiting in program
-// order: a wave runs it for its first-arriving lanes before the waiting loop
-// of its second-arriving lanes (a waiting lane never blocks a lane of its own
-// wave that has yet to publish).  The wait is bounded all the same.
-template <bool kGlobal>
-__device__ __forceinline__ bool arrive(float4 *slot, float4 *dummy, uint32_t *word, const Sum &mine, Sum &other,
-                                       int32_t *status) {
-    uint32_t old = word_or<kGlobal>(word, 1u);
-    const bool first = !(old & 1u);
-    slot_store<kGlobal>(first ? slot : dummy, mine);
-    lds_release<kGlobal>();
-    word_or<kGlobal>(word, first ? 2u : 0u);  // the slot is written
-    if (first) return false;                  // the sibling finishes the node
-    for (int spin = 0; !(old & 2u); ++spin) { // a first child in another wave, between its two steps
-        if (spin > kSlotSpin) { atomicOr(status, 8); break; }
-        old = word_load<kGlobal>(word);
+// The subtree root's summary P: into its parent's record and the deposit, or
+// the root box when the subtree is the whole tree.
+template <bool kTri>
+__device__ __forceinline__ void finish_subtree(const RefitArgs &a, int64_t k, int32_t r, int32_t rtag, const Sum &P) {
+    if (rtag < 0) {
+        write_root(a.root, P);
+    } else if ((rtag >> 1) >= a.n - 1) {
+        atomicOr(a.status, 4);
+    } else {
+        write_internal<kTri>(a.nodes + 6 * static_cast<int64_t>(rtag >> 1) + 3 * (rtag & 1), r, P);
+        deposit_store(a.deposit + 3 * k, P);
     }
-    lds_acquire<kGlobal>();
-    other = slot_load<kGlobal>(slot);
-    return true;
 }
 
-// Phase 1 for subtree k by a workgroup of kThreads threads, each taking kLeaves
-// adjacent leaves and advancing their climbs together, one level per step, so
-// that no climb waits behind another of its thread.  kThreads is a compile-time
-// stride: blockDim would be reloaded from the dispatch packet, and that load's
-// wait would also wait for the record stores in flight.  smem:
-// refit_sub_lds(C) bytes.  The climb that finishes the subtree root deposits
-// its summary at deposit[k]; returns after the workgroup's barrier.
-template <bool kTri, int kThreads, int kLeaves>
+// Phase 1 for subtree k by a workgroup of kThreads threads, thread j owning
+// the nodes f + j + u kThreads (u < kPer).  kThreads is a compile-time stride:
+// blockDim would be reloaded from the dispatch packet, and that load's wait
+// would also wait for the record stores in flight.  smem: refit_sub_lds(C)
+// bytes.  The root's summary goes into its parent's record and deposit[k];
+// returns after the workgroup's barrier.
+template <bool kTri, int kThreads, int kPer>
 __device__ void refit_subtree(const RefitArgs &a, int64_t k, unsigned char *smem) {
     const int C = 1 << a.chunk_log2;
     const int32_t r = a.subtrees[k];
     const int64_t f = a.subtrees[a.n + k], l = a.subtrees[2 * a.n + k];
-    float4 *s_slot = reinterpret_cast<float4 *>(smem);                 // [C][3]
-    float4 *s_dummy = s_slot + 3 * C + 3 * (threadIdx.x / 64);         // [kDummyWaves][3]
-    uint32_t *s_word = reinterpret_cast<uint32_t *>(s_slot + 3 * (C + kDummyWaves));   // [C]
-    int32_t *s_par = reinterpret_cast<int32_t *>(s_word + C);          // [C] parent tags
+    float4 *s_slot = reinterpret_cast<float4 *>(smem);                          // [C][3]
+    uint8_t *s_done = reinterpret_cast<uint8_t *>(s_slot + 3 * C);             // [C]
     const int64_t size = l - f + 1;
-    if (f < 0 || l >= a.n || size < 1 || size > C || size > static_cast<int64_t>(kThreads) * kLeaves) {
+    if (f < 0 || l >= a.n || size < 1 || size > C || size > static_cast<int64_t>(kThreads) * kPer ||
+        (size > 1 && (r < f || r > l))) {
         if (threadIdx.x == 0) atomicOr(a.status, 4);
         __syncthreads();
         return;
     }
     if (k == 0 && threadIdx.x == 0 && a.hdr_nv && *a.hdr_nv != a.nv) atomicOr(a.status, 32);
-    // the leaves' ids, parent tags and vertices are loaded before the LDS set-up
-    // and its barrier, so the gathers overlap them
-    Sum S[kLeaves];
-    int32_t p[kLeaves], slot[kLeaves];
-    bool live[kLeaves];
-    f3 x[kLeaves], y[kLeaves], z[kLeaves];
-    int32_t id[kLeaves], tag[kLeaves];
-    const int64_t i0 = f + static_cast<int64_t>(threadIdx.x) * kLeaves;
-#pragma unroll
-    for (int u = 0; u < kLeaves; ++u) {
-        const int64_t i = i0 + u;
-        tag[u] = -2;
-        if (i > l) continue;
-        id[u] = a.prim[i];
-        tag[u] = a.leaf_parent[i];
-        if (kTri) {
-            x[u] = vload(a.verts, a.nv, a.leaf_faces[i]);
-            y[u] = vload(a.verts, a.nv, a.leaf_faces[a.n + i]);
-            z[u] = vload(a.verts, a.nv, a.leaf_faces[2 * a.n + i]);
-        } else {
-            x[u] = y[u] = z[u] = vload(a.verts, a.nv, id[u]);
+    if (size == 1) {                  // one leaf: the whole tree, or a child of a top node
+        if (threadIdx.x == 0) {
+            if (r != ~static_cast<int32_t>(f)) {
+                atomicOr(a.status, 4);
+            } else {
+                int32_t id;
+                f3 x, y, z;
+                load_leaf<kTri>(a, f, id, x, y, z);
+                const int32_t tag = a.leaf_parent[f];
+                const Sum S = leaf_sum<kTri>(x, y, z);
+                if (tag < 0) {
+                    write_root(a.root, S);
+                } else if ((tag >> 1) >= a.n - 1) {
+                    atomicOr(a.status, 4);
+                } else {
+                    write_leaf<kTri>(a.nodes + 6 * static_cast<int64_t>(tag >> 1) + 3 * (tag & 1), f, id, x, y, z);
+                    deposit_store(a.deposit + 3 * k, S);
+                }
+            }
         }
+        __syncthreads();
+        return;
     }
-    for (int j = threadIdx.x; j < size; j += kThreads) {
-        s_word[j] = 0u;
-        s_par[j] = f + j < a.n - 1 ? a.node_parent[f + j] : -1;
+    // set-up: the owned nodes' child references, then their leaf children's
+    // primitives, written into the nodes' records.  A node with two leaf
+    // children is finished here (mark 0); the summary of a lone leaf child waits
+    // in its parent's own slot, which nothing else reads before the parent is
+    // done.  The steps end when the root's mark is set.
+    const int jr = static_cast<int>(r - f);
+    int32_t nid[kPer], cref[kPer][2];
+    bool pend[kPer];
+    int32_t rtag = -1;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int64_t i = f + threadIdx.x + static_cast<int64_t>(u) * kThreads;
+        nid[u] = -1;
+        pend[u] = false;
+        if (i > l || i >= a.n - 1) continue;
+        if (a.node_aux[i] >= 0) continue;     // the one top node whose index lies in [f, l]
+        nid[u] = static_cast<int32_t>(i);
+        cref[u][0] = child_ref(a, i, 0);
+        cref[u][1] = child_ref(a, i, 1);
+        if (i == r) rtag = a.node_parent[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        if (nid[u] < 0) continue;
+        const int j = static_cast<int>(nid[u] - f);
+        const int32_t c0 = cref[u][0], c1 = cref[u][1];
+        bool ok = true;
+        if (c0 >= 0) ok = ok && c0 >= f && c0 <= l && c0 < a.n - 1 && c0 != nid[u];
+        else ok = ok && ~static_cast<int64_t>(c0) >= f && ~static_cast<int64_t>(c0) <= l;
+        if (c1 >= 0) ok = ok && c1 >= f && c1 <= l && c1 < a.n - 1 && c1 != nid[u];
+        else ok = ok && ~static_cast<int64_t>(c1) >= f && ~static_cast<int64_t>(c1) <= l;
+        if (!ok) {
+            atomicOr(a.status, 4);
+            nid[u] = -1;
+            s_done[j] = kNotDone;
+            continue;
+        }
+        Sum L[2];
+        bool leaf[2] = {c0 < 0, c1 < 0};
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            if (!leaf[s]) continue;
+            const int64_t li = ~static_cast<int64_t>(s == 0 ? c0 : c1);
+            int32_t id;
+            f3 x, y, z;
+            load_leaf<kTri>(a, li, id, x, y, z);
+            write_leaf<kTri>(a.nodes + 6 * static_cast<int64_t>(nid[u]) + 3 * s, li, id, x, y, z);
+            L[s] = leaf_sum<kTri>(x, y, z);
+        }
+        if (leaf[0] && leaf[1]) {
+            const Sum P = join<kTri>(L[0], L[1]);
+            if (nid[u] == r) finish_subtree<kTri>(a, k, r, rtag, P);   // a subtree of two leaves
+            else lds_slot_store(s_slot + 3 * j, P);
+            s_done[j] = 0;
+        } else {
+            if (leaf[0] || leaf[1]) lds_slot_store(s_slot + 3 * j, leaf[0] ? L[0] : L[1]);
+            s_done[j] = kNotDone;
+            pend[u] = true;
+        }
     }
     __syncthreads();
+    // the exit test reads the root's mark only once it can no longer change in
+    // the step being tested (a mark written in step s is s + 1): every thread
+    // leaves after the same barrier
+    for (int step = 0; step < kMaxSteps && s_done[jr] > step; ++step) {
 #pragma unroll
-    for (int u = 0; u < kLeaves; ++u) {
-        const int64_t i = i0 + u;
-        live[u] = false;
-        if (tag[u] == -2) continue;
-        S[u] = leaf_sum<kTri>(x[u], y[u], z[u]);
-        if (tag[u] < 0) {                     // a single leaf is the root
-            write_root(a.root, S[u]);
-            continue;
+        for (int u = 0; u < kPer; ++u) {
+            if (!pend[u]) continue;
+            const int32_t c0 = cref[u][0], c1 = cref[u][1];
+            const int j = static_cast<int>(nid[u] - f);
+            const bool in0 = c0 >= 0, in1 = c1 >= 0;
+            const int j0 = in0 ? static_cast<int>(c0 - f) : j, j1 = in1 ? static_cast<int>(c1 - f) : j;
+            const int d0 = in0 ? s_done[j0] : 0, d1 = in1 ? s_done[j1] : 0;
+            if (d0 > step || d1 > step) continue;
+            pend[u] = false;
+            // a leaf child's summary waits in the node's own slot (j)
+            const Sum A = lds_slot_load(s_slot + 3 * j0);
+            const Sum B = lds_slot_load(s_slot + 3 * j1);
+            float4 *rec = a.nodes + 6 * static_cast<int64_t>(nid[u]);
+            if (in0) write_internal<kTri>(rec, c0, A);
+            if (in1) write_internal<kTri>(rec + 3, c1, B);
+            const Sum P = join<kTri>(A, B);
+            if (nid[u] == r) finish_subtree<kTri>(a, k, r, rtag, P);
+            else lds_slot_store(s_slot + 3 * j, P);
+            s_done[j] = static_cast<uint8_t>(step + 1);
         }
-        p[u] = tag[u] >> 1;
-        slot[u] = tag[u] & 1;
-        if (p[u] >= a.n - 1) { atomicOr(a.status, 4); continue; }
-        float4 *rec = a.nodes + 6 * static_cast<int64_t>(p[u]) + 3 * slot[u];
-        rec[0] = make_float4(x[u].x, x[u].y, x[u].z, __int_as_float(~static_cast<int32_t>(i)));
-        rec[1] = make_float4(y[u].x, y[u].y, y[u].z, __int_as_float(id[u]));
-        if (kTri) rec[2] = make_float4(z[u].x, z[u].y, z[u].z, 0.0f);
-        if (r == ~static_cast<int32_t>(i)) {  // a one-leaf subtree
-            deposit_store(a.deposit + 3 * k, S[u]);
-            continue;
-        }
-        live[u] = true;
+        lds_step_barrier();
     }
-    // a valid tree is at most 62 levels deep
-    for (int level = 0; level < 64; ++level) {
-        bool any = false;
-#pragma unroll
-        for (int u = 0; u < kLeaves; ++u) {
-            if (!live[u]) continue;
-            live[u] = false;
-            const int64_t jl = p[u] - f;
-            if (jl < 0 || jl >= size) { atomicOr(a.status, 4); continue; }
-            const int j = static_cast<int>(jl);
-            const int32_t ptag = s_par[j];
-            Sum O;
-            if (!arrive<false>(s_slot + 3 * j, s_dummy, s_word + j, S[u], O, a.status)) continue;
-            S[u] = join_slots<kTri>(S[u], O, slot[u]);
-            if (ptag < 0) {                   // p is the root: the subtree is the whole tree
-                write_root(a.root, S[u]);
-                continue;
-            }
-            const int32_t c = p[u];
-            p[u] = ptag >> 1;
-            slot[u] = ptag & 1;
-            if (p[u] >= a.n - 1) { atomicOr(a.status, 4); continue; }
-            write_internal<kTri>(a.nodes + 6 * static_cast<int64_t>(p[u]) + 3 * slot[u], c, S[u]);
-            if (c == r) {
-                deposit_store(a.deposit + 3 * k, S[u]);
-                continue;
-            }
-            live[u] = true;
-            any = true;
-        }
-        if (!__builtin_amdgcn_readfirstlane(__ballot(any) != 0)) break;
-    }
+    if (threadIdx.x == 0 && s_done[jr] == kNotDone) atomicOr(a.status, 4);   // the root never became ready
     __syncthreads();
 }
 
-// Phase 2 over T top nodes and NS subtrees by one workgroup of kThreads:
-// the climbs from the deposited subtree roots t, t + kThreads, ... (at most
-// kRoots per thread, advanced together; more are taken kRoots at a time)
-// through the top nodes.  The slots and arrival words live in LDS (smem,
-// refit_top_lds(T) bytes), or with kGlobal in a.top_scratch.  Returns after
-// the root's box is written.
-template <bool kTri, int kThreads, bool kGlobal, int kRoots = 2>
-__device__ void refit_top(const RefitArgs &a, int T, int NS, unsigned char *smem) {
-    // slots [T][3] (global: [tstride][3]), dummies [kDummyWaves][3], words, then in
-    // LDS each top node's id and parent link
-    float4 *t_slot;
-    uint32_t *t_word;
-    int32_t *t_node = nullptr, *t_par = nullptr;
-    const int64_t ts = kGlobal ? a.tstride : T;
-    if (kGlobal) {
-        t_slot = a.top_scratch;
-    } else {
-        t_slot = reinterpret_cast<float4 *>(smem);
-    }
-    float4 *t_dummy = t_slot + 3 * ts + 3 * (threadIdx.x / 64);
-    t_word = reinterpret_cast<uint32_t *>(t_slot + 3 * (ts + kDummyWaves));
-    if (!kGlobal) {
-        t_node = reinterpret_cast<int32_t *>(t_word + T);
-        t_par = t_node + T;
-    }
-    for (int t = threadIdx.x; t < T; t += kThreads) {
-        if (kGlobal) {
-            __hip_atomic_store(t_word + t, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            t_word[t] = 0u;
-            t_node[t] = a.top_nodes[t];
-            t_par[t] = a.top_parent[t];
-        }
-    }
-    if (kGlobal) __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    for (int k0 = 0; k0 < NS; k0 += kRoots * kThreads) {
-        Sum S[kRoots];
-        int32_t tag[kRoots];
-        bool live[kRoots];
+// Phase 2 over T top nodes and NS subtrees by one workgroup of kThreads, thread
+// j owning top nodes j + u kThreads (u < kTPer; T <= kTPer kThreads), in LDS
+// (refit_top_lds(T) bytes of smem).  A top node's subtree children's summaries
+// are the deposits, read at set-up (as the subtree phase's leaves: a node with
+// two is finished there, a lone one waits in the node's own slot); the root
+// (node 0) writes the root box.
+template <bool kTri, int kThreads, int kTPer>
+__device__ void refit_top_lds_steps(const RefitArgs &a, int T, int NS, unsigned char *smem) {
+    float4 *t_slot = reinterpret_cast<float4 *>(smem);                          // [T][3]
+    uint8_t *t_done = reinterpret_cast<uint8_t *>(t_slot + 3 * T);             // [T]
+    int *t_fin = reinterpret_cast<int *>(t_done + ((T + 3) & ~3));           // the root's mark (its owner's)
+    int32_t pn[kTPer], ch[kTPer][2], cn[kTPer][2];
+    bool pend[kTPer];
+    // the tables are read for every slot up to the cap at once (one round trip,
+    // T arriving with them); slots from T on are ignored
 #pragma unroll
-        for (int u = 0; u < kRoots; ++u) {
-            const int k = k0 + u * kThreads + threadIdx.x;
-            live[u] = k < NS;
-            if (!live[u]) continue;
-            S[u] = deposit_load(a.deposit + 3 * k);
-            tag[u] = a.sub_parent[k];
-        }
-        // a valid top tree is at most 62 levels high
-        for (int level = 0; level < 64; ++level) {
-            bool any = false;
+    for (int u = 0; u < kTPer; ++u) {
+        const int t = threadIdx.x + u * kThreads;
+        pend[u] = false;
+        pn[u] = -1;
+        if (t >= a.n) continue;
+        pn[u] = a.top_nodes[t];
+        ch[u][0] = a.top_child[t];
+        ch[u][1] = a.top_child[a.n + t];
+        cn[u][0] = a.top_child[2 * a.n + t];
+        cn[u][1] = a.top_child[3 * a.n + t];
+    }
 #pragma unroll
-            for (int u = 0; u < kRoots; ++u) {
-                if (!live[u]) continue;
-                live[u] = false;
-                const int tp = tag[u] >> 1, slot = tag[u] & 1;
-                if (tag[u] < 0 || tp >= T) { atomicOr(a.status, 8); continue; }
-                const int32_t ptag = kGlobal ? a.top_parent[tp] : t_par[tp];
-                Sum O;
-                if (!arrive<kGlobal>(t_slot + 3 * tp, t_dummy, t_word + tp, S[u], O, a.status)) continue;
-                S[u] = join_slots<kTri>(S[u], O, slot);
-                if (ptag < 0) {               // tp is the root
-                    write_root(a.root, S[u]);
-                    continue;
-                }
-                const int pt = ptag >> 1;
-                if (pt >= T) { atomicOr(a.status, 8); continue; }
-                const int32_t pn = kGlobal ? a.top_nodes[pt] : t_node[pt];
-                const int32_t cn = kGlobal ? a.top_nodes[tp] : t_node[tp];
-                if (pn < 0 || pn >= a.n - 1) { atomicOr(a.status, 8); continue; }
-                write_internal<kTri>(a.nodes + 6 * static_cast<int64_t>(pn) + 3 * (ptag & 1), cn, S[u]);
-                tag[u] = ptag;
-                live[u] = true;
-                any = true;
+    for (int u = 0; u < kTPer; ++u)
+        if (threadIdx.x + u * kThreads < T && pn[u] == 0) *t_fin = kNotDone;
+    // every subtree child's deposited summary, all loads in flight together
+    // (deposit 0 stands in where a slot has no subtree child)
+    uint64_t dw[kTPer][2][6];
+#pragma unroll
+    for (int u = 0; u < kTPer; ++u)
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+            const int32_t c = ch[u][s2];
+            const bool sub = threadIdx.x + u * kThreads < T && c < 0 && ~c < NS;
+            deposit_load_words(a.deposit + 3 * (sub ? ~c : 0), dw[u][s2]);
+        }
+#pragma unroll
+    for (int u = 0; u < kTPer; ++u) {
+        const int t = threadIdx.x + u * kThreads;
+        if (t >= T) continue;
+        const int32_t c0 = ch[u][0], c1 = ch[u][1];
+        const bool ok = pn[u] >= 0 && pn[u] < a.n - 1 && (c0 >= 0 ? c0 < T && c0 != t : ~c0 < NS) &&
+                        (c1 >= 0 ? c1 < T && c1 != t : ~c1 < NS);
+        if (!ok) {
+            atomicOr(a.status, 8);
+            t_done[t] = kNotDone;
+            continue;
+        }
+        if (c0 < 0 && c1 < 0) {
+            const Sum P = join<kTri>(sum_of_words(dw[u][0]), sum_of_words(dw[u][1]));
+            if (pn[u] == 0) {             // the root over two subtrees
+                write_root(a.root, P);
+                *t_fin = 0;
+            } else {
+                lds_slot_store(t_slot + 3 * t, P);
             }
-            if (!__builtin_amdgcn_readfirstlane(__ballot(any) != 0)) break;
+            t_done[t] = 0;
+        } else {
+            if (c0 < 0 || c1 < 0) lds_slot_store(t_slot + 3 * t, sum_of_words(dw[u][c0 < 0 ? 0 : 1]));
+            t_done[t] = kNotDone;
+            pend[u] = true;
         }
     }
     __syncthreads();
+    for (int step = 0; step < kMaxSteps && *t_fin > step; ++step) {   // as in the subtree phase
+#pragma unroll
+        for (int u = 0; u < kTPer; ++u) {
+            if (!pend[u]) continue;
+            const int t = threadIdx.x + u * kThreads;
+            const int32_t c0 = ch[u][0], c1 = ch[u][1];
+            const bool in0 = c0 >= 0, in1 = c1 >= 0;
+            const int d0 = in0 ? t_done[c0] : 0, d1 = in1 ? t_done[c1] : 0;
+            if (d0 > step || d1 > step) continue;
+            pend[u] = false;
+            // a lone subtree child's summary waits in the node's own slot (t)
+            const Sum A = lds_slot_load(t_slot + 3 * (in0 ? c0 : t));
+            const Sum B = lds_slot_load(t_slot + 3 * (in1 ? c1 : t));
+            float4 *rec = a.nodes + 6 * static_cast<int64_t>(pn[u]);
+            if (in0) write_internal<kTri>(rec, cn[u][0], A);
+            if (in1) write_internal<kTri>(rec + 3, cn[u][1], B);
+            const Sum P = join<kTri>(A, B);
+            if (pn[u] == 0) {             // the root
+                write_root(a.root, P);
+                *t_fin = step + 1;
+            } else {
+                lds_slot_store(t_slot + 3 * t, P);
+                t_done[t] = static_cast<uint8_t>(step + 1);
+            }
+        }
+        lds_step_barrier();
+    }
+    if (threadIdx.x == 0 && *t_fin == kNotDone) atomicOr(a.status, 8);
+    __syncthreads();
+}
+
+// Phase 2 with the slots and done words in global scratch (a.top_scratch), for
+// top trees beyond the LDS: the same steps, each thread visiting the nodes
+// j, j + kThreads, ... and reading their links again in every step (slow, but
+// only very large trees take it).  Slots and marks use device-scope accesses.
+template <bool kTri, int kThreads>
+__device__ void refit_top_global_steps(const RefitArgs &a, int T, int NS, unsigned char *smem) {
+    float4 *g_slot = a.top_scratch;                                             // [tstride][3]
+    uint32_t *g_done = reinterpret_cast<uint32_t *>(g_slot + 3 * a.tstride);   // [tstride]
+    int *t_fin = reinterpret_cast<int *>(smem);                 // the root's mark
+    for (int t = threadIdx.x; t < T; t += kThreads)
+        __hip_atomic_store(g_done + t, ~0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) *t_fin = kNotDone;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    auto mark = [&](int32_t c) -> uint32_t {
+        return c >= 0 ? __hip_atomic_load(g_done + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+    };
+    for (int step = 0; step < kMaxSteps && *t_fin > step; ++step) {   // as in the subtree phase
+        for (int t = threadIdx.x; t < T; t += kThreads) {
+            if (__hip_atomic_load(g_done + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ~0u) continue;
+            const int32_t c0 = a.top_child[t], c1 = a.top_child[a.n + t], p = a.top_nodes[t];
+            if (c0 >= T || c1 >= T || (c0 < 0 && ~c0 >= NS) || (c1 < 0 && ~c1 >= NS) || p < 0 || p >= a.n - 1) {
+                atomicOr(a.status, 8);
+                continue;
+            }
+            const uint32_t d0 = mark(c0), d1 = mark(c1);
+            if (d0 > static_cast<uint32_t>(step) || d1 > static_cast<uint32_t>(step)) continue;
+            const Sum A = deposit_load(c0 >= 0 ? g_slot + 3 * c0 : a.deposit + 3 * ~c0);
+            const Sum B = deposit_load(c1 >= 0 ? g_slot + 3 * c1 : a.deposit + 3 * ~c1);
+            float4 *rec = a.nodes + 6 * static_cast<int64_t>(p);
+            if (c0 >= 0) write_internal<kTri>(rec, a.top_nodes[c0], A);
+            if (c1 >= 0) write_internal<kTri>(rec + 3, a.top_nodes[c1], B);
+            const Sum P = join<kTri>(A, B);
+            if (p == 0) {
+                write_root(a.root, P);
+                *t_fin = step + 1;
+            } else {
+                deposit_store(g_slot + 3 * t, P);   // waits for its stores
+                __hip_atomic_store(g_done + t, static_cast<uint32_t>(step + 1), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && *t_fin == kNotDone) atomicOr(a.status, 8);
+    __syncthreads();
+}
+
+// Phase 2: in LDS when T fits kTPer nodes per thread (kGlobal false), else in
+// global scratch.
+template <bool kTri, int kThreads, bool kGlobal, int kTPer>
+__device__ void refit_top(const RefitArgs &a, int T, int NS, unsigned char *smem) {
+    if (kGlobal) {
+        refit_top_global_steps<kTri, kThreads>(a, T, NS, smem);
+    } else if (T > kTPer * kThreads) {
+        if (threadIdx.x == 0) atomicOr(a.status, 8);
+        __syncthreads();
+    } else {
+        refit_top_lds_steps<kTri, kThreads, kTPer>(a, T, NS, smem);
+    }
 }
 
 }  // namespace mgu

@@ -28,8 +28,9 @@ EXPECT = {
         r"traverse_batch_kernelILb0ELi(16|32)ELi4EE": (6, 0),
     },
     "lbvh.hip": {
-        # two 512-thread workgroups per CU (16 waves): at least 4 waves per SIMD
-        r"refit_kernelILb1ELi512ELi[124]EE": (4, 0),
+        # three workgroups per CU: 6 waves per SIMD at 512 threads, 3 at 256
+        r"refit_kernelILb1ELi512ELi[12]ELi6EE": (6, 0),
+        r"refit_kernelILb1ELi256ELi1ELi3EE": (3, 0),
         r"radix_pass_kernelILi2EE": (8, 0),
         r"hierarchy_kernel": (8, 0),
         r"morton_kernel": (8, 0),

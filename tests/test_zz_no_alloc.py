@@ -33,12 +33,12 @@ def _sec(b, L, name, count, dtype=np.int32):
 def _canonical(b, L, n):
     """The order-free content of the top-node and subtree lists.  Both are filled
     through atomic counters, so their order (and the indices that point into them)
-    may differ between any two builds; what is unique is each top node's parent
-    and slot and each subtree's extent, parent, slot and deposited summary."""
+    may differ between any two builds; what is unique is each top node's two
+    children (a top node, or a subtree with its extent and deposited summary)."""
     hdr = LbvhHeader.from_buffer_copy(b[:ctypes.sizeof(LbvhHeader)].tobytes())
     n_top, n_sub = hdr.n_top, hdr.n_sub
     top = _sec(b, L, "top_nodes", n)[:n_top]
-    link = _sec(b, L, "top_link", 2 * n)
+    tch = _sec(b, L, "top_child", 2 * n).reshape(2, n)
     sub = _sec(b, L, "subtrees", 3 * n).reshape(3, n)[:, :n_sub]
     dep = _sec(b, L, "deposits", 12 * n, np.float32).reshape(n, 12)[:n_sub].view(np.uint32)
     aux = _sec(b, L, "node_aux", max(n - 1, 0))
@@ -46,12 +46,14 @@ def _canonical(b, L, n):
     on_top = np.flatnonzero(aux >= 0)
     assert (top[aux[on_top]] == on_top).all()
 
-    def parent_of(l):
-        return (-1, -1) if l < 0 else (int(top[l >> 1]), int(l & 1))
+    def child(c):
+        if c >= 0:
+            return ("top", int(top[c]))
+        k = ~c
+        return ("sub", int(sub[0, k]), int(sub[1, k]), int(sub[2, k]), dep[k].tobytes())
 
-    tops = {int(t): parent_of(int(link[i])) for i, t in enumerate(top)}
-    subs = {(int(sub[0, k]), int(sub[1, k]), int(sub[2, k])): (parent_of(int(link[n + k])), dep[k].tobytes())
-            for k in range(n_sub)}
+    tops = {int(t): (child(int(tch[0, i])), child(int(tch[1, i]))) for i, t in enumerate(top)}
+    subs = sorted((int(sub[0, k]), int(sub[1, k]), int(sub[2, k])) for k in range(n_sub))
     return np.sort(on_top), tops, subs
 
 
@@ -61,7 +63,7 @@ def _compare(mg, ref, got):
     wrote); those lists compare in order-free form."""
     L, n = ref.layout, ref.n
     a, b = host(ref.buf), host(got.buf)
-    for lo, hi in ((0, L.off_node_aux), (L.off_inv_prim, L.total_bytes)):
+    for lo, hi in ((0, L.off_node_aux), (L.off_child, L.off_top_nodes), (L.off_inv_prim, L.total_bytes)):
         diff = np.flatnonzero(a[lo:hi] != b[lo:hi])
         assert diff.size == 0, f"{diff.size} bytes differ in [{lo}, {hi}), first at {lo + diff[0]}"
     ca, cb = _canonical(a, L, n), _canonical(b, L, n)
