@@ -274,6 +274,24 @@ mg_status mg_lbvh_build_static(const float *verts, int32_t n_verts, const int32_
 mg_status mg_lbvh_refit(const float *verts, int32_t n_verts, void *bvh, size_t bvh_bytes,
                         int32_t n_prims, int32_t prim_kind, void *stream);
 
+/* The per-frame update of a fixed-topology mesh in one launch (Sec. 3.4: the
+ * vertex buffer written from the current reconstruction frame, the render
+ * Gaussians re-posed from their faces, the collision BVH refit, O(N_v)):
+ * copies frame k of frames [n_frames][3][n_verts] into live [3][n_verts],
+ * re-poses the n_gauss Gaussians bound to faces [3][n_faces] (arguments and
+ * outputs as for mg_mesh_gaussian_update, flags 0; n_gauss may be 0) and refits
+ * bvh, a MG_PRIM_TRIANGLES BVH built over those faces and n_verts vertices.
+ * All three read the vertices from frame k itself, so they run side by side in
+ * one kernel; the results are bitwise those of mg_vertex_buffer_update,
+ * mg_mesh_gaussian_update and mg_lbvh_refit called in turn.  live must not
+ * overlap frame k.  The refit's rules hold (no concurrent refit of one BVH;
+ * a vertex count other than the build's sets status bit 32). */
+mg_status mg_frame_update(const float *frames, int32_t n_frames, int32_t n_verts, int32_t k, float *live,
+                          const int32_t *faces, int32_t n_faces, const int32_t *gface, const float *bary,
+                          const float *q_local, const float *log_scale, const float *offset,
+                          int32_t n_gauss, float *mean, float *quat, float *cov, float *rot, void *bvh,
+                          size_t bvh_bytes, void *stream);
+
 /* Traversal choice for the query calls (NULL options = MG_QUERY_AUTO).
  *   MG_QUERY_LANE   one query per lane, depth-first, nearer child first
  *   MG_QUERY_BATCH  one wave per `batch` queries (1, 2, 4, 8, 16 or 32) sharing

@@ -79,6 +79,7 @@ PROTOTYPES = {
     "mg_lbvh_workspace_size": (I32, [I32, I32, P]),
     "mg_lbvh_build": (I32, [P, I32, P, I32, I32, P, SZ, P, SZ, P]),
     "mg_lbvh_build_static": (I32, [P, I32, P, I32, I32, P, SZ, P]),
+    "mg_frame_update": (I32, [P, I32, I32, I32, P, P, I32, P, P, P, P, P, I32, P, P, P, P, P, SZ, P]),
     "mg_lbvh_refit": (I32, [P, I32, P, SZ, I32, I32, P]),
     "mg_closest_point_query": (I32, [P, SZ, I32, P, I32, P, I32, F32, P, P, P, P, P, P, P]),
     "mg_closest_point_bruteforce": (I32, [P, I32, P, I32, P, I32, F32, P, P, P, P, P, P]),

@@ -16,7 +16,7 @@ from ._lib import MG_PRIM_POINTS, MG_PRIM_TRIANGLES, MG_QUERY_AUTO, MG_QUERY_BAT
 
 __all__ = [
     "frame_index", "vertex_buffer_update", "fill", "blend", "mesh_gaussian_update", "mesh_gaussian_update_backward",
-    "LBVH", "query_order", "lbvh_bytes", "lbvh_workspace_bytes", "lbvh_build", "lbvh_build_static", "lbvh_refit", "closest_point_query", "closest_point_bruteforce",
+    "LBVH", "query_order", "lbvh_bytes", "lbvh_workspace_bytes", "lbvh_build", "lbvh_build_static", "frame_update", "lbvh_refit", "closest_point_query", "closest_point_bruteforce",
     "nearest_point_query", "knn_surface_query", "mean", "chamfer", "point_mesh_backward", "chamfer_backward", "adam_step",
     "validate_indices", "validate_finite", "version", "check_device",
 ]
@@ -230,6 +230,37 @@ def lbvh_refit(bvh, verts):
     _call("mg_lbvh_refit", _ptr(_same_verts(bvh, verts, "lbvh_refit")), verts.shape[1], _ptr(bvh.buf), bvh.nbytes, bvh.n,
           bvh.kind, _stream())
     return bvh
+
+
+def frame_update(frames, k, live, faces, gface, bary, q_local, log_scale, bvh, offset=None, *, out=None,
+                 quat=True, cov=True, rot=False):
+    """One launch of the per-frame update: live[3][V] <- frames[k], the Gaussians re-posed
+    from frame k (returns the output dict as mesh_gaussian_update), bvh refit on frame k."""
+    _f32(frames, name="frames")
+    T, three, V = frames.shape
+    if three != 3 or tuple(live.shape) != (3, V):
+        raise ValueError("frames must be [T][3][V] and live [3][V]")
+    _f32(live, 3, "live"); _i32(faces, "faces"); _i32(gface, "gface")
+    _f32(bary, 2, "bary"); _f32(q_local, 4, "q_local"); _f32(log_scale, 3, "log_scale"); _f32(offset, None, "offset")
+    if bvh.kind != MG_PRIM_TRIANGLES or bvh.n != faces.shape[1]:
+        raise ValueError("frame_update: bvh must be a triangle BVH over faces")
+    if bvh.n_verts is not None and bvh.n_verts != V:
+        raise ValueError(f"frame_update: frames have {V} vertices, the BVH was built on {bvh.n_verts}")
+    G = gface.shape[0]
+    dev = live.device
+    out = dict(out or {})
+    if "mean" not in out:
+        out["mean"] = torch.empty(3, G, device=dev)
+    if quat and "quat" not in out:
+        out["quat"] = torch.empty(4, G, device=dev)
+    if cov and "cov" not in out:
+        out["cov"] = torch.empty(6, G, device=dev)
+    if rot and "rot" not in out:
+        out["rot"] = torch.empty(9, G, device=dev)
+    _call("mg_frame_update", _ptr(frames), T, V, int(k), _ptr(live), _ptr(faces), faces.shape[1], _ptr(gface),
+          _ptr(bary), _ptr(q_local), _ptr(log_scale), _ptr(offset), G, _ptr(out["mean"]), _ptr(out.get("quat")),
+          _ptr(out.get("cov")), _ptr(out.get("rot")), _ptr(bvh.buf), bvh.nbytes, _stream())
+    return out
 
 
 def _opts(kernel, batch, seed=False, order=None, counters=None, queue=None, hint=None, warm=False, waves=0):

@@ -28,6 +28,7 @@
 #include <mutex>
 
 #include "refit.hpp"
+#include "repose.hpp"
 
 namespace mgu {
 namespace {
@@ -568,18 +569,17 @@ __global__ __launch_bounds__(256) void top_child_kernel(const int32_t *__restric
     }
 }
 
-// The refit: workgroups of kThreads take subtrees (kPer nodes per thread);
-// each counts the subtrees it finished into the header's arrival word once
-// their deposits are complete, and the one that brings it to the number of
-// subtrees refits the top nodes (then clears the word for the next refit).
-// smem: refit_lds_bytes(chunk_log2) bytes.
-template <bool kTri, int kThreads, int kPer, int kMinWaves>
-__global__ __launch_bounds__(kThreads, kMinWaves) void refit_kernel(RefitArgs a) {
-    extern __shared__ __align__(16) unsigned char smem[];
+// The refit over workgroups block, block + nblocks, ...: each takes subtrees
+// (kPer nodes per thread) and counts the subtrees it finished into the
+// header's arrival word once their deposits are complete; the one that brings
+// it to the number of subtrees refits the top nodes (then clears the word for
+// the next refit).  smem: refit_lds_bytes(chunk_log2) bytes.
+template <bool kTri, int kThreads, int kPer>
+__device__ void refit_blocks(const RefitArgs &a, int64_t block, int64_t nblocks, unsigned char *smem) {
     __shared__ int s_last;
     const int32_t ns = *a.n_sub;
     int mine = 0;
-    for (int64_t k = blockIdx.x; k < ns; k += gridDim.x) {
+    for (int64_t k = block; k < ns; k += nblocks) {
         refit_subtree<kTri, kThreads, kPer>(a, k, smem);     // ends with a barrier
         ++mine;
     }
@@ -599,6 +599,48 @@ __global__ __launch_bounds__(kThreads, kMinWaves) void refit_kernel(RefitArgs a)
         refit_top<kTri, kThreads, true, 1>(a, T, ns, smem);
     }
     if (threadIdx.x == 0) __hip_atomic_store(a.arrivals, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <bool kTri, int kThreads, int kPer, int kMinWaves>
+__global__ __launch_bounds__(kThreads, kMinWaves) void refit_kernel(RefitArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    refit_blocks<kTri, kThreads, kPer>(a, blockIdx.x, gridDim.x, smem);
+}
+
+// The frame update in one launch: workgroups [0, sub_blocks) refit (as
+// refit_kernel), the next copy_blocks copy the frame into the live buffer,
+// and the rest re-pose the Gaussians, gauss_tile each.  Every part reads the
+// frame's vertices from the frame store, so none waits for another; the copy
+// and re-pose workgroups, dispatched after the refit's, fill the compute units
+// the refit leaves idle (its later subtrees and its one-workgroup top phase).
+struct FrameWork {
+    const float *src;          // frame k, [3][n_verts]
+    float *live;               // [3][n_verts]
+    int64_t n3;                // 3 n_verts
+    int64_t copy_tile;         // floats per copy workgroup
+    Inputs in;                 // re-pose inputs (verts = src)
+    float *mean, *quat, *cov, *rot;
+    int64_t gauss_tile;        // Gaussians per re-pose workgroup
+    int64_t sub_blocks, copy_blocks;
+};
+
+template <int kThreads, int kPer, int kMinWaves>
+__global__ __launch_bounds__(kThreads, kMinWaves) void frame_update_kernel(RefitArgs a, FrameWork w) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t b = blockIdx.x;
+    if (b < w.sub_blocks) {
+        refit_blocks<true, kThreads, kPer>(a, b, w.sub_blocks, smem);
+        return;
+    }
+    if (b < w.sub_blocks + w.copy_blocks) {
+        const int64_t i0 = (b - w.sub_blocks) * w.copy_tile;
+        const int64_t i1 = i0 + w.copy_tile < w.n3 ? i0 + w.copy_tile : w.n3;
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += kThreads) w.live[i] = w.src[i];
+        return;
+    }
+    const int64_t g0 = (b - w.sub_blocks - w.copy_blocks) * w.gauss_tile;
+    const int64_t g1 = g0 + w.gauss_tile < w.in.ng ? g0 + w.gauss_tile : w.in.ng;
+    for (int64_t g = g0 + threadIdx.x; g < g1; g += kThreads) repose_store(w.in, g, w.mean, w.quat, w.cov, w.rot);
 }
 
 template <bool kTri, int kThreads, int kPer, int kMinWaves>
@@ -655,6 +697,17 @@ RefitArgs refit_args(const float *verts, int64_t nv, void *bvh, int64_t n, int k
     a.n = n;
     a.chunk_log2 = chunk_log2_for(n);
     return a;
+}
+
+template <int kThreads, int kPer, int kMinWaves>
+mg_status launch_frame_t(const RefitArgs &a, const FrameWork &w, int64_t grid, hipStream_t s) {
+    const size_t lds = refit_lds_bytes(a.chunk_log2);
+    if (lds > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&frame_update_kernel<kThreads, kPer, kMinWaves>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    hipLaunchKernelGGL((frame_update_kernel<kThreads, kPer, kMinWaves>), dim3(static_cast<unsigned>(grid)),
+                       dim3(kThreads), lds, s, a, w);
+    return launch_status();
 }
 
 mg_status launch_refit(const float *verts, int64_t nv, void *bvh, int64_t n, int kind, hipStream_t s) {
@@ -808,6 +861,43 @@ extern "C" mg_status mg_lbvh_build_static(const float *verts, int32_t n_verts, c
     if (st != MG_OK) return st;
     return build_into(verts, n_verts, faces, n_prims, prim_kind, bvh, bvh_bytes, ws,
                       static_cast<size_t>(kStaticWsBytes), stream);
+}
+
+extern "C" mg_status mg_frame_update(const float *frames, int32_t n_frames, int32_t n_verts, int32_t k,
+                                     float *live, const int32_t *faces, int32_t n_faces, const int32_t *gface,
+                                     const float *bary, const float *q_local, const float *log_scale,
+                                     const float *offset, int32_t n_gauss, float *mean, float *quat, float *cov,
+                                     float *rot, void *bvh, size_t bvh_bytes, void *stream) {
+    if (bad_count(n_verts) || bad_count(n_faces) || bad_count(n_gauss) || n_frames <= 0 || k < 0 ||
+        k >= n_frames || n_verts == 0 || n_faces == 0 || !frames || !live || !faces || !bvh)
+        return MG_ERR_INVALID_ARGUMENT;
+    if (n_gauss > 0 && (!gface || !bary || !q_local || !log_scale || !mean)) return MG_ERR_INVALID_ARGUMENT;
+    const mg_lbvh_layout L = make_layout(n_faces, MG_PRIM_TRIANGLES);
+    if (bvh_bytes < static_cast<size_t>(L.total_bytes)) return MG_ERR_WORKSPACE_TOO_SMALL;
+    const int64_t n3 = 3 * static_cast<int64_t>(n_verts);
+    const float *src = frames + static_cast<int64_t>(k) * n3;
+    if (src < live + n3 && live < src + n3) return MG_ERR_INVALID_ARGUMENT;   // overlap
+    const RefitArgs a = refit_args(src, n_verts, bvh, n_faces, MG_PRIM_TRIANGLES);
+    const int64_t C = int64_t(1) << a.chunk_log2;
+    FrameWork w;
+    w.src = src;
+    w.live = live;
+    w.n3 = n3;
+    w.in = Inputs{src, n_verts, faces, n_faces, gface, bary, q_local, log_scale, offset, n_gauss};
+    w.mean = mean; w.quat = quat; w.cov = cov; w.rot = rot;
+    w.sub_blocks = 2 * ((n_faces + C - 1) / C);
+    const int threads = a.chunk_log2 <= 8 ? 256 : 512;
+    w.copy_tile = 16 * static_cast<int64_t>(threads);
+    w.copy_blocks = (n3 + w.copy_tile - 1) / w.copy_tile;
+    w.gauss_tile = 2 * static_cast<int64_t>(threads);
+    const int64_t gauss_blocks = (static_cast<int64_t>(n_gauss) + w.gauss_tile - 1) / w.gauss_tile;
+    const int64_t grid = w.sub_blocks + w.copy_blocks + gauss_blocks;
+    if (grid > 0x7fffffff) return MG_ERR_INVALID_ARGUMENT;
+    hipStream_t s = as_stream(stream);
+    if (a.chunk_log2 <= 8) return launch_frame_t<256, 1, 3>(a, w, grid, s);
+    if (a.chunk_log2 == 9) return launch_frame_t<512, 1, 6>(a, w, grid, s);
+    if (a.chunk_log2 == 10) return launch_frame_t<512, 2, 6>(a, w, grid, s);
+    return launch_frame_t<512, 4, 2>(a, w, grid, s);
 }
 
 extern "C" mg_status mg_lbvh_refit(const float *verts, int32_t n_verts, void *bvh, size_t bvh_bytes,
