@@ -111,6 +111,7 @@ _CSRC = "paper_2606_00444_amd/csrc/"
 KERNEL_SOURCES = {
     "gaussian_update": [_CSRC + f for f in ("gaussian.hip", "repose.hpp", "mgu_internal.hpp")],
     "refit": [_CSRC + f for f in ("lbvh.hip", "refit.hpp", "mgu_internal.hpp")],
+    "frame_update": [_CSRC + f for f in ("lbvh.hip", "refit.hpp", "repose.hpp", "mgu_internal.hpp")],
     "collide": [_CSRC + f for f in ("query.hip", "traverse.hpp", "mgu_internal.hpp")],
     "batch": [_CSRC + f for f in ("batch.hip", "traverse.hpp", "refit.hpp", "repose.hpp", "mgu_internal.hpp")],
 }
@@ -717,7 +718,7 @@ def run_refine(args):
         torch.cuda.synchronize()
         run = g.replay
     ms_per_step, wall = timed_region(run, K, torch)
-    hist = r.losses().numpy().sum(1)
+    hist = r.losses().numpy()[:, 3]
 
     # per-kernel average durations at V1, the queries starting from V0's answers as
     # in the step (each phase alone in a graph of R launches; the hints are copies,
@@ -872,10 +873,11 @@ def run_c1(args):
         mg.closest_point_query(bvh, live, particles, normal=True, out=col, hint=col["face"] if hint is None else hint,
                                **o_col)
 
+    def frame_update(k):
+        mg.frame_update(frames, k, live, F, b["face"], b["bary"], b["q_local"], b["log_scale"], bvh, out=gout)
+
     def step(i):
-        mg.vertex_buffer_update(frames, i % T, live)
-        phase_update()
-        mg.lbvh_refit(bvh, live)
+        frame_update(i % T)
         phase_collide()
 
     for i in range(args.warmup):
@@ -897,8 +899,7 @@ def run_c1(args):
     ph = {"vertex_copy": graph_ms(lambda r: mg.vertex_buffer_update(frames, r % T, live), reps, torch),
           "gaussian_update": graph_ms(lambda r: phase_update(), reps, torch),
           "refit": graph_ms(lambda r: mg.lbvh_refit(bvh, live), reps, torch)}
-    ph["frame_update"] = graph_ms(lambda r: (mg.vertex_buffer_update(frames, r % T, live), phase_update(),
-                                             mg.lbvh_refit(bvh, live)), reps, torch)
+    ph["frame_update"] = graph_ms(lambda r: frame_update(r % T), reps, torch)
     hint = col["face"].clone()
     ph["collide"] = graph_ms(lambda r: phase_collide(hint=hint), reps, torch)
     cnt = torch.zeros(4, dtype=torch.int64, device=dev)
@@ -910,7 +911,9 @@ def run_c1(args):
         "vertex_copy": 24.0 * NV,
         "gaussian_update": 92.0 * G + 12.0 * NF + 12.0 * NV,
         "refit": 12.0 * NV + 12.0 * NF + 48.0 * NF,
-        "frame_update": 24.0 * NV + (92.0 * G + 12.0 * NF + 12.0 * NV) + (12.0 * NV + 12.0 * NF + 48.0 * NF),
+        # the minimum per frame of the refit path: vertices once, face indices once and
+        # the 64 B of records per face, the Gaussians' 40 B in and 52 B out
+        "frame_update": 12.0 * NV + 76.0 * NF + 92.0 * G,
         "collide": 52.0 * Q,
     }
     kernels = {}
@@ -918,7 +921,7 @@ def run_c1(args):
         gbs = alg_bytes[k] / (ms * 1e-3) / 1e9
         kernels[k] = {"ms": round(ms, 5), "alg_bytes": int(alg_bytes[k]), "GB_s": round(gbs, 1),
                       "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
-    single = {k: ph[k] for k in ("gaussian_update", "refit", "collide")}
+    single = {k: ph[k] for k in ("gaussian_update", "refit", "frame_update", "collide")}
     dom = max(single, key=single.get)
 
     # the same 60 frames as one persistent launch (re-pose, refit, queries per frame)
@@ -938,7 +941,7 @@ def run_c1(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"c1: {WORKLOADS['c1'][1]}", "frames": T, "vertices": NV, "faces": NF,
                    "gaussians": G, "queries": Q, "timing": "eager" if args.eager else "hip-graph"},
-        "frame_update": dict(kernels["frame_update"], what="vertex copy, Gaussian re-pose, refit"),
+        "frame_update": dict(kernels["frame_update"], what="vertex copy, Gaussian re-pose, refit in one launch"),
         "queries_per_s": round(Q * 1000.0 / ms_per_step, 1),
         "traversal": {"node_expansions_per_query": round(n_exp / Q, 1),
                       "leaf_bound_tests_per_query": round(n_lbox / Q, 1),
@@ -1145,12 +1148,9 @@ def main():
     side = torch.cuda.Stream() if args.streams >= 2 else None
     side2 = torch.cuda.Stream() if args.streams == 3 else None
     def frame_update(k):
-        """The frame update: copy frame k, re-pose the Gaussians, refit.  (Running the
-        re-pose beside the refit on another stream was measured slower: the fork and
-        join inside the graph cost more than the overlap of kernels this short.)"""
-        phase_copy(k)
-        phase_update()
-        phase_refit()
+        """The frame update in one launch: copy frame k, re-pose the Gaussians, refit
+        (mg_frame_update; bitwise the three separate calls, timed alone below)."""
+        mg.frame_update(frames, k, live, F, b["face"], b["bary"], b["q_local"], b["log_scale"], bvh, out=gout)
 
     def step(i):
         # simulation runs at the reconstruction rate: step i at f_sim = f_recon -> frame i (mod T)
@@ -1313,7 +1313,9 @@ def main():
         "vertex_copy": 24.0 * NV,
         "gaussian_update": 92.0 * G + 12.0 * NF + 12.0 * NV,
         "refit": 12.0 * NV + 12.0 * NF + 48.0 * NF,
-        "frame_update": 24.0 * NV + (92.0 * G + 12.0 * NF + 12.0 * NV) + (12.0 * NV + 12.0 * NF + 48.0 * NF),
+        # the minimum per frame of the refit path: vertices once, face indices once and
+        # the 64 B of records per face, the Gaussians' 40 B in and 52 B out
+        "frame_update": 12.0 * NV + 76.0 * NF + 92.0 * G,
         "collide": 52.0 * Q,
         "rebuild": 200.0 * tf_mean + 12.0 * tv_mean,
     }
@@ -1340,7 +1342,7 @@ def main():
     trav = {"node_expansions_per_query": round(n_exp / n_q, 1), "leaf_bound_tests_per_query": round(n_lbox / n_q, 1),
             "exact_leaf_tests_per_query": round(n_lex / n_q, 1)}
     coll_ops = OPS_EXPANSION * n_exp + OPS_LEAF_BOUND * n_lbox + OPS_EXACT * n_lex
-    single = {k: ph[k] for k in ("gaussian_update", "refit", "collide")}   # the kernels of one phase
+    single = {k: ph[k] for k in ("gaussian_update", "refit", "frame_update", "collide")}   # one kernel each
     dom = max(single, key=single.get)
     roofline = kernel_roofline(args.workload, dom, ph[dom], alg_bytes, coll_ops, Q)
     q_per_frame = 2 * Q + NV
@@ -1356,7 +1358,7 @@ def main():
                    "streams": args.streams},
         "refit_path": {"ms_per_frame": round(refit_path_ms, 5), "frames_per_s": round(1000.0 / refit_path_ms, 1),
                        "what": "frame update + collision queries from the previous frame's faces"},
-        "frame_update": dict(kernels["frame_update"], what="vertex copy, Gaussian re-pose, refit"),
+        "frame_update": dict(kernels["frame_update"], what="vertex copy, Gaussian re-pose, refit in one launch"),
         "rebuild_path": {"ms_per_frame": round(rebuild_path_ms, 5), "frames_per_s": round(1000.0 / rebuild_path_ms, 1),
                          "what": "varying-topology target: rebuild, collision queries and template projection "
                                  "onto it (no hints exist across topologies)"},

@@ -464,17 +464,22 @@ mg_status mg_reduce_workspace_size(int64_t n, size_t *ws_bytes);
  * fixed-order per-block float64 partial sums, then one block sums them. */
 mg_status mg_mean(const float *x, int64_t n, double *out, void *ws, size_t ws_bytes, void *stream);
 
-/* Both nearest-neighbour directions and the two means:
+/* The two-sided Chamfer distance (Sec. 4.2's geometric metric, read as the
+ * sum of the two mean squared nearest distances):
  * nn_ab[i] / d_ab[i]: nearest b of a_i and its squared distance (via bvh_b,
  * a MG_PRIM_POINTS BVH over b); nn_ba / d_ba likewise via bvh_a over a;
- * out[0] = mean d_ab, out[1] = mean d_ba (device float64).  opts as for
- * mg_nearest_point_query (applies to both directions) except hint, which is
- * ignored: with opts->warm set, the entries of nn_ab and nn_ba on entry are
- * the hints of their directions (ids out of range count as none). */
+ * out (device float64 [3]): out[0] = mean d_ab, out[1] = mean d_ba,
+ * out[2] = (out[0] + out[1]) + add[0], where add (device float64, or NULL for
+ * 0) is another loss term to fold in, e.g. the point-to-mesh term of the
+ * template projection.  opts as for mg_nearest_point_query (applies to both
+ * directions) except hint, which is ignored: with opts->warm set, the entries
+ * of nn_ab and nn_ba on entry are the hints of their directions (ids out of
+ * range count as none). */
 mg_status mg_chamfer(const float *a, int32_t na, const void *bvh_a, size_t bvh_a_bytes,
                      const float *b, int32_t nb, const void *bvh_b, size_t bvh_b_bytes,
                      int32_t *nn_ab, float *d_ab, int32_t *nn_ba, float *d_ba, double *out,
-                     void *ws, size_t ws_bytes, const mg_query_options *opts, void *stream);
+                     const double *add, void *ws, size_t ws_bytes, const mg_query_options *opts,
+                     void *stream);
 
 /* g_verts [3][n_verts] += scale * g * sum_q -2 w_k (y_q - c_q) on the three
  * vertices of each query's face (queries with face == -1 contribute nothing).

@@ -92,7 +92,7 @@ PROTOTYPES = {
     "mg_knn_surface_query": (I32, [P, SZ, I32, P, I32, P, I32, I32, F32, F32, P, P, P, P, P]),
     "mg_reduce_workspace_size": (I32, [I64, P]),
     "mg_mean": (I32, [P, I64, P, P, SZ, P]),
-    "mg_chamfer": (I32, [P, I32, P, SZ, P, I32, P, SZ, P, P, P, P, P, P, SZ, P, P]),
+    "mg_chamfer": (I32, [P, I32, P, SZ, P, I32, P, SZ, P, P, P, P, P, P, P, SZ, P, P]),
     "mg_point_mesh_backward": (I32, [P, I32, P, I32, P, I32, P, P, P, F32, P, P, P]),
     "mg_chamfer_backward": (I32, [P, I32, P, I32, P, P, F32, F32, P, P, P]),
     "mg_adam_step": (I32, [P, P, P, P, I64, I32, F32, F32, F32, F32, P]),

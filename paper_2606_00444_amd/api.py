@@ -420,23 +420,29 @@ def mean(x, out=None):
     return out
 
 
-def chamfer(a, bvh_a, b, bvh_b, *, out=None, kernel=None, batch=0, seed=False, warm=False):
-    """Two-sided Chamfer pieces: dict nn_ab, d_ab, nn_ba, d_ba and means [2] (float64).
+def chamfer(a, bvh_a, b, bvh_b, *, out=None, add=None, kernel=None, batch=0, seed=False, warm=False):
+    """Two-sided Chamfer: dict nn_ab, d_ab, nn_ba, d_ba and loss [3] (float64: mean d_ab,
+    mean d_ba, their sum plus add), with means = loss[0:2] and total = loss[2:3] as views.
 
-    out: optional dict of preallocated outputs with those keys (means may be any
-    contiguous float64 [2] view).  warm: out's nn_ab / nn_ba hold earlier answers
-    (e.g. the previous step's; -1 for none) that start the queries."""
+    out: optional dict of preallocated outputs with those keys (loss may be any
+    contiguous float64 [3] view).  add: an optional float64 device scalar folded
+    into the total.  warm: out's nn_ab / nn_ba hold earlier answers (e.g. the
+    previous step's; -1 for none) that start the queries."""
     na, nb = _f32(a, 3, "a").shape[1], _f32(b, 3, "b").shape[1]
     dev = a.device
     o = dict(out or {})
     for k, n, dt in (("nn_ab", na, torch.int32), ("d_ab", na, torch.float32), ("nn_ba", nb, torch.int32),
-                     ("d_ba", nb, torch.float32), ("means", 2, torch.float64)):
+                     ("d_ba", nb, torch.float32), ("loss", 3, torch.float64)):
         if o.get(k) is None:
             o[k] = torch.empty(n, dtype=dt, device=dev)
+    if add is not None and (add.dtype != torch.float64 or add.numel() != 1):
+        raise TypeError("add must be a float64 device scalar")
     ws = _rws(dev)
     _call("mg_chamfer", _ptr(a), na, _ptr(bvh_a.buf), bvh_a.nbytes, _ptr(b), nb, _ptr(bvh_b.buf),
           bvh_b.nbytes, _ptr(_i32(o["nn_ab"])), _ptr(_f32(o["d_ab"])), _ptr(_i32(o["nn_ba"])), _ptr(_f32(o["d_ba"])),
-          _ptr(_f64(o["means"], "means")), _ptr(ws), ws.numel(), _opts(kernel, batch, seed, warm=warm), _stream())
+          _ptr(_f64(o["loss"], "loss")), _ptr(add), _ptr(ws), ws.numel(), _opts(kernel, batch, seed, warm=warm),
+          _stream())
+    o["means"], o["total"] = o["loss"][0:2], o["loss"][2:3]
     return o
 
 

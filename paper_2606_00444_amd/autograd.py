@@ -107,7 +107,7 @@ class ChamferLoss(torch.autograd.Function):
             bvh_b = api.lbvh_build(b_, None)
         o = api.chamfer(a_, bvh_a, b_, bvh_b, **(query or {}))
         ctx.save_for_backward(a_, b_, o["nn_ab"], o["nn_ba"])
-        return o["means"].sum()
+        return o["total"].reshape(())
 
     @staticmethod
     def backward(ctx, g):
@@ -122,6 +122,51 @@ class ChamferLoss(torch.autograd.Function):
         return ga, gb, None, None
 
 
+class TemplateProjectionLoss(torch.autograd.Function):
+    """L(V) = P(V) + CD(mu(V), Y) (float64 scalar) in one Function: the point-to-mesh
+    term, the Gaussian means, the Chamfer term and their sum (mg_chamfer's total with P
+    folded in) all come from library calls, and so does the backward.
+
+    apply(verts, faces, gface, bary, q_local, log_scale, offset, targets, bvh,
+    targets_bvh=None, query=None, nn_query=None)."""
+
+    @staticmethod
+    def forward(ctx, verts, faces, gface, bary, q_local, log_scale, offset, targets, bvh, targets_bvh=None,
+                query=None, nn_query=None):
+        if targets.requires_grad:
+            raise ValueError("TemplateProjectionLoss treats targets as constants")
+        v = verts.detach()
+        api.lbvh_refit(bvh, v)
+        rec = api.closest_point_query(bvh, v, targets, **(query or {}))
+        P = api.mean(rec["dist2"])
+        mu = api.mesh_gaussian_update(v, faces, gface, bary, q_local, log_scale, offset, quat=False,
+                                      cov=False)["mean"]
+        bvh_mu = api.lbvh_build(mu, None)
+        bvh_y = targets_bvh if targets_bvh is not None else api.lbvh_build(targets, None)
+        o = api.chamfer(mu, bvh_mu, targets, bvh_y, add=P, **(nn_query or {}))
+        ctx.save_for_backward(v, faces, gface, bary, q_local, log_scale, offset, targets, rec["face"],
+                              rec["point"], rec["bary"], mu, o["nn_ab"], o["nn_ba"])
+        return o["total"].reshape(())
+
+    @staticmethod
+    def backward(ctx, g):
+        if not ctx.needs_input_grad[0]:
+            return (None,) * 12
+        v, faces, gface, bary, q_local, log_scale, offset, targets, face, point, bq, mu, nn_ab, nn_ba = \
+            ctx.saved_tensors
+        gl = g.detach().to(torch.float64).contiguous()
+        gv = _zeros(v)
+        ny, G = targets.shape[1], mu.shape[1]
+        if ny:
+            api.point_mesh_backward(v, faces, targets, {"face": face, "point": point, "bary": bq}, 1.0 / ny, gv,
+                                    g_loss=gl)
+        if G:
+            gmu = api.chamfer_backward(mu, targets, nn_ab, nn_ba, 1.0 / G, 1.0 / ny if ny else 0.0, _zeros(mu),
+                                       g_loss=gl)
+            api.mesh_gaussian_update_backward(v, faces, gface, bary, q_local, log_scale, offset, gmu, g_verts=gv)
+        return (gv,) + (None,) * 11
+
+
 def template_projection_loss(verts, faces, binding, targets, bvh, targets_bvh=None, query=None, nn_query=None):
     """L(V) = P(V) + CD(mu(V), Y) as a differentiable float64 scalar.
 
@@ -129,7 +174,6 @@ def template_projection_loss(verts, faces, binding, targets, bvh, targets_bvh=No
     device tensors; bvh: triangle LBVH over faces (refit in place);
     targets_bvh: optional point LBVH over targets.
     """
-    P = PointToMeshLoss.apply(verts, faces, targets, bvh, query)
-    mu = MeshGaussianBinding.apply(verts, faces, binding["face"], binding["bary"], binding["q_local"],
-                                   binding["log_scale"], binding.get("offset"), False)
-    return P + ChamferLoss.apply(mu, targets, targets_bvh, nn_query)
+    return TemplateProjectionLoss.apply(verts, faces, binding["face"], binding["bary"], binding["q_local"],
+                                        binding["log_scale"], binding.get("offset"), targets, bvh, targets_bvh,
+                                        query, nn_query)

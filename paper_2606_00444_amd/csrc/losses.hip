@@ -161,6 +161,12 @@ __global__ __launch_bounds__(256) void validate_finite_kernel(const float *__res
     if (__ballot(bad) != 0ull && (threadIdx.x % kWave) == 0) atomicExch(status, MG_ERR_NONFINITE_INPUT);
 }
 
+// out[2] = (out[0] + out[1]) + add[0] (add may be null): the two-sided Chamfer
+// sum, plus an optional loss term already on the device.
+__global__ void chamfer_total_kernel(double *__restrict__ out, const double *__restrict__ add) {
+    if (threadIdx.x == 0) out[2] = (out[0] + out[1]) + (add ? add[0] : 0.0);
+}
+
 inline int reduce_blocks(int64_t n, int64_t &chunk) {
     const int64_t per_block = static_cast<int64_t>(kReduceThreads) * kReduceItems;
     int64_t blocks = (n + per_block - 1) / per_block;
@@ -200,8 +206,8 @@ extern "C" mg_status mg_mean(const float *x, int64_t n, double *out, void *ws, s
 
 extern "C" mg_status mg_chamfer(const float *a, int32_t na, const void *bvh_a, size_t bvh_a_bytes, const float *b,
                                 int32_t nb, const void *bvh_b, size_t bvh_b_bytes, int32_t *nn_ab, float *d_ab,
-                                int32_t *nn_ba, float *d_ba, double *out, void *ws, size_t ws_bytes,
-                                const mg_query_options *opts, void *stream) {
+                                int32_t *nn_ba, float *d_ba, double *out, const double *add, void *ws,
+                                size_t ws_bytes, const mg_query_options *opts, void *stream) {
     if (bad_count(na) || bad_count(nb) || !out || !nn_ab || !nn_ba || !d_ab || !d_ba || !bvh_a || !bvh_b)
         return MG_ERR_INVALID_ARGUMENT;
     if ((na > 0 && !a) || (nb > 0 && !b)) return MG_ERR_INVALID_ARGUMENT;
@@ -224,7 +230,10 @@ extern "C" mg_status mg_chamfer(const float *a, int32_t na, const void *bvh_a, s
     hipStream_t s = as_stream(stream);
     st = launch_mean(d_ab, na, out, ws, s);
     if (st != MG_OK) return st;
-    return launch_mean(d_ba, nb, out + 1, ws, s);
+    st = launch_mean(d_ba, nb, out + 1, ws, s);
+    if (st != MG_OK) return st;
+    hipLaunchKernelGGL(chamfer_total_kernel, dim3(1), dim3(64), 0, s, out, add);
+    return launch_status();
 }
 
 extern "C" mg_status mg_point_mesh_backward(const float *verts, int32_t n_verts, const int32_t *faces,

@@ -21,7 +21,7 @@ definitions) and its gradient with the library's kernels, then applies Adam
 
 No step synchronises with the host, so a whole run (reset + K steps) can be
 captured in one HIP graph and replayed.  The loss of step s (at the V that
-step starts from) is kept in history[s] = (P, CD a->b, CD b->a), float64.
+step starts from) is kept in history[s] = (P, CD a->b, CD b->a, L), float64.
 """
 
 import math
@@ -62,7 +62,7 @@ class TemplateRefiner:
         # each step's queries start from the previous step's answers (none at first)
         for t in (self.rec["face"], self.ch["nn_ab"], self.ch["nn_ba"]):
             t.fill_(-1)
-        self.history = torch.zeros(max_steps, 3, dtype=torch.float64, device=dev)
+        self.history = torch.zeros(max_steps, 4, dtype=torch.float64, device=dev)
         self.max_steps = max_steps
         self.bvh = api.lbvh_build(verts0, faces)
         self.bvh_y = api.lbvh_build(targets, None)
@@ -86,19 +86,20 @@ class TemplateRefiner:
         self.t = 0
 
     def loss_and_grad(self, hist_row=None):
-        """Evaluate L at the current V: fills gV (dL/dV) and, if given, a float64 [3] history row."""
+        """Evaluate L at the current V: fills gV (dL/dV) and, if given, a float64 [4] history row
+        (P, CD a->b, CD b->a, L = P + CD, the last summed by mg_chamfer)."""
         b = self.binding
         api.fill(self.gV, 0.0)
         api.fill(self.gmu, 0.0)
         api.lbvh_refit(self.bvh, self.V)
         api.closest_point_query(self.bvh, self.V, self.targets, out=self.rec, hint=self.rec["face"], **self.query)
-        row = hist_row if hist_row is not None else torch.empty(3, dtype=torch.float64, device=self.V.device)
+        row = hist_row if hist_row is not None else torch.empty(4, dtype=torch.float64, device=self.V.device)
         api.mean(self.rec["dist2"], out=row[0:1])
         api.mesh_gaussian_update(self.V, self.faces, b["face"], b["bary"], b["q_local"], b["log_scale"],
                                  b.get("offset"), out={"mean": self.mu}, quat=False, cov=False)
         api.lbvh_refit(self.bvh_mu, self.mu)
-        api.chamfer(self.mu, self.bvh_mu, self.targets, self.bvh_y, out=dict(self.ch, means=row[1:3]), warm=True,
-                    **self.nn_query)
+        api.chamfer(self.mu, self.bvh_mu, self.targets, self.bvh_y, out=dict(self.ch, loss=row[1:4]),
+                    add=row[0:1], warm=True, **self.nn_query)
         if self.ny:
             api.point_mesh_backward(self.V, self.faces, self.targets, self.rec, 1.0 / self.ny, self.gV)
         if self.G:
@@ -132,5 +133,5 @@ class TemplateRefiner:
         return g
 
     def losses(self):
-        """Host copy of the loss history so far: [t][3] (P, CD a->b, CD b->a)."""
+        """Host copy of the loss history so far: [t][4] (P, CD a->b, CD b->a, L)."""
         return self.history[:self.t].cpu()

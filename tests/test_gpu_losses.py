@@ -42,6 +42,13 @@ def test_chamfer_parity(device):
     means = host(out["means"])
     assert means.sum() == pytest.approx(cd, rel=1e-5)
     assert means[0] == pytest.approx(d_ab.mean(), rel=1e-5)
+    # the library's total is the two means summed in float64, plus an added term
+    assert host(out["total"])[0] == means[0] + means[1]
+    import torch
+    extra = torch.tensor([0.25], dtype=torch.float64, device=device)
+    out2 = mg.chamfer(A, ba, B, bb, add=extra)
+    m2 = host(out2["means"])
+    assert host(out2["total"])[0] == (m2[0] + m2[1]) + 0.25
     # every nearest neighbour is the oracle's or ties it, and every distance matches
     L = scale_of(np.concatenate([mu, Y], axis=1))
     for src, dst, nn_dev, d_dev, d_ref in ((mu, Y, out["nn_ab"], out["d_ab"], d_ab),
