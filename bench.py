@@ -988,6 +988,31 @@ def cpu_baseline_c1(sc, frames_np, reps=5):
             "wall_s": round(time.perf_counter() - t_all, 2)}
 
 
+def per_query_distribution(mg, torch, bvh, verts, queries, opts, hint, out, sample):
+    """Node expansions and exact leaf tests per query over a seeded sample of the query
+    set: each sampled query is traversed alone (same options, its own previous-frame hint),
+    with its own counter row, and the percentiles of the counts are reported."""
+    rng = np.random.default_rng(20260603)
+    n = queries.shape[1]
+    idx = np.sort(rng.choice(n, min(sample, n), replace=False))
+    dev = queries.device
+    qs = [queries[:, i:i + 1].contiguous() for i in idx]
+    hs = [hint[i:i + 1].contiguous() for i in idx]
+    one = {"face": torch.empty(1, dtype=torch.int32, device=dev), "point": torch.empty(3, 1, device=dev),
+           "bary": torch.empty(2, 1, device=dev), "dist2": torch.empty(1, device=dev),
+           "normal": torch.empty(3, 1, device=dev) if out.get("normal") is not None else None}
+    cnt = torch.zeros(len(idx), 4, dtype=torch.int64, device=dev)
+    for j in range(len(idx)):
+        mg.closest_point_query(bvh, verts, qs[j], normal=one["normal"] is not None, out=one, counters=cnt[j],
+                               hint=hs[j], **opts)
+    c = cnt.cpu().numpy()
+    pct = lambda x: {f"p{p}": float(np.percentile(x, p)) for p in (10, 50, 90, 99)} | {"max": int(x.max()),
+                                                                                       "mean": float(x.mean())}
+    return {"sample": int(len(idx)), "how": "each sampled query traversed alone with the step's options and its "
+                                            "previous-frame hint (frame in the middle of the sampled ones)",
+            "node_expansions": pct(c[:, 0]), "exact_leaf_tests": pct(c[:, 2])}
+
+
 def copy_calibration(mb, reps):
     """A plain copy of known size (the vertex-buffer copy kernel): reads and writes mb MB per launch.
     Its FETCH_SIZE / WRITE_SIZE counters calibrate the counters of the other kernels."""
@@ -1017,7 +1042,8 @@ def main():
     ap.add_argument("--streams", type=int, choices=(1, 2, 3), default=3,
                     help="c2/c5: run the rebuild comparison path on a second stream (2), also the projection "
                          "onto the rebuilt target on a third (3), or everything serially (1)")
-    ap.add_argument("--phase", choices=["copy", "update", "refit", "collide", "rebuild", "target_queries"],
+    ap.add_argument("--phase", choices=["copy", "update", "refit", "frame_update", "collide", "rebuild",
+                                        "target_queries"],
                     help="profiling aid (c2/c5): run only this phase --reps times, eagerly, and exit")
     ap.add_argument("--reps", type=int, default=60)
     ap.add_argument("--knn", type=int, default=1, help="track: NearestSurface with the k nearest faces (1-8)")
@@ -1203,7 +1229,8 @@ def main():
             phase_collide(hint=hints_c[r % len(frames_c)])
 
         phases = {"copy": lambda r: phase_copy(r % T), "update": lambda r: phase_update(),
-                  "refit": lambda r: phase_refit(), "collide": collide_at,
+                  "refit": lambda r: phase_refit(), "frame_update": lambda r: frame_update(r % T),
+                  "collide": collide_at,
                   "rebuild": lambda r: phase_rebuild(r % n_used), "target_queries": lambda r: phase_target_queries(0)}
         phase_copy(0)
         phase_rebuild(0)
@@ -1341,6 +1368,11 @@ def main():
     n_q //= len(frames_c)
     trav = {"node_expansions_per_query": round(n_exp / n_q, 1), "leaf_bound_tests_per_query": round(n_lbox / n_q, 1),
             "exact_leaf_tests_per_query": round(n_lex / n_q, 1)}
+    trav["per_query_distribution"] = per_query_distribution(
+        mg, torch, bvh, live, particles, dict(o_col, order=None), prev_hints(frames_c[len(frames_c) // 2]),
+        {k: v for k, v in col.items()}, 1000)
+    phase_copy(0)
+    phase_refit()
     coll_ops = OPS_EXPANSION * n_exp + OPS_LEAF_BOUND * n_lbox + OPS_EXACT * n_lex
     single = {k: ph[k] for k in ("gaussian_update", "refit", "frame_update", "collide")}   # one kernel each
     dom = max(single, key=single.get)
