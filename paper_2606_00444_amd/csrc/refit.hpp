@@ -14,12 +14,13 @@
 //
 // The schedule is level-synchronous.  Each thread owns fixed internal nodes;
 // at set-up it gathers the primitives of its nodes' leaf children, writes them
-// into the nodes' records and keeps their summaries in registers.  Then, step
-// by step, every node whose internal children are finished joins its two
-// children's summaries (from registers or LDS slots), writes its record and
-// its own slot and marks itself done; a workgroup barrier ends each step.  A
-// node of height h finishes in step h - 1, so a subtree takes as many steps as
-// it is high, with no atomics and no waiting beyond the barriers.
+// into the nodes' records, finishes a node over two leaves and parks a lone
+// leaf child's summary in its parent's LDS slot.  Then, step by step, each
+// thread joins one of its nodes whose internal children are finished (their
+// summaries from LDS slots), writes its record and its own slot and marks it
+// done; a workgroup barrier ends each step.  With one node per thread a node
+// of height h finishes in step h - 2, so a subtree takes about as many steps
+// as it is high, with no atomics and no waiting beyond the barriers.
 //
 // Phase 1 (a workgroup per subtree): a Karras node covers a contiguous leaf
 // range and its index is one end of that range, so the internal nodes of a
@@ -275,8 +276,18 @@ __device__ __forceinline__ Sum deposit_load(const float4 *src) {
 // fence of its own.  The LDS barrier fences LDS alone: a fence of every
 // address space would also wait for the record stores in flight (on CDNA,
 // vector loads and stores share one counter).
-constexpr int kMaxSteps = 64;     // a valid tree is at most 62 levels high
+//
+// A thread joins at most one of its nodes per step (the first whose children
+// are done), so a wave runs one join per step whatever the number of nodes per
+// thread; a ready node then waits at most (nodes per thread - 1) steps, and a
+// valid tree (at most 62 levels) finishes within 62 x 4 steps.
+constexpr int kMaxSteps = 250;    // marks stay below kNotDone
 constexpr uint8_t kNotDone = 0xff;
+
+// Keeps the given values' loads ahead of this point: the step loops read all
+// their marks in one LDS round trip instead of one per branch.  (No code is
+// emitted.)
+__device__ __forceinline__ void issued_before(int x, int y) { __asm__ volatile("" ::"v"(x), "v"(y)); }
 
 __device__ __forceinline__ void lds_step_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
@@ -382,7 +393,7 @@ __device__ void refit_subtree(const RefitArgs &a, int64_t k, unsigned char *smem
     // in its parent's own slot, which nothing else reads before the parent is
     // done.  The steps end when the root's mark is set.
     const int jr = static_cast<int>(r - f);
-    int32_t nid[kPer], cref[kPer][2];
+    int32_t nid[kPer], cref[kPer][2] = {};
     bool pend[kPer];
     int32_t rtag = -1;
 #pragma unroll
@@ -436,29 +447,50 @@ __device__ void refit_subtree(const RefitArgs &a, int64_t k, unsigned char *smem
             pend[u] = true;
         }
     }
+    // the slots each pending node reads: an internal child's, or its own for a
+    // leaf child (whose summary waits there)
+    int sj0[kPer], sj1[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int j = pend[u] ? static_cast<int>(nid[u] - f) : jr;
+        sj0[u] = pend[u] && cref[u][0] >= 0 ? static_cast<int>(cref[u][0] - f) : j;
+        sj1[u] = pend[u] && cref[u][1] >= 0 ? static_cast<int>(cref[u][1] - f) : j;
+    }
     __syncthreads();
     // the exit test reads the root's mark only once it can no longer change in
     // the step being tested (a mark written in step s is s + 1): every thread
     // leaves after the same barrier
-    for (int step = 0; step < kMaxSteps && s_done[jr] > step; ++step) {
+    for (int step = 0; step < kMaxSteps; ++step) {
+        const int rm = s_done[jr];
+        int d0[kPer], d1[kPer];
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
-            if (!pend[u]) continue;
-            const int32_t c0 = cref[u][0], c1 = cref[u][1];
-            const int j = static_cast<int>(nid[u] - f);
-            const bool in0 = c0 >= 0, in1 = c1 >= 0;
-            const int j0 = in0 ? static_cast<int>(c0 - f) : j, j1 = in1 ? static_cast<int>(c1 - f) : j;
-            const int d0 = in0 ? s_done[j0] : 0, d1 = in1 ? s_done[j1] : 0;
-            if (d0 > step || d1 > step) continue;
-            pend[u] = false;
-            // a leaf child's summary waits in the node's own slot (j)
+            d0[u] = s_done[sj0[u]];
+            d1[u] = s_done[sj1[u]];
+            issued_before(d0[u], d1[u]);
+        }
+        if (rm <= step) break;
+        int su = -1;      // a leaf child is always done
+#pragma unroll
+        for (int u = kPer - 1; u >= 0; --u)
+            if (pend[u] && (cref[u][0] < 0 || d0[u] <= step) && (cref[u][1] < 0 || d1[u] <= step)) su = u;
+        if (su >= 0) {
+            int32_t id = nid[0], c0 = cref[0][0], c1 = cref[0][1];
+            int j0 = sj0[0], j1 = sj1[0];
+#pragma unroll
+            for (int u = 1; u < kPer; ++u)
+                if (su == u) { id = nid[u]; c0 = cref[u][0]; c1 = cref[u][1]; j0 = sj0[u]; j1 = sj1[u]; }
+#pragma unroll
+            for (int u = 0; u < kPer; ++u)
+                if (su == u) pend[u] = false;
+            const int j = static_cast<int>(id - f);
             const Sum A = lds_slot_load(s_slot + 3 * j0);
             const Sum B = lds_slot_load(s_slot + 3 * j1);
-            float4 *rec = a.nodes + 6 * static_cast<int64_t>(nid[u]);
-            if (in0) write_internal<kTri>(rec, c0, A);
-            if (in1) write_internal<kTri>(rec + 3, c1, B);
+            float4 *rec = a.nodes + 6 * static_cast<int64_t>(id);
+            if (c0 >= 0) write_internal<kTri>(rec, c0, A);
+            if (c1 >= 0) write_internal<kTri>(rec + 3, c1, B);
             const Sum P = join<kTri>(A, B);
-            if (nid[u] == r) finish_subtree<kTri>(a, k, r, rtag, P);
+            if (id == r) finish_subtree<kTri>(a, k, r, rtag, P);
             else lds_slot_store(s_slot + 3 * j, P);
             s_done[j] = static_cast<uint8_t>(step + 1);
         }
@@ -479,7 +511,7 @@ __device__ void refit_top_lds_steps(const RefitArgs &a, int T, int NS, unsigned 
     float4 *t_slot = reinterpret_cast<float4 *>(smem);                          // [T][3]
     uint8_t *t_done = reinterpret_cast<uint8_t *>(t_slot + 3 * T);             // [T]
     int *t_fin = reinterpret_cast<int *>(t_done + ((T + 3) & ~3));           // the root's mark (its owner's)
-    int32_t pn[kTPer], ch[kTPer][2], cn[kTPer][2];
+    int32_t pn[kTPer], ch[kTPer][2] = {}, cn[kTPer][2] = {};
     bool pend[kTPer];
     // the tables are read for every slot up to the cap at once (one round trip,
     // T arriving with them); slots from T on are ignored
@@ -536,25 +568,49 @@ __device__ void refit_top_lds_steps(const RefitArgs &a, int T, int NS, unsigned 
             pend[u] = true;
         }
     }
+    // the slots each pending node reads: a top child's, or its own for a lone
+    // subtree child (whose summary waits there)
+    int sj0[kTPer], sj1[kTPer];
+#pragma unroll
+    for (int u = 0; u < kTPer; ++u) {
+        const int t = pend[u] ? static_cast<int>(threadIdx.x) + u * kThreads : 0;
+        sj0[u] = pend[u] && ch[u][0] >= 0 ? ch[u][0] : t;
+        sj1[u] = pend[u] && ch[u][1] >= 0 ? ch[u][1] : t;
+    }
     __syncthreads();
-    for (int step = 0; step < kMaxSteps && *t_fin > step; ++step) {   // as in the subtree phase
+    for (int step = 0; step < kMaxSteps; ++step) {   // as in the subtree phase
+        const int rm = *t_fin;
+        int d0[kTPer], d1[kTPer];
 #pragma unroll
         for (int u = 0; u < kTPer; ++u) {
-            if (!pend[u]) continue;
-            const int t = threadIdx.x + u * kThreads;
-            const int32_t c0 = ch[u][0], c1 = ch[u][1];
-            const bool in0 = c0 >= 0, in1 = c1 >= 0;
-            const int d0 = in0 ? t_done[c0] : 0, d1 = in1 ? t_done[c1] : 0;
-            if (d0 > step || d1 > step) continue;
-            pend[u] = false;
-            // a lone subtree child's summary waits in the node's own slot (t)
-            const Sum A = lds_slot_load(t_slot + 3 * (in0 ? c0 : t));
-            const Sum B = lds_slot_load(t_slot + 3 * (in1 ? c1 : t));
-            float4 *rec = a.nodes + 6 * static_cast<int64_t>(pn[u]);
-            if (in0) write_internal<kTri>(rec, cn[u][0], A);
-            if (in1) write_internal<kTri>(rec + 3, cn[u][1], B);
+            d0[u] = t_done[sj0[u]];
+            d1[u] = t_done[sj1[u]];
+            issued_before(d0[u], d1[u]);
+        }
+        if (rm <= step) break;
+        int su = -1;      // a subtree child is always done
+#pragma unroll
+        for (int u = kTPer - 1; u >= 0; --u)
+            if (pend[u] && (ch[u][0] < 0 || d0[u] <= step) && (ch[u][1] < 0 || d1[u] <= step)) su = u;
+        if (su >= 0) {
+            int32_t p = pn[0], c0 = ch[0][0], c1 = ch[0][1], n0 = cn[0][0], n1 = cn[0][1];
+            int j0 = sj0[0], j1 = sj1[0], t = threadIdx.x;
+#pragma unroll
+            for (int u = 1; u < kTPer; ++u)
+                if (su == u) {
+                    p = pn[u]; c0 = ch[u][0]; c1 = ch[u][1]; n0 = cn[u][0]; n1 = cn[u][1];
+                    j0 = sj0[u]; j1 = sj1[u]; t = threadIdx.x + u * kThreads;
+                }
+#pragma unroll
+            for (int u = 0; u < kTPer; ++u)
+                if (su == u) pend[u] = false;
+            const Sum A = lds_slot_load(t_slot + 3 * j0);
+            const Sum B = lds_slot_load(t_slot + 3 * j1);
+            float4 *rec = a.nodes + 6 * static_cast<int64_t>(p);
+            if (c0 >= 0) write_internal<kTri>(rec, n0, A);
+            if (c1 >= 0) write_internal<kTri>(rec + 3, n1, B);
             const Sum P = join<kTri>(A, B);
-            if (pn[u] == 0) {             // the root
+            if (p == 0) {                 // the root
                 write_root(a.root, P);
                 *t_fin = step + 1;
             } else {
@@ -618,14 +674,20 @@ __device__ void refit_top_global_steps(const RefitArgs &a, int T, int NS, unsign
 }
 
 // Phase 2: in LDS when T fits kTPer nodes per thread (kGlobal false), else in
-// global scratch.
+// global scratch.  The LDS form is run with the fewest nodes per thread that
+// hold T (1, 2 or kTPer): every owned node costs its mark loads in every step.
 template <bool kTri, int kThreads, bool kGlobal, int kTPer>
 __device__ void refit_top(const RefitArgs &a, int T, int NS, unsigned char *smem) {
+    constexpr int kTwo = kTPer < 2 ? kTPer : 2;
     if (kGlobal) {
         refit_top_global_steps<kTri, kThreads>(a, T, NS, smem);
     } else if (T > kTPer * kThreads) {
         if (threadIdx.x == 0) atomicOr(a.status, 8);
         __syncthreads();
+    } else if (T <= kThreads) {
+        refit_top_lds_steps<kTri, kThreads, 1>(a, T, NS, smem);
+    } else if (T <= kTwo * kThreads) {
+        refit_top_lds_steps<kTri, kThreads, kTwo>(a, T, NS, smem);
     } else {
         refit_top_lds_steps<kTri, kThreads, kTPer>(a, T, NS, smem);
     }
