@@ -653,15 +653,17 @@ mg_status launch_refit_t(const RefitArgs &a, int grid, hipStream_t s) {
     return launch_status();
 }
 
-// A thread per internal node of a subtree of up to 256 or 512 leaves, and 2
-// or 4 nodes per thread in 512-thread workgroups for 1024- and 2048-leaf
-// subtrees.  Up to 1024 leaves three workgroups fit a CU beside each other
-// (about 50 KB of LDS each, six waves per SIMD for 512 threads), so a tree
-// of 500,000 faces has nearly all its subtrees resident at once.
+// 512-thread workgroups: a thread per internal node of a subtree of up to 256
+// or 512 leaves, and 2 or 4 nodes per thread for 1024- and 2048-leaf subtrees.
+// Up to 1024 leaves three workgroups fit a CU beside each other (about 50 KB
+// of LDS each, six waves per SIMD), so a tree of 500,000 faces has nearly all
+// its subtrees resident at once.  256-leaf subtrees leave half the threads
+// idle in phase 1, but phase 2 then holds up to 512 top nodes at one node per
+// thread (a 40,000-face tree has 276: 24.5 us against 26.4 us with 256-thread
+// workgroups, whose phase 2 needs two nodes per thread there).
 template <bool kTri>
 mg_status launch_refit_k(const RefitArgs &a, int grid, hipStream_t s) {
-    if (a.chunk_log2 <= 8) return launch_refit_t<kTri, 256, 1, 3>(a, grid, s);
-    if (a.chunk_log2 == 9) return launch_refit_t<kTri, 512, 1, 6>(a, grid, s);
+    if (a.chunk_log2 <= 9) return launch_refit_t<kTri, 512, 1, 6>(a, grid, s);
     if (a.chunk_log2 == 10) return launch_refit_t<kTri, 512, 2, 6>(a, grid, s);
     return launch_refit_t<kTri, 512, 4, 2>(a, grid, s);
 }
@@ -886,7 +888,7 @@ extern "C" mg_status mg_frame_update(const float *frames, int32_t n_frames, int3
     w.in = Inputs{src, n_verts, faces, n_faces, gface, bary, q_local, log_scale, offset, n_gauss};
     w.mean = mean; w.quat = quat; w.cov = cov; w.rot = rot;
     w.sub_blocks = 2 * ((n_faces + C - 1) / C);
-    const int threads = a.chunk_log2 <= 8 ? 256 : 512;
+    const int threads = 512;                 // as the plain refit (launch_refit_k)
     w.copy_tile = 16 * static_cast<int64_t>(threads);
     w.copy_blocks = (n3 + w.copy_tile - 1) / w.copy_tile;
     w.gauss_tile = 2 * static_cast<int64_t>(threads);
@@ -894,8 +896,7 @@ extern "C" mg_status mg_frame_update(const float *frames, int32_t n_frames, int3
     const int64_t grid = w.sub_blocks + w.copy_blocks + gauss_blocks;
     if (grid > 0x7fffffff) return MG_ERR_INVALID_ARGUMENT;
     hipStream_t s = as_stream(stream);
-    if (a.chunk_log2 <= 8) return launch_frame_t<256, 1, 3>(a, w, grid, s);
-    if (a.chunk_log2 == 9) return launch_frame_t<512, 1, 6>(a, w, grid, s);
+    if (a.chunk_log2 <= 9) return launch_frame_t<512, 1, 6>(a, w, grid, s);
     if (a.chunk_log2 == 10) return launch_frame_t<512, 2, 6>(a, w, grid, s);
     return launch_frame_t<512, 4, 2>(a, w, grid, s);
 }

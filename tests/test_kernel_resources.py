@@ -28,9 +28,9 @@ EXPECT = {
         r"traverse_batch_kernelILb0ELi(16|32)ELi4EE": (6, 0),
     },
     "lbvh.hip": {
-        # three workgroups per CU: 6 waves per SIMD at 512 threads, 3 at 256
+        # three 512-thread workgroups per CU: 6 waves per SIMD
         r"refit_kernelILb1ELi512ELi[12]ELi6EE": (6, 0),
-        r"refit_kernelILb1ELi256ELi1ELi3EE": (3, 0),
+        r"frame_update_kernelILi512ELi[12]ELi6EE": (6, 0),
         r"radix_pass_kernelILi2EE": (8, 0),
         r"hierarchy_kernel": (8, 0),
         r"morton_kernel": (8, 0),
