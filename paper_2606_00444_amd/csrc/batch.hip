@@ -196,6 +196,7 @@ __device__ RefitArgs refit_args(const PlanScene &P, int64_t t, PlanHeader *h) {
     a.n_sub = P.n_sub;
     a.n = s.n_faces;
     a.chunk_log2 = P.chunk_log2;
+    a.inf = INFINITY;
     return a;
 }
 

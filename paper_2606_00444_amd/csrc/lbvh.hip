@@ -698,6 +698,7 @@ RefitArgs refit_args(const float *verts, int64_t nv, void *bvh, int64_t n, int k
     a.arrivals = &hdr->refit_arrivals;
     a.n = n;
     a.chunk_log2 = chunk_log2_for(n);
+    a.inf = INFINITY;
     return a;
 }
 

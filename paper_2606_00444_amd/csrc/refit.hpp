@@ -67,6 +67,7 @@ struct RefitArgs {
     uint32_t *arrivals;           // subtrees finished in this launch (plain refit)
     int64_t n;
     int chunk_log2;
+    float inf;                    // +infinity, set at run time (see box_min)
 };
 
 // The summary a finished node hands to its parent.
@@ -172,13 +173,28 @@ __device__ __forceinline__ void child_range(f3 d, const Sum &c, float ba, float 
     cb = has ? hi_c : bb;
 }
 
+// Box union by the three-input median with an infinite third operand: one
+// instruction per coordinate, where the two-input min and max first quiet a
+// possible signalling NaN of each operand loaded from LDS (two more).  inf is
+// passed in at run time: with a literal infinity the compiler turns the median
+// back into min and max.  Box coordinates are finite and never -0 (leaf boxes
+// add +0), where both forms give the same result.
+__device__ __forceinline__ f3 box_min(f3 a, f3 b, float inf) {
+    return f3{__builtin_amdgcn_fmed3f(a.x, b.x, -inf), __builtin_amdgcn_fmed3f(a.y, b.y, -inf),
+              __builtin_amdgcn_fmed3f(a.z, b.z, -inf)};
+}
+__device__ __forceinline__ f3 box_max(f3 a, f3 b, float inf) {
+    return f3{__builtin_amdgcn_fmed3f(a.x, b.x, inf), __builtin_amdgcn_fmed3f(a.y, b.y, inf),
+              __builtin_amdgcn_fmed3f(a.z, b.z, inf)};
+}
+
 // The summary of a node from its children's, in slot order.
 template <bool kTri>
-__device__ __forceinline__ Sum join(const Sum &L, const Sum &R) {
+__device__ __forceinline__ Sum join(const Sum &L, const Sum &R, float inf) {
 #pragma clang fp contract(off)
     Sum P;
-    P.lo = fmin3(L.lo, R.lo);
-    P.hi = fmax3(L.hi, R.hi);
+    P.lo = box_min(L.lo, R.lo, inf);
+    P.hi = box_max(L.hi, R.hi, inf);
     P.d = f3{0.0f, 0.0f, 0.0f};
     P.sn = 0.0f;
     P.a = -INFINITY;
@@ -437,7 +453,7 @@ __device__ void refit_subtree(const RefitArgs &a, int64_t k, unsigned char *smem
             L[s] = leaf_sum<kTri>(x, y, z);
         }
         if (leaf[0] && leaf[1]) {
-            const Sum P = join<kTri>(L[0], L[1]);
+            const Sum P = join<kTri>(L[0], L[1], a.inf);
             if (nid[u] == r) finish_subtree<kTri>(a, k, r, rtag, P);   // a subtree of two leaves
             else lds_slot_store(s_slot + 3 * j, P);
             s_done[j] = 0;
@@ -489,7 +505,7 @@ __device__ void refit_subtree(const RefitArgs &a, int64_t k, unsigned char *smem
             float4 *rec = a.nodes + 6 * static_cast<int64_t>(id);
             if (c0 >= 0) write_internal<kTri>(rec, c0, A);
             if (c1 >= 0) write_internal<kTri>(rec + 3, c1, B);
-            const Sum P = join<kTri>(A, B);
+            const Sum P = join<kTri>(A, B, a.inf);
             if (id == r) finish_subtree<kTri>(a, k, r, rtag, P);
             else lds_slot_store(s_slot + 3 * j, P);
             s_done[j] = static_cast<uint8_t>(step + 1);
@@ -554,7 +570,7 @@ __device__ void refit_top_lds_steps(const RefitArgs &a, int T, int NS, unsigned 
             continue;
         }
         if (c0 < 0 && c1 < 0) {
-            const Sum P = join<kTri>(sum_of_words(dw[u][0]), sum_of_words(dw[u][1]));
+            const Sum P = join<kTri>(sum_of_words(dw[u][0]), sum_of_words(dw[u][1]), a.inf);
             if (pn[u] == 0) {             // the root over two subtrees
                 write_root(a.root, P);
                 *t_fin = 0;
@@ -609,7 +625,7 @@ __device__ void refit_top_lds_steps(const RefitArgs &a, int T, int NS, unsigned 
             float4 *rec = a.nodes + 6 * static_cast<int64_t>(p);
             if (c0 >= 0) write_internal<kTri>(rec, n0, A);
             if (c1 >= 0) write_internal<kTri>(rec + 3, n1, B);
-            const Sum P = join<kTri>(A, B);
+            const Sum P = join<kTri>(A, B, a.inf);
             if (p == 0) {                 // the root
                 write_root(a.root, P);
                 *t_fin = step + 1;
@@ -656,7 +672,7 @@ __device__ void refit_top_global_steps(const RefitArgs &a, int T, int NS, unsign
             float4 *rec = a.nodes + 6 * static_cast<int64_t>(p);
             if (c0 >= 0) write_internal<kTri>(rec, a.top_nodes[c0], A);
             if (c1 >= 0) write_internal<kTri>(rec + 3, a.top_nodes[c1], B);
-            const Sum P = join<kTri>(A, B);
+            const Sum P = join<kTri>(A, B, a.inf);
             if (p == 0) {
                 write_root(a.root, P);
                 *t_fin = step + 1;
