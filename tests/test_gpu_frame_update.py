@@ -79,3 +79,38 @@ def test_frame_update_without_gaussians(device):
     torch.cuda.synchronize()
     np.testing.assert_array_equal(host(live), host(frames[1]))
     np.testing.assert_array_equal(_refit_bytes(bvh_b)[0], _refit_bytes(bvh_a)[0])
+
+
+def test_frame_update_2048_leaf_subtrees(device):
+    """A mesh of more than 524,288 faces (the 1M-face split target of the large
+    configuration as a fixed template): 2048-leaf subtrees, four nodes per thread.
+    Fused against separate calls, bitwise, on a displaced copy of the vertices."""
+    import paper_2606_00444_amd as mg
+    from synth.gaussians import draw_binding
+    sc = make_config(5)
+    v, f = sc.target(3)
+    assert f.shape[1] > 524288
+    rng = np.random.default_rng(11)
+    b_np = draw_binding(rng, v.T.astype(np.float64), f.T, n_gauss=200_000)
+    L = scale_of(v)
+    frames_np = np.stack([v, v + (rng.normal(size=v.shape) * 1e-3 * L).astype(np.float32)])
+    frames = dev(frames_np, device)
+    F = dev(f, device)
+    b = {k: dev(b_np[k], device) for k in ("face", "bary", "q_local", "log_scale")}
+    bvh_a, bvh_b = mg.lbvh_build(frames[0].contiguous(), F), mg.lbvh_build(frames[0].contiguous(), F)
+    live_a = torch.empty(3, v.shape[1], device=device)
+    live_b = torch.empty(3, v.shape[1], device=device)
+    print("frame update: 1M-face mesh, frame 1", flush=True)
+    mg.vertex_buffer_update(frames, 1, live_a)
+    ga = mg.mesh_gaussian_update(live_a, F, b["face"], b["bary"], b["q_local"], b["log_scale"])
+    mg.lbvh_refit(bvh_a, live_a)
+    gb = mg.frame_update(frames, 1, live_b, F, b["face"], b["bary"], b["q_local"], b["log_scale"], bvh_b)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host(live_b).view(np.uint32), host(live_a).view(np.uint32))
+    for key in ("mean", "quat", "cov"):
+        np.testing.assert_array_equal(host(gb[key]).view(np.uint32), host(ga[key]).view(np.uint32))
+    na, ha = _refit_bytes(bvh_a)
+    nb, hb = _refit_bytes(bvh_b)
+    np.testing.assert_array_equal(nb, na)
+    np.testing.assert_array_equal(hb, ha)
+    assert int(host(bvh_b.buf[:16].view(torch.int32))[2]) == 0
